@@ -1,0 +1,230 @@
+"""CPU oracle for the preconditioned Jacobi eigensolver with gap-aware pivoting.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product.  It shares no code with the HIP
+path; the only thing both sides consume is the seeded input module.
+
+Pipeline (Shao & Nakatsukasa, Sec. 2.1 and Algorithm 1):
+
+1. read the upper triangle of A and mirror it (Algorithm 1 input: a symmetric matrix);
+2. ``precond='fp32'``: cyclic FP32 Jacobi -> V_l (Sec. 2.1, low-precision spectral
+   decomposition), re-orthogonalised in FP64 by Householder QR with diag(R) > 0 (the
+   experiments of Sec. 4 use Householder QR), then A_hat = Q^T (A Q), symmetrised;
+3. FP64 Jacobi on A_hat with greedy or gap-aware pivots (eq. (1)) until the chosen stop
+   rule holds (Theorem 1 certificate by default);
+4. V = Q V_J, optionally polished by one Newton-Schulz step; eigenvalues =
+   diag(A_final), sorted ascending with V's columns permuted.
+
+The Jacobi loop itself is C (``jacobi_oracle.cpp``), compiled without FMA contraction.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "jacobi_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GREEDY, GAP = 0, 1
+STOP_CERT, STOP_OFF, STOP_SCORE = 0, 1, 2
+OK, MAXROT, STALL, NONFINITE = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C++ into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("rotations", ctypes.c_longlong), ("rescans", ctypes.c_longlong),
+                ("final_sel", ctypes.c_double), ("final_cert", ctypes.c_double),
+                ("final_off", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        dp, ip, fp = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                      ctypes.POINTER(ctypes.c_float))
+        L.orc_score_gap.restype = ctypes.c_double
+        L.orc_score_gap.argtypes = [ctypes.c_double] * 3
+        L.orc_rotation.restype = None
+        L.orc_rotation.argtypes = [ctypes.c_double] * 3 + [dp] * 3
+        L.orc_jacobi.restype = ctypes.c_int
+        L.orc_jacobi.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_longlong, ctypes.c_int, dp, ip, dp, ctypes.c_longlong,
+                                 ctypes.POINTER(_Stats)]
+        L.orc_jacobi_f32.restype = ctypes.c_int
+        L.orc_jacobi_f32.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+# ----------------------------------------------------------------- primitives
+def score_gap(aii: float, ajj: float, aij: float) -> float:
+    """eq. (1) for one pair (0 when a_ij == 0)."""
+    return lib().orc_score_gap(aii, ajj, aij)
+
+
+def rotation(app: float, aqq: float, apq: float):
+    """(t, c, s) of the Jacobi rotation that diagonalises [[app, apq], [apq, aqq]]."""
+    t, c, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_rotation(app, aqq, apq, ctypes.byref(t), ctypes.byref(c), ctypes.byref(s))
+    return t.value, c.value, s.value
+
+
+@dataclass
+class JacobiResult:
+    a: np.ndarray              # final matrix
+    vj: np.ndarray | None      # product of the rotations
+    pivots: np.ndarray         # (rotations, 2) int32
+    cs: np.ndarray             # (rotations, 2) float64
+    rotations: int
+    rescans: int
+    final_sel: float
+    final_cert: float
+    final_off: float
+    status: int
+
+
+def jacobi(a: np.ndarray, pivot: int = GAP, stop: int = STOP_CERT, thr: float = 0.0,
+           maxrot: int | None = None, scan: int = 1, want_vj: bool = True,
+           logcap: int | None = None) -> JacobiResult:
+    """FP64 Jacobi (Algorithm 1) on a full symmetric matrix, absolute threshold ``thr``."""
+    a = np.array(a, dtype=np.float64, order="C", copy=True)
+    n = a.shape[0]
+    if maxrot is None:
+        maxrot = max(64, 40 * n * n)
+    if logcap is None:
+        logcap = min(maxrot, 40 * n * n + 64)
+    vj = np.empty((n, n)) if want_vj else None
+    plog = np.empty((logcap, 2), dtype=np.int32)
+    cslog = np.empty((logcap, 2), dtype=np.float64)
+    st = _Stats()
+    lib().orc_jacobi(_dp(a), n, pivot, stop, float(thr), int(maxrot), scan, _dp(vj),
+                     plog.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(cslog),
+                     int(logcap), ctypes.byref(st))
+    r = int(st.rotations)
+    k = min(r, logcap)
+    return JacobiResult(a, vj, plog[:k].copy(), cslog[:k].copy(), r, int(st.rescans),
+                        st.final_sel, st.final_cert, st.final_off, int(st.status))
+
+
+def jacobi_f32(a: np.ndarray, max_sweeps: int = 20, tol: float = 2.0 ** -22):
+    """Cyclic FP32 Jacobi: returns (A32_final, V32, sweeps)."""
+    a32 = np.array(a, dtype=np.float32, order="C", copy=True)
+    n = a32.shape[0]
+    v32 = np.empty((n, n), dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    sweeps = lib().orc_jacobi_f32(a32.ctypes.data_as(fp), n, v32.ctypes.data_as(fp),
+                                  max_sweeps, tol)
+    return a32, v32, sweeps
+
+
+def householder_q(x: np.ndarray) -> np.ndarray:
+    """Orthogonal factor of a Householder QR (LAPACK geqrf/orgqr) with diag(R) > 0."""
+    q, r = np.linalg.qr(np.asarray(x, dtype=np.float64))
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return q * d[None, :]
+
+
+@dataclass
+class EighResult:
+    w: np.ndarray
+    v: np.ndarray | None
+    rotations: int
+    pivots: np.ndarray
+    status: int
+    normF: float
+    thr: float
+    a_hat: np.ndarray
+    q: np.ndarray | None
+    sweeps32: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def polish(v: np.ndarray) -> np.ndarray:
+    """One Newton-Schulz step toward the nearest orthogonal matrix, written as a small
+    correction: R = I - V^T V, V <- V + V R / 2 (Sec. 2.1 names Newton-Schulz as one way
+    to orthogonalise in working precision)."""
+    r = np.eye(v.shape[1]) - v.T @ v
+    return v + 0.5 * (v @ r)
+
+
+def symmetric_from_upper(a: np.ndarray) -> np.ndarray:
+    """Algorithm 1 input: take the upper triangle (i <= j) and mirror it."""
+    a = np.asarray(a, dtype=np.float64)
+    u = np.triu(a)
+    return u + np.triu(a, 1).T
+
+
+def threshold(stop: int, tol: float, n: int, normF: float) -> float:
+    """Absolute threshold from a relative tolerance.  Certificate: Theorem 1 asks for
+    max L_ij <= tau / (2 n (n-1)) to guarantee |lambda_k - a_kk| <= tau, tau = tol ||A||_F."""
+    if stop == STOP_CERT:
+        return tol * normF / (2.0 * n * (n - 1)) if n > 1 else 0.0
+    return tol * normF
+
+
+def eigh(a: np.ndarray, tol: float, pivot: int = GAP, precond: str = "fp32",
+         stop: int = STOP_CERT, abs_thr: float | None = None, want_v: bool = True,
+         maxrot: int | None = None, scan: int = 1, sweeps32: int = 20,
+         polish_v: bool = True) -> EighResult:
+    """Whole preconditioned solve: returns ascending eigenvalues and eigenvectors."""
+    a = symmetric_from_upper(a)
+    n = a.shape[0]
+    if not np.all(np.isfinite(a)):
+        return EighResult(np.full(n, np.nan), None, 0, np.empty((0, 2), np.int32), NONFINITE,
+                          float("nan"), float("nan"), a, None)
+    normF = float(np.sqrt(np.sum(a * a)))
+    thr = abs_thr if abs_thr is not None else threshold(stop, tol, n, normF)
+    q = None
+    sw = 0
+    if precond == "fp32" and n > 1:
+        _, v32, sw = jacobi_f32(a, max_sweeps=sweeps32)
+        q = householder_q(v32.astype(np.float64))
+        a_hat = q.T @ (a @ q)
+        a_hat = 0.5 * (a_hat + a_hat.T)
+    else:
+        a_hat = a.copy()
+    res = jacobi(a_hat, pivot=pivot, stop=stop, thr=thr, maxrot=maxrot, scan=scan,
+                 want_vj=want_v)
+    d = np.diag(res.a).copy()
+    order = np.argsort(d, kind="stable")
+    w = d[order]
+    v = None
+    if want_v:
+        v = res.vj if q is None else q @ res.vj
+        if polish_v:
+            v = polish(v)
+        v = np.ascontiguousarray(v[:, order])
+    return EighResult(w, v, res.rotations, res.pivots, res.status, normF, thr, a_hat, q, sw,
+                      {"final_cert": res.final_cert, "final_off": res.final_off,
+                       "rescans": res.rescans})
+
+
+def total_relative_error(lam_exact: np.ndarray, lam: np.ndarray) -> float:
+    """Sec. 4 error measure: sum_i |lambda_i - lambda_hat_i| / ||A||_2 (both sorted)."""
+    lam_exact = np.sort(lam_exact)
+    return float(np.sum(np.abs(lam_exact - np.sort(lam))) / np.max(np.abs(lam_exact)))

@@ -1,0 +1,392 @@
+// Oracle for the preconditioned Jacobi eigensolver with gap-aware pivoting
+// (N. Shao, Y. Nakatsukasa, "Accelerating preconditioned Jacobi methods via
+// perturbation-inspired pivoting").
+//
+// TEST INFRASTRUCTURE ONLY.  This is a plain, slow, CPU implementation written for
+// readability, used by the test-suite and by the benchmark's CPU baseline to check the
+// HIP implementation.  It shares no code, header, table or helper with the HIP path,
+// and the product never calls it.
+//
+// Everything is row-major, full symmetric storage, FP64 (FP32 for the low-precision
+// preconditioner), built with -O2 -ffp-contract=off and no fast-math so that each
+// operation below is one correctly rounded IEEE operation in the order written.
+//
+// Readings of points the paper leaves open (every one is also listed in the design notes):
+//   * score when a_ij^2 == 0 in FP64: defined as 0 (eq. (1) is 0/0 when also a_ii == a_jj);
+//   * rotation: the small-angle root of t^2 + 2 theta t - 1 = 0 with
+//     theta = (a_pp - a_qq) / (2 a_pq), sgn(0) = +1, and t = 1/(2 theta) once
+//     |theta| > 2^500 (theta^2 would overflow);
+//   * argmax ties: the lexicographically smallest (i, j), i < j;
+//   * stop rules: certificate max_{i!=j} L_ij <= thr (Theorem 1), off(A) <= thr, or
+//     the selection score of the best pivot <= thr.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+// eq. (1): L_ij = 2|a_ij|^2 / (|a_ii - a_jj| + sqrt(|a_ii - a_jj|^2 + 4|a_ij|^2)).
+// Defined as 0 when a_ij^2 is 0 in FP64 (a_ij == 0, or |a_ij| < 2^-537 so that the
+// square underflows): eq. (1) would be 0/0 when also a_ii == a_jj.
+double gap_score(double aii, double ajj, double aij) {
+  double a2 = aij * aij;
+  if (a2 == 0.0) return 0.0;
+  double d = std::fabs(aii - ajj);
+  return (2.0 * a2) / (d + std::sqrt(d * d + 4.0 * a2));
+}
+
+// Classical greedy score: the magnitude of the off-diagonal entry.
+double greedy_score(double aij) { return std::fabs(aij); }
+
+// c, s such that G^T [[app, apq], [apq, aqq]] G is diagonal, G = [[c, -s], [s, c]] (Sec. 2).
+template <typename T>
+void rotation(T app, T aqq, T apq, T* t, T* c, T* s) {
+  T theta = (app - aqq) / (T(2) * apq);
+  T tt;
+  if (std::fabs(theta) > T(0x1p500)) {
+    tt = T(1) / (T(2) * theta);
+  } else {
+    tt = T(1) / (std::fabs(theta) + std::sqrt(T(1) + theta * theta));
+    if (theta < T(0)) tt = -tt;
+  }
+  T cc = T(1) / std::sqrt(T(1) + tt * tt);
+  *t = tt;
+  *c = cc;
+  *s = tt * cc;
+}
+
+// float version of the 2^500 guard cannot be represented; for float the guard value is
+// 2^60 (theta^2 overflows float beyond 2^64).
+template <>
+void rotation<float>(float app, float aqq, float apq, float* t, float* c, float* s) {
+  float theta = (app - aqq) / (2.0f * apq);
+  float tt;
+  if (std::fabs(theta) > 0x1p60f) {
+    tt = 1.0f / (2.0f * theta);
+  } else {
+    tt = 1.0f / (std::fabs(theta) + std::sqrt(1.0f + theta * theta));
+    if (theta < 0.0f) tt = -tt;
+  }
+  float cc = 1.0f / std::sqrt(1.0f + tt * tt);
+  *t = tt;
+  *c = cc;
+  *s = tt * cc;
+}
+
+struct Matrix {
+  double* a;
+  int n;
+  double at(int i, int j) const { return a[(size_t)i * n + j]; }
+};
+
+// Score of pair (i, j) under a strategy: 0 = greedy |a_ij|, 1 = gap L_ij.
+double pair_score(const Matrix& m, int i, int j, int strategy) {
+  if (strategy == 1) return gap_score(m.at(i, i), m.at(j, j), m.at(i, j));
+  return greedy_score(m.at(i, j));
+}
+
+// Best (score, column) of row k over l != k; ties go to the smallest column.
+void row_best(const Matrix& m, int k, int strategy, double* best, int* arg) {
+  double b = -1.0;
+  int a = -1;
+  for (int l = 0; l < m.n; ++l) {
+    if (l == k) continue;
+    double v = pair_score(m, k, l, strategy);
+    if (v > b) {
+      b = v;
+      a = l;
+    }
+  }
+  *best = b;
+  *arg = a;
+}
+
+double row_off2(const Matrix& m, int k) {
+  double s = 0.0;
+  for (int l = 0; l < m.n; ++l)
+    if (l != k) s += m.at(k, l) * m.at(k, l);
+  return s;
+}
+
+// Per-row best-score cache (the O(n) maintenance the paper describes in Sec. 3.2).
+struct RowCache {
+  int strategy;
+  std::vector<double> best;
+  std::vector<int> arg;
+  long long rescans = 0;
+
+  void build(const Matrix& m) {
+    best.assign(m.n, 0.0);
+    arg.assign(m.n, -1);
+    for (int k = 0; k < m.n; ++k) row_best(m, k, strategy, &best[k], &arg[k]);
+  }
+
+  // Called after rotation (p, q) has been applied to m.
+  void refresh(const Matrix& m, int p, int q) {
+    for (int k = 0; k < m.n; ++k) {
+      if (k == p || k == q) {
+        row_best(m, k, strategy, &best[k], &arg[k]);
+        continue;
+      }
+      double sp = pair_score(m, k, p, strategy);
+      double sq = pair_score(m, k, q, strategy);
+      if (arg[k] == p || arg[k] == q) {
+        // the cached maximum itself moved; every other entry is still <= best[k]
+        double v = sp;
+        int col = p;
+        if (sq > v) {
+          v = sq;
+          col = q;
+        }
+        if (v > best[k] || (v == best[k] && col <= arg[k])) {
+          best[k] = v;
+          arg[k] = col;
+        } else {
+          row_best(m, k, strategy, &best[k], &arg[k]);
+          ++rescans;
+        }
+      } else {
+        if (sp > best[k] || (sp == best[k] && p < arg[k])) {
+          best[k] = sp;
+          arg[k] = p;
+        }
+        if (sq > best[k] || (sq == best[k] && q < arg[k])) {
+          best[k] = sq;
+          arg[k] = q;
+        }
+      }
+    }
+  }
+
+  // Row with the largest cached value (smallest row on ties) -> lexicographic argmax.
+  void argmax(double* v, int* i, int* j) const {
+    double b = -1.0;
+    int r = -1;
+    for (int k = 0; k < (int)best.size(); ++k)
+      if (best[k] > b) {
+        b = best[k];
+        r = k;
+      }
+    *v = b;
+    if (r < 0) {
+      *i = *j = -1;
+      return;
+    }
+    *i = std::min(r, arg[r]);
+    *j = std::max(r, arg[r]);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+enum { OR_GREEDY = 0, OR_GAP = 1 };
+enum { OR_STOP_CERT = 0, OR_STOP_OFF = 1, OR_STOP_SCORE = 2 };
+enum { OR_OK = 0, OR_MAXROT = 1, OR_STALL = 2, OR_NONFINITE = 3 };
+
+struct OrStats {
+  long long rotations;
+  long long rescans;
+  double final_sel;   // selection score of the last candidate pivot
+  double final_cert;  // max_{i != j} L_ij at exit
+  double final_off;   // sqrt(sum_{i != j} a_ij^2) at exit
+  int status;
+};
+
+double orc_score_gap(double aii, double ajj, double aij) { return gap_score(aii, ajj, aij); }
+
+void orc_rotation(double app, double aqq, double apq, double* t, double* c, double* s) {
+  rotation<double>(app, aqq, apq, t, c, s);
+}
+
+// Two-sided Jacobi (Algorithm 1) on the full symmetric row-major n x n matrix A, in place.
+//   pivot : 0 greedy |a_ij|, 1 gap-aware L_ij (eq. (1))
+//   stop  : 0 max L_ij <= thr (Theorem 1 certificate), 1 off(A) <= thr, 2 best selection score <= thr
+//   scan  : 0 full O(n^2) scan per rotation, 1 per-row best cache (Sec. 3.2)
+//   VJ    : optional n x n row-major, set to the product of the rotations (starts at I)
+//   plog  : optional int[2*logcap] pivots (p, q), 0-based, p < q
+//   cslog : optional double[2*logcap] (c, s) of each rotation
+int orc_jacobi(double* A, int n, int pivot, int stop, double thr, long long maxrot, int scan,
+               double* VJ, int* plog, double* cslog, long long logcap, OrStats* st) {
+  Matrix m{A, n};
+  std::memset(st, 0, sizeof(*st));
+  for (long long i = 0; i < (long long)n * n; ++i)
+    if (!std::isfinite(A[i])) {
+      st->status = OR_NONFINITE;
+      return OR_NONFINITE;
+    }
+  if (VJ) {
+    std::fill(VJ, VJ + (size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) VJ[(size_t)i * n + i] = 1.0;
+  }
+  RowCache sel{pivot}, cert{OR_GAP};
+  std::vector<double> off2;
+  bool need_cert = (stop == OR_STOP_CERT);
+  if (scan == 1) {
+    sel.build(m);
+    if (need_cert && pivot != OR_GAP) cert.build(m);
+    off2.resize(n);
+    for (int k = 0; k < n; ++k) off2[k] = row_off2(m, k);
+  }
+  long long rot = 0;
+  int status = OR_OK;
+  double vsel = 0.0, vcert = 0.0, voff = 0.0;
+  for (;;) {
+    int p = -1, q = -1;
+    // --- pivot candidate and stop quantities
+    if (scan == 0) {
+      vsel = -1.0;
+      vcert = 0.0;
+      double s2 = 0.0;
+      for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+          double v = pair_score(m, i, j, pivot);
+          if (v > vsel) {
+            vsel = v;
+            p = i;
+            q = j;
+          }
+          double l = gap_score(m.at(i, i), m.at(j, j), m.at(i, j));
+          if (l > vcert) vcert = l;
+          s2 += m.at(i, j) * m.at(i, j);
+        }
+      voff = std::sqrt(2.0 * s2);
+    } else {
+      sel.argmax(&vsel, &p, &q);
+      if (pivot == OR_GAP) {
+        vcert = vsel;
+      } else if (need_cert) {
+        int a, b;
+        cert.argmax(&vcert, &a, &b);
+      }
+      double s2 = 0.0;
+      for (int k = 0; k < n; ++k) s2 += off2[k];
+      voff = std::sqrt(s2);
+    }
+    if (n < 2) break;
+    if (stop == OR_STOP_CERT && vcert <= thr) break;
+    if (stop == OR_STOP_OFF && voff <= thr) break;
+    if (stop == OR_STOP_SCORE && vsel <= thr) break;
+    if (rot >= maxrot) {
+      status = OR_MAXROT;
+      break;
+    }
+    double apq = m.at(p, q);
+    if (apq == 0.0) {  // the best candidate has nothing to annihilate
+      status = OR_STALL;
+      break;
+    }
+    // --- rotation (Sec. 2): A <- G^T A G with G = G(c, s, p, q)
+    double t, c, s;
+    rotation<double>(m.at(p, p), m.at(q, q), apq, &t, &c, &s);
+    for (int k = 0; k < n; ++k) {
+      if (k == p || k == q) continue;
+      double akp = m.at(k, p), akq = m.at(k, q);
+      double xn = c * akp + s * akq;
+      double yn = c * akq - s * akp;
+      A[(size_t)k * n + p] = xn;
+      A[(size_t)p * n + k] = xn;
+      A[(size_t)k * n + q] = yn;
+      A[(size_t)q * n + k] = yn;
+    }
+    double app = m.at(p, p), aqq = m.at(q, q);
+    A[(size_t)p * n + p] = app + t * apq;
+    A[(size_t)q * n + q] = aqq - t * apq;
+    A[(size_t)p * n + q] = 0.0;
+    A[(size_t)q * n + p] = 0.0;
+    if (VJ) {
+      for (int i = 0; i < n; ++i) {
+        double vp = VJ[(size_t)i * n + p], vq = VJ[(size_t)i * n + q];
+        VJ[(size_t)i * n + p] = c * vp + s * vq;
+        VJ[(size_t)i * n + q] = c * vq - s * vp;
+      }
+    }
+    if (plog && rot < logcap) {
+      plog[2 * rot] = p;
+      plog[2 * rot + 1] = q;
+    }
+    if (cslog && rot < logcap) {
+      cslog[2 * rot] = c;
+      cslog[2 * rot + 1] = s;
+    }
+    ++rot;
+    if (scan == 1) {
+      sel.refresh(m, p, q);
+      if (need_cert && pivot != OR_GAP) cert.refresh(m, p, q);
+      off2[p] = row_off2(m, p);
+      off2[q] = row_off2(m, q);
+    }
+  }
+  st->rotations = rot;
+  st->rescans = sel.rescans + cert.rescans;
+  st->final_sel = vsel;
+  st->final_cert = vcert;
+  st->final_off = voff;
+  st->status = status;
+  return status;
+}
+
+// Low-precision spectral decomposition (Sec. 2.1): cyclic-by-rows two-sided Jacobi in
+// FP32 on the full symmetric row-major A32 (in place), accumulating V32 (row-major,
+// starts at I).  A sweep visits every pair (p, q), p < q, in row order.  Sweeps stop once
+// off(A32) <= tol * ||A32||_F, once a sweep fails to reduce off(A32), or after max_sweeps.
+// Returns the number of sweeps performed.
+int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol) {
+  std::fill(V32, V32 + (size_t)n * n, 0.0f);
+  for (int i = 0; i < n; ++i) V32[(size_t)i * n + i] = 1.0f;
+  auto off_and_norm = [&](double* off, double* nrm) {
+    double so = 0.0, sd = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double v = A32[(size_t)i * n + j];
+        if (i == j)
+          sd += v * v;
+        else
+          so += v * v;
+      }
+    *off = std::sqrt(so);
+    *nrm = std::sqrt(so + sd);
+  };
+  double off, nrm;
+  off_and_norm(&off, &nrm);
+  int sweeps = 0;
+  while (sweeps < max_sweeps && off > tol * nrm) {
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        float apq = A32[(size_t)p * n + q];
+        if (apq == 0.0f) continue;
+        float t, c, s;
+        rotation<float>(A32[(size_t)p * n + p], A32[(size_t)q * n + q], apq, &t, &c, &s);
+        for (int k = 0; k < n; ++k) {
+          if (k == p || k == q) continue;
+          float akp = A32[(size_t)k * n + p], akq = A32[(size_t)k * n + q];
+          float xn = c * akp + s * akq;
+          float yn = c * akq - s * akp;
+          A32[(size_t)k * n + p] = xn;
+          A32[(size_t)p * n + k] = xn;
+          A32[(size_t)k * n + q] = yn;
+          A32[(size_t)q * n + k] = yn;
+        }
+        float app = A32[(size_t)p * n + p], aqq = A32[(size_t)q * n + q];
+        A32[(size_t)p * n + p] = app + t * apq;
+        A32[(size_t)q * n + q] = aqq - t * apq;
+        A32[(size_t)p * n + q] = 0.0f;
+        A32[(size_t)q * n + p] = 0.0f;
+        for (int i = 0; i < n; ++i) {
+          float vp = V32[(size_t)i * n + p], vq = V32[(size_t)i * n + q];
+          V32[(size_t)i * n + p] = c * vp + s * vq;
+          V32[(size_t)i * n + q] = c * vq - s * vp;
+        }
+      }
+    ++sweeps;
+    double prev = off;
+    off_and_norm(&off, &nrm);
+    if (off >= prev) break;
+  }
+  return sweeps;
+}
+
+}  // extern "C"

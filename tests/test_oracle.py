@@ -1,0 +1,341 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests re-types the oracle's formulas: each compares it with something
+independent of it (the paper's worked example, the exact eigenvalues of 2x2 blocks in
+high precision, matrices of known spectrum, LAPACK, invariants of orthogonal similarity,
+brute force over all pairs, Theorem 1).
+"""
+import json
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2607_23187_amd import inputs as I
+
+U = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+mpmath.mp.prec = 200
+
+
+def setup_module(_):
+    O.build(force=False)
+
+
+def exact_2x2_shift(a, d, b):
+    """|lambda - a| for the eigenvalue of [[a, b], [b, d]] that continues a (mpmath).
+
+    The eigenvalues are (a+d)/2 +- sqrt(((a-d)/2)^2 + b^2); the one nearest a moves by
+    sqrt(((a-d)/2)^2 + b^2) - |a-d|/2.  This is the quantity the paper says the score
+    measures for the 2x2 block (Sec. 3: the score is the Li-Li bound, tight for 2x2)."""
+    a, d, b = mpmath.mpf(a), mpmath.mpf(d), mpmath.mpf(b)
+    h = (a - d) / 2
+    return mpmath.sqrt(h * h + b * b) - abs(h)
+
+
+def exact_2x2_eigs(a, d, b):
+    a, d, b = mpmath.mpf(a), mpmath.mpf(d), mpmath.mpf(b)
+    m = (a + d) / 2
+    r = mpmath.sqrt(((a - d) / 2) ** 2 + b * b)
+    return m - r, m + r
+
+
+def ulps(x, ref):
+    ref = float(ref)
+    return abs(x - ref) / max(np.spacing(abs(ref)), np.finfo(float).tiny)
+
+
+# ------------------------------------------------------------------ eq. (1)
+def test_score_is_exact_2x2_eigenvalue_shift():
+    rng = np.random.default_rng(1)
+    worst = 0.0
+    for _ in range(2000):
+        a = rng.uniform(-3, 3)
+        d = a + rng.choice([1.0, 1e-3, 1e-8, 1e-12, 0.0]) * rng.standard_normal()
+        b = rng.choice([1.0, 1e-4, 1e-9, 1e-14]) * rng.standard_normal()
+        got = O.score_gap(a, d, b)
+        worst = max(worst, ulps(got, exact_2x2_shift(a, d, b)))
+    assert worst <= 4.0
+
+
+def test_score_special_cases():
+    # a_ij = 0 -> 0 (also in the 0/0 case a_ii == a_jj)
+    assert O.score_gap(1.0, 1.0, 0.0) == 0.0
+    assert O.score_gap(1.0, 2.0, 0.0) == 0.0
+    # equal diagonal -> |a_ij| (the gap score coincides with the greedy one)
+    for b in (1e-3, -2.5, 1e-150):
+        assert O.score_gap(0.5, 0.5, b) == pytest.approx(abs(b), rel=4 * U)
+    # a_ij^2 underflows to 0 -> defined as 0 (the reading of eq. (1) for that case)
+    assert O.score_gap(0.5, 0.5, 7e-300) == 0.0
+    # large gap -> a^2 / |delta| (quadratic regime of the Li-Li bound)
+    assert O.score_gap(0.0, 1.0, 1e-6) == pytest.approx(1e-12, rel=1e-11)
+    # 0 <= L <= |a_ij|
+    rng = np.random.default_rng(2)
+    for _ in range(500):
+        a, d, b = rng.standard_normal(3)
+        s = O.score_gap(a, d, b)
+        assert 0.0 <= s <= abs(b) * (1 + 4 * U)
+
+
+def test_worked_example_scores():
+    """Sec. 1: block 1 (gap 1) is harmless, block 2 (gap 1e-10) moves eigenvalues by O(1e-9)."""
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    b1, b2 = g["matrix_blocks"]
+    l12 = O.score_gap(b1[0][0], b1[1][1], b1[0][1])
+    l34 = O.score_gap(b2[0][0], b2[1][1], b2[0][1])
+    assert l12 <= g["block1_diagonal_error_below"] * (1 + 1e-12)
+    assert 0.1 * g["block2_diagonal_error_order"] < l34 < 10 * g["block2_diagonal_error_order"]
+    assert ulps(l12, exact_2x2_shift(b1[0][0], b1[1][1], b1[0][1])) <= 2
+    assert ulps(l34, exact_2x2_shift(b2[0][0], b2[1][1], b2[0][1])) <= 2
+
+
+def test_worked_example_pivots_and_stop():
+    """Greedy picks (1,2) first, the gap score picks (3,4) (Sec. 1).  With a raw
+    threshold of 1e-15 on the certificate the gap strategy is done after one rotation,
+    greedy needs two."""
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    a = I.worked_example().a
+    for scan in (0, 1):
+        rg = O.jacobi(a, pivot=O.GREEDY, stop=O.STOP_CERT, thr=1e-15, scan=scan)
+        rl = O.jacobi(a, pivot=O.GAP, stop=O.STOP_CERT, thr=1e-15, scan=scan)
+        assert list(rg.pivots[0] + 1) == g["greedy_first_pivot_1based"]
+        assert list(rl.pivots[0] + 1) == g["gap_first_pivot_1based"]
+        assert rl.rotations == 1 and rg.rotations == 2
+    # block 2 after the gap rotation equals its exact eigenvalues (closed form, 2 ulp)
+    lo, hi = exact_2x2_eigs(a[2, 2], a[3, 3], a[2, 3])
+    d = np.diag(rl.a)
+    assert ulps(d[2], lo) <= 2 and ulps(d[3], hi) <= 2
+    # block 1 untouched, within 1e-16 of its eigenvalues
+    lo1, hi1 = exact_2x2_eigs(1.0, 2.0, 1e-8)
+    assert abs(mpmath.mpf(d[0]) - lo1) <= 1.0001e-16
+    assert abs(mpmath.mpf(d[1]) - hi1) <= 1.0001e-16
+
+
+# ------------------------------------------------------------------ rotation
+def test_one_rotation_diagonalises_2x2():
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        a, d = rng.uniform(-2, 2, 2)
+        b = rng.choice([1.0, 1e-5, 1e-11]) * rng.standard_normal()
+        if rng.uniform() < 0.1:
+            d = a
+        m = np.array([[a, b], [b, d]])
+        r = O.jacobi(m, pivot=O.GAP, stop=O.STOP_CERT, thr=0.0, maxrot=1, scan=0)
+        assert r.rotations == 1
+        assert r.a[0, 1] == 0.0 and r.a[1, 0] == 0.0
+        lo, hi = exact_2x2_eigs(a, d, b)
+        got = np.sort(np.diag(r.a))
+        scale = max(abs(a), abs(d), abs(b))
+        assert abs(got[0] - float(lo)) <= 4 * U * scale
+        assert abs(got[1] - float(hi)) <= 4 * U * scale
+        # V_J is the rotation: orthogonal and it diagonalises m
+        v = r.vj
+        assert np.allclose(v.T @ v, np.eye(2), atol=4 * U)
+        assert np.allclose(v.T @ m @ v, r.a, atol=8 * U * scale)
+
+
+def test_rotation_small_angle_and_overflow_guard():
+    t, c, s = O.rotation(1.0, 1.0, 0.3)       # equal diagonal: 45 degrees, sgn(0) = +1
+    assert t == 1.0 and c == pytest.approx(np.sqrt(0.5), rel=2 * U) and s == c
+    t, c, s = O.rotation(1e300, -1e300, 1e-300)  # |theta| beyond 2^500
+    assert c == 1.0 and np.isfinite(t) and abs(t) < 1e-300
+    for args in [(2.0, 1.0, 0.5), (1.0, 2.0, 0.5), (1.0, 2.0, -0.5), (3.0, -1.0, 2.0)]:
+        t, c, s = O.rotation(*args)
+        assert abs(t) <= 1.0 and c * c + s * s == pytest.approx(1.0, abs=4 * U)
+
+
+# ------------------------------------------------------------------ invariants
+def test_orthogonal_similarity_invariants():
+    a0 = I.random_symmetric(12, seed=4)
+    prev = a0
+    tr0, fro0 = np.trace(a0), np.linalg.norm(a0)
+    for k in range(1, 40):
+        r = O.jacobi(a0, pivot=O.GAP, stop=O.STOP_CERT, thr=0.0, maxrot=k, scan=1)
+        a = r.a
+        assert abs(np.trace(a) - tr0) <= 64 * U * fro0
+        assert abs(np.linalg.norm(a) - fro0) <= 64 * U * fro0
+        assert np.array_equal(a, a.T)
+        # off(A)^2 drops by exactly 2 a_pq^2 in exact arithmetic
+        p, q = r.pivots[-1]
+        off = lambda m: np.sum(m * m) - np.sum(np.diag(m) ** 2)
+        assert abs((off(prev) - off(a)) - 2 * prev[p, q] ** 2) <= 256 * U * fro0 ** 2
+        # V_J^T A0 V_J reproduces the iterate
+        assert np.allclose(r.vj.T @ a0 @ r.vj, a, atol=256 * U * fro0)
+        assert np.linalg.norm(r.vj.T @ r.vj - np.eye(12)) <= 64 * U
+        prev = a
+
+
+# ------------------------------------------------------------------ argmax
+def test_first_pivot_is_bruteforce_argmax():
+    """The chosen pivot maximises the exact 2x2 eigenvalue shift over all pairs."""
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        n = int(rng.integers(3, 7))
+        lam = rng.uniform(1, 2, n)
+        lam[: n // 2] = lam[0] + rng.uniform(0, 1e-9, n // 2)  # a tight cluster
+        a = I.from_spectrum(lam, rng)
+        a = a + np.diag(rng.uniform(0, 1e-3, n))
+        best, arg = -1.0, None
+        for i in range(n):
+            for j in range(i + 1, n):
+                v = exact_2x2_shift(a[i, i], a[j, j], a[i, j])
+                if v > best:
+                    best, arg = v, (i, j)
+        r = O.jacobi(a, pivot=O.GAP, stop=O.STOP_CERT, thr=0.0, maxrot=1, scan=0)
+        assert tuple(r.pivots[0]) == arg
+        g = O.jacobi(a, pivot=O.GREEDY, stop=O.STOP_CERT, thr=0.0, maxrot=1, scan=1)
+        iu = np.triu_indices(n, 1)
+        k = int(np.argmax(np.abs(a[iu])))
+        assert tuple(g.pivots[0]) == (iu[0][k], iu[1][k])
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 16, 64, 150])
+@pytest.mark.parametrize("pivot", [O.GREEDY, O.GAP])
+def test_row_cache_equals_full_scan(n, pivot):
+    """Sec. 3.2: maintaining per-row maxima after each rotation selects exactly the
+    pivots of a full O(n^2) scan."""
+    p = I.clustered(n, seed=100 + n, size=4, offset=1e-9) if n >= 4 else None
+    a = p.a if p else I.random_symmetric(n, seed=n)
+    normF = np.linalg.norm(a)
+    thr = O.threshold(O.STOP_CERT, 10 * n * U, n, normF)
+    r0 = O.jacobi(a, pivot=pivot, stop=O.STOP_CERT, thr=thr, scan=0, want_vj=False)
+    r1 = O.jacobi(a, pivot=pivot, stop=O.STOP_CERT, thr=thr, scan=1, want_vj=False)
+    assert r0.rotations == r1.rotations
+    assert np.array_equal(r0.pivots, r1.pivots)
+    assert np.array_equal(r0.a, r1.a)
+
+
+def test_ties_break_to_smallest_pair():
+    a = np.eye(5)
+    for (i, j) in [(1, 3), (0, 4), (2, 3), (0, 2)]:
+        a[i, j] = a[j, i] = 0.25
+    for pivot in (O.GREEDY, O.GAP):
+        for scan in (0, 1):
+            r = O.jacobi(a, pivot=pivot, stop=O.STOP_CERT, thr=0.0, maxrot=1, scan=scan)
+            assert tuple(r.pivots[0]) == (0, 2)
+
+
+# ------------------------------------------------------------------ whole solves
+def _known(n, seed, size=8, offset=1e-10):
+    p = I.clustered(n, seed=seed, size=size, offset=offset)
+    return p.a, p.lam
+
+
+@pytest.mark.parametrize("pivot", [O.GREEDY, O.GAP])
+@pytest.mark.parametrize("precond", ["none", "fp32"])
+def test_known_spectrum_and_lapack(pivot, precond):
+    a, lam = _known(64, seed=7)
+    n = 64
+    nrm2 = np.max(np.abs(lam))
+    tol = 10 * n * U * nrm2 / np.linalg.norm(a)
+    e = O.eigh(a, tol=tol, pivot=pivot, precond=precond, stop=O.STOP_CERT)
+    assert e.status == O.OK
+    bound = 10 * n * U * nrm2
+    assert np.max(np.abs(e.w - lam)) <= bound
+    assert np.max(np.abs(e.w - np.linalg.eigvalsh(a))) <= bound
+    # Theorem 1: the certificate bounds the diagonal's distance to the spectrum
+    assert np.max(np.abs(e.w - np.linalg.eigvalsh(a))) <= 2 * n * (n - 1) * e.thr + 4 * n * U * nrm2
+    # V: orthonormal columns, and A V ~ V W within the off-norm left at the stop
+    assert np.linalg.norm(e.v.T @ e.v - np.eye(n)) <= 10 * n * U
+
+
+def test_theorem1_proof_inequality_at_stop():
+    """At the certificate stop every pair satisfies |a_ij|^2 <= eps |a_ii - a_jj| + eps^2
+    (the first step of the proof of Theorem 1)."""
+    a, lam = _known(48, seed=8, size=6, offset=1e-9)
+    n = 48
+    thr = O.threshold(O.STOP_CERT, 1e-12, n, np.linalg.norm(a))
+    r = O.jacobi(a, pivot=O.GAP, stop=O.STOP_CERT, thr=thr, scan=1)
+    f = r.a
+    d = np.diag(f)
+    lhs = f ** 2
+    rhs = thr * np.abs(d[:, None] - d[None, :]) + thr ** 2
+    np.fill_diagonal(lhs, 0.0)
+    assert np.all(lhs <= rhs * (1 + 1e-12))
+    # and the bound of Theorem 1 itself
+    assert np.max(np.abs(np.sort(d) - np.linalg.eigvalsh(a))) <= 2 * n * (n - 1) * thr + 8 * n * U
+
+
+def test_greedy_off_stop_diagonalises():
+    a, lam = _known(32, seed=9)
+    normF = np.linalg.norm(a)
+    e = O.eigh(a, tol=1e-15, pivot=O.GREEDY, precond="fp32", stop=O.STOP_OFF)
+    assert e.extra["final_off"] <= 1e-15 * normF
+    assert np.max(np.abs(e.w - lam)) <= 10 * 32 * U * 2
+
+
+def test_nonfinite_and_maxrot():
+    a = I.random_symmetric(6, seed=10)
+    a[1, 4] = np.nan
+    assert O.eigh(a, tol=1e-12, precond="none").status == O.NONFINITE
+    b = I.random_symmetric(6, seed=11)
+    e = O.eigh(b, tol=1e-14, precond="none", maxrot=3)
+    assert e.status == O.MAXROT and e.rotations == 3
+    assert np.linalg.norm(e.v.T @ e.v - np.eye(6)) <= 64 * U
+
+
+def test_degenerate_sizes():
+    e = O.eigh(np.array([[3.5]]), tol=1e-12, precond="fp32")
+    assert e.w.tolist() == [3.5] and e.v.tolist() == [[1.0]] and e.rotations == 0
+    e = O.eigh(np.diag([3.0, 1.0, 2.0]), tol=1e-12, precond="none")
+    assert e.w.tolist() == [1.0, 2.0, 3.0] and e.rotations == 0
+    assert np.array_equal(np.abs(e.v), np.eye(3)[:, [1, 2, 0]])
+
+
+def test_upper_triangle_is_read():
+    a, lam = _known(16, seed=12)
+    junk = a.copy()
+    junk[np.tril_indices(16, -1)] = 1e3
+    e1 = O.eigh(a, tol=1e-13, precond="none")
+    e2 = O.eigh(junk, tol=1e-13, precond="none")
+    assert np.array_equal(e1.w, e2.w)
+
+
+# ------------------------------------------------------------------ preconditioner
+def test_fp32_preconditioner_quality():
+    """Sec. 2.1: after V^T A V with a re-orthogonalised low-precision eigenbasis the
+    off-diagonal entries are O(||A|| u_l); V is orthogonal to working precision."""
+    n = 96
+    a, lam = _known(n, seed=13)
+    nrm2 = np.max(np.abs(lam))
+    a32, v32, sweeps = O.jacobi_f32(a)
+    assert 1 <= sweeps <= 20
+    u32 = 2.0 ** -24
+    # FP32 Jacobi: eigenvalues to FP32 accuracy, columns eigenvectors to FP32 accuracy
+    assert np.max(np.abs(np.sort(np.diag(a32).astype(np.float64)) - lam)) <= 64 * np.sqrt(n) * u32 * nrm2
+    v = v32.astype(np.float64)
+    assert np.linalg.norm(v.T @ v - np.eye(n)) <= 64 * n * u32
+    q = O.householder_q(v)
+    assert np.linalg.norm(q.T @ q - np.eye(n)) <= 4 * n * U
+    ah = q.T @ (a @ q)
+    off = np.abs(ah - np.diag(np.diag(ah)))
+    assert off.max() <= 64 * np.sqrt(n) * u32 * nrm2
+
+
+# ------------------------------------------------------------------ Sec. 4.1 behaviour
+def test_sec41_gap_beats_greedy_on_tight_cluster():
+    """Sec. 4.1: with alpha = 1 the gap-aware pivots need far fewer rotations than greedy
+    to the same certificate; with alpha = 0.01 they are about as good (slightly better).
+    Fig. 2 discussion: gap pivots start inside the cluster, greedy pivots outside it."""
+    n = 120
+    out = {}
+    for alpha in (1.0, 0.01):
+        p = I.sec41(n=n, alpha=alpha)
+        tol = 10 * n * U * 3.0 / np.linalg.norm(p.a)
+        for pivot in (O.GREEDY, O.GAP):
+            e = O.eigh(p.a, tol=tol, pivot=pivot, precond="fp32", stop=O.STOP_CERT)
+            assert np.max(np.abs(e.w - p.lam)) <= 10 * n * U * 3.0
+            clu = np.diag(e.a_hat) < 1.5
+            pv = e.pivots[:1000]
+            out[(alpha, pivot)] = (e.rotations, np.mean(clu[pv[:, 0]] & clu[pv[:, 1]]))
+    assert out[(1.0, O.GAP)][0] < 0.6 * out[(1.0, O.GREEDY)][0]
+    assert out[(0.01, O.GAP)][0] <= 1.05 * out[(0.01, O.GREEDY)][0]
+    assert out[(1.0, O.GAP)][1] > 0.5 > out[(1.0, O.GREEDY)][1]
+
+
+def test_total_relative_error_definition():
+    lam = np.array([1.0, 2.0, -4.0])
+    assert O.total_relative_error(lam, lam + np.array([1e-3, 0, 0])) == pytest.approx(1e-3 / 4)
