@@ -1,0 +1,150 @@
+/*
+ * jacobi.h -- C ABI of the MI355X (gfx950) preconditioned Jacobi eigensolver with the
+ * gap-aware pivot score of Shao & Nakatsukasa, "Accelerating preconditioned Jacobi
+ * methods via perturbation-inspired pivoting".
+ *
+ * Problem (Algorithm 1): given a real symmetric A (n x n), compute its eigenvalues as
+ * the diagonal of a sequence of Jacobi rotations A <- G^T A G (Sec. 2), each rotation
+ * annihilating the off-diagonal entry chosen by a pivot rule:
+ *   greedy: argmax_{i != j} |a_ij|                                  (Sec. 1)
+ *   gap   : argmax_{i != j} L_ij,                                    (eq. (1))
+ *           L_ij = 2 a_ij^2 / (|a_ii - a_jj| + sqrt((a_ii - a_jj)^2 + 4 a_ij^2)),
+ *           with L_ij := 0 when a_ij^2 is 0 in FP64.
+ * Ties go to the lexicographically smallest (i, j), i < j.
+ * The eigenvectors are the preconditioner times the accumulated rotations (Sec. 2.1).
+ *
+ * Preconditioner (Sec. 2.1): with JE_PRECOND_FP32 the library first computes an FP32
+ * spectral decomposition by a parallel cyclic Jacobi in FP32, re-orthogonalises its
+ * eigenvector matrix in FP64 by Newton-Schulz, and runs the FP64 pivoted Jacobi on
+ * Q^T A Q, whose off-diagonal entries are O(||A|| u_32).
+ *
+ * Stop rule (default, Theorem 1): stop once max_{i != j} L_ij <= eps with
+ *   eps = tol * ||A||_F / (2 n (n - 1)),
+ * which guarantees |lambda_k - a_kk| <= tol * ||A||_F for the sorted diagonal.
+ *
+ * Conventions for every entry point:
+ *   - All matrix/vector pointers are DEVICE pointers (hipMalloc'd memory or torch CUDA
+ *     tensors) unless stated otherwise.  The library never frees caller memory.
+ *   - A is column-major with leading dimension lda >= max(1, n): element (i, j) is
+ *     A[i + j*lda].  Only the upper triangle (i <= j) is read; it is mirrored.  A is
+ *     never modified.
+ *   - W receives n eigenvalues in ascending order (stable: equal values keep the order
+ *     of the diagonal positions that produced them).
+ *   - V (may be NULL = eigenvalues only) is column-major with leading dimension ldv >= n:
+ *     component i of the eigenvector of W[k] is V[i + k*ldv].
+ *   - All calls are blocking: work is enqueued on `stream` (NULL = the null stream of
+ *     the current device) and the call returns once it has completed.
+ *   - The library owns a per-device workspace pool (grown on demand, released by
+ *     jacobi_release()).  Calls from several host threads are serialised internally.
+ *
+ * Return status (int):
+ *   0                 JE_OK
+ *   -k (k >= 1)       the k-th argument is invalid (LAPACK info convention)
+ *   JE_WARN_MAXROT    the rotation cap was reached; W, V hold the current iterate (V is
+ *                     still orthogonal)
+ *   JE_WARN_STALL     the best remaining pivot has a_pq == 0 (nothing to annihilate)
+ *                     while the stop rule does not hold; W, V hold the current iterate
+ *   JE_ERR_NONFINITE  A holds NaN or Inf in its upper triangle; outputs untouched
+ *   JE_ERR_NOMEM      device memory for the workspace could not be allocated
+ *   JE_ERR_DEVICE     a HIP runtime call failed (no device, launch failure, ...)
+ *   JE_ERR_TOO_LARGE  n exceeds JE_MAX_N
+ */
+#ifndef JACOBI_GAP_JACOBI_H
+#define JACOBI_GAP_JACOBI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A HIP stream handle (hipStream_t) passed as an opaque pointer. */
+typedef void* je_stream;
+
+#define JE_MAX_N 8192
+
+enum je_pivot { JE_PIVOT_GREEDY = 0, JE_PIVOT_GAP = 1 };
+enum je_precond { JE_PRECOND_NONE = 0, JE_PRECOND_FP32 = 1 };
+enum je_stop {
+  JE_STOP_CERT = 0,  /* max_{i!=j} L_ij <= tol*||A||_F / (2n(n-1))   (Theorem 1)           */
+  JE_STOP_OFF = 1,   /* off(A) = sqrt(sum_{i!=j} a_ij^2) <= tol*||A||_F                      */
+  JE_STOP_SCORE = 2  /* selection score of the best pivot (|a_pq| or L_pq) <= tol*||A||_F  */
+};
+enum je_status {
+  JE_OK = 0,
+  JE_WARN_MAXROT = 1,
+  JE_WARN_STALL = 2,
+  JE_ERR_NONFINITE = 3,
+  JE_ERR_NOMEM = 4,
+  JE_ERR_DEVICE = 5,
+  JE_ERR_TOO_LARGE = 6
+};
+
+/* Options of the _ex / _batched entry points.  Fill with je_opts_default() first. */
+typedef struct je_opts {
+  int stop;                  /* enum je_stop                              (JE_STOP_CERT) */
+  int polish_v;              /* 1: one FP64 Newton-Schulz step on V             (1)   */
+  int fp32_max_sweeps;       /* sweeps cap of the FP32 preconditioner          (20)   */
+  long long max_rotations;   /* <= 0: 40 n^2 + 64                              (0)    */
+  double abs_thr;            /* > 0: absolute threshold of the stop rule,             */
+                             /*      overriding the one derived from tol         (0)  */
+  int* pivot_log;            /* device int32[2*pivot_log_cap]: (p, q) of every        */
+                             /* rotation of the FP64 phase, 0-based, p < q; NULL = off */
+  long long pivot_log_cap;
+} je_opts;
+
+/* Statistics of one solve (host struct, filled before return). */
+typedef struct je_stats {
+  long long rotations;       /* FP64 Jacobi rotations performed                     */
+  long long rescans;         /* full row rescans of the per-row score cache         */
+  double final_max_score;    /* max_{i!=j} L_ij of the final iterate (certificate)  */
+  double final_off;          /* off(A) of the final iterate                         */
+  double normF;              /* ||A||_F of the input                                */
+  double thr;                /* absolute stop threshold used                        */
+  int sweeps32;              /* FP32 preconditioner sweeps                          */
+  int status;
+  float ms_precond;          /* FP32 Jacobi + re-orthogonalisation                  */
+  float ms_gemm;             /* Q^T A Q contraction                                 */
+  float ms_jacobi;           /* FP64 pivoted Jacobi (initial scores + rotations)    */
+  float ms_finalize;         /* eigenvectors, polish, sort                          */
+} je_stats;
+
+void je_opts_default(je_opts* opts);
+
+/* Eigenvalues W (and eigenvectors V, ldv = n) of the symmetric A, stop rule of Theorem 1
+ * with tolerance tol > 0 relative to ||A||_F.  pivot: enum je_pivot, precond: enum
+ * je_precond.  Null stream, default options. */
+int jacobi_eigh(const double* A, int n, int lda, double* W, double* V, double tol, int pivot,
+                int precond);
+
+/* As jacobi_eigh with explicit ldv, options (NULL = defaults), statistics (host pointer,
+ * may be NULL) and stream. */
+int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
+                   int pivot, int precond, const je_opts* opts, je_stats* stats,
+                   je_stream stream);
+
+/* `batch` independent problems of (possibly different) sizes solved together.
+ * A, W, V: HOST arrays of `batch` device pointers (V[b] may be NULL);
+ * n, lda, ldv: HOST int arrays; info: HOST int array receiving each problem's status;
+ * stats: HOST array of `batch` je_stats or NULL.  The whole batch shares tol, pivot,
+ * precond and opts (opts->pivot_log is ignored).  Returns the worst status (errors before
+ * warnings) or a negative argument index. */
+int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const int* lda,
+                        double* const* W, double* const* V, const int* ldv, double tol,
+                        int pivot, int precond, const je_opts* opts, int* info,
+                        je_stats* stats, je_stream stream);
+
+/* Device bytes the workspace pool holds for one solve of size n. */
+size_t jacobi_workspace_size(int n, int precond);
+
+/* Static description of a status code. */
+const char* jacobi_strerror(int status);
+
+/* Free the workspace pool of every device. */
+void jacobi_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACOBI_GAP_JACOBI_H */

@@ -1,0 +1,405 @@
+// Host side of the C ABI declared in include/jacobi.h: argument checking, the per-device
+// workspace pool and the order of the phases of one solve:
+//   1. symmetric FP64 copy of the upper triangle, finiteness check, ||A||_F
+//   2. (FP32 preconditioner) parallel cyclic FP32 Jacobi -> V_l, FP64 Newton-Schulz -> Q,
+//      A_hat = Q^T (A Q) on the matrix cores, symmetrised                     (Sec. 2.1)
+//   3. initial per-row scores, persistent pivoted Jacobi (greedy or eq. (1)), stop rule of
+//      Theorem 1 (or off-norm / raw score); the rotation log is drained into V = Q G_1 G_2...
+//   4. one Newton-Schulz polish of V, eigenvalues sorted ascending, V permuted to match.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/jacobi.h"
+#include "kernels.h"
+
+using namespace je;
+
+namespace {
+
+std::mutex g_mu;
+
+struct Pool {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::vector<Pool> g_pools;
+
+void* pool_get(size_t bytes, int* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { *err = JE_ERR_DEVICE; return nullptr; }
+  if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1);
+  Pool& p = g_pools[dev];
+  if (p.bytes < bytes) {
+    if (p.ptr) { (void)hipDeviceSynchronize(); (void)hipFree(p.ptr); p.ptr = nullptr; p.bytes = 0; }
+    if (hipMalloc(&p.ptr, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *err = JE_ERR_NOMEM;
+      return nullptr;
+    }
+    p.bytes = bytes;
+  }
+  return p.ptr;
+}
+
+inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+inline int ld_of(int n) { return (n + 7) & ~7; }
+
+long long log_cap_for(int n, long long maxrot) {
+  long long cap = 1ll << 22;
+  return std::max<long long>(1, std::min(cap, maxrot));
+}
+
+long long default_maxrot(int n) { return 40ll * n * n + 64; }
+
+// Workspace carving for one problem of size n.
+struct WS {
+  double *Asym, *A, *Q, *X, *T, *R, *Vw;
+  double *diag, *bs, *bv, *cb, *off2, *rowsq, *scal;
+  int *ba, *bst, *ca, *cst, *ts, *rank, *flag;
+  JCtl* ctl;
+  RotEntry* log;
+  void* f32;
+  long long log_cap;
+};
+
+size_t ws_bytes(int n, int precond, long long log_cap) {
+  size_t ld = ld_of(n);
+  size_t mat = al((size_t)n * ld * 8);
+  size_t b = 0;
+  b += mat;                       // Asym (also the Jacobi matrix without preconditioner)
+  b += mat;                       // Vw
+  if (precond) b += 5 * mat;      // A, Q, X, T, R
+  else b += 2 * mat;              // X, R (polish)
+  b += 6 * al((size_t)n * 8);     // diag bs bv cb off2 rowsq
+  b += al(64);                    // scalars
+  b += 7 * al((size_t)n * 4);     // ba bst ca cst ts rank flag
+  b += al(sizeof(JCtl));
+  b += al((size_t)log_cap * sizeof(RotEntry));
+  if (precond) b += al(precond_f32_bytes(n));
+  return b;
+}
+
+WS ws_carve(void* base, int n, int precond, long long log_cap) {
+  WS w{};
+  char* p = (char*)base;
+  size_t ld = ld_of(n);
+  size_t mat = al((size_t)n * ld * 8);
+  auto take = [&](size_t b) { char* r = p; p += al(b); return (void*)r; };
+  w.Asym = (double*)take(mat);
+  w.Vw = (double*)take(mat);
+  if (precond) {
+    w.A = (double*)take(mat);
+    w.Q = (double*)take(mat);
+    w.X = (double*)take(mat);
+    w.T = (double*)take(mat);
+    w.R = (double*)take(mat);
+  } else {
+    w.A = w.Asym;
+    w.Q = nullptr;
+    w.X = (double*)take(mat);
+    w.R = (double*)take(mat);
+    w.T = nullptr;
+  }
+  w.diag = (double*)take((size_t)n * 8);
+  w.bs = (double*)take((size_t)n * 8);
+  w.bv = (double*)take((size_t)n * 8);
+  w.cb = (double*)take((size_t)n * 8);
+  w.off2 = (double*)take((size_t)n * 8);
+  w.rowsq = (double*)take((size_t)n * 8);
+  w.scal = (double*)take(64);
+  w.ba = (int*)take((size_t)n * 4);
+  w.bst = (int*)take((size_t)n * 4);
+  w.ca = (int*)take((size_t)n * 4);
+  w.cst = (int*)take((size_t)n * 4);
+  w.ts = (int*)take((size_t)n * 4);
+  w.rank = (int*)take((size_t)n * 4);
+  w.flag = (int*)take((size_t)n * 4);
+  w.ctl = (JCtl*)take(sizeof(JCtl));
+  w.log = (RotEntry*)take((size_t)log_cap * sizeof(RotEntry));
+  w.f32 = precond ? take(precond_f32_bytes(n)) : nullptr;
+  w.log_cap = log_cap;
+  return w;
+}
+
+#define HIPCHK(x)                       \
+  do {                                  \
+    if ((x) != hipSuccess) {            \
+      (void)hipGetLastError();          \
+      return JE_ERR_DEVICE;             \
+    }                                   \
+  } while (0)
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  bool ok;
+  explicit Timer(hipStream_t st) : s(st) {
+    ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    if (ok) (void)hipEventRecord(a, s);
+  }
+  float stop() {
+    float ms = 0.f;
+    if (!ok) return 0.f;
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+  ~Timer() {
+    if (ok) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  }
+};
+
+// One Newton-Schulz step toward the nearest orthogonal matrix, as a small correction:
+// R = I - X^T X, X <- X + X R / 2.  Returns ||R||_F (before the step) through `rnorm`.
+int ns_step(double*& X, double*& Xalt, double* R, int n, int ld, double* part, double* scal,
+            double* rnorm, hipStream_t s) {
+  HIPCHK(launch_dgemm(n, 1, -1.0, X, ld, X, ld, 0.0, nullptr, 0, R, ld, s));
+  HIPCHK(launch_add_identity(R, n, ld, 1.0, s));
+  if (rnorm) {
+    HIPCHK(launch_fro2(R, n, ld, part, scal, s));
+    HIPCHK(hipMemcpyAsync(rnorm, scal, 8, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(launch_dgemm(n, 0, 0.5, X, ld, R, ld, 1.0, X, ld, Xalt, ld, s));
+  std::swap(X, Xalt);
+  return JE_OK;
+}
+
+int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, double tol,
+              int pivot, int precond, const je_opts& o, je_stats* st, hipStream_t s) {
+  const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
+  const long long cap = log_cap_for(n, maxrot);
+  int err = JE_OK;
+  void* base = pool_get(ws_bytes(n, precond, cap), &err);
+  if (!base) return err;
+  WS w = ws_carve(base, n, precond, cap);
+  const int ld = ld_of(n);
+  je_stats S{};
+
+  // ---- 1. symmetric copy, finiteness, ||A||_F
+  Timer tp(s);
+  HIPCHK(hipMemsetAsync(w.flag, 0, 4, s));
+  HIPCHK(launch_symcopy(Au, n, lda, w.Asym, ld, w.diag, nullptr, w.flag, s));
+  HIPCHK(launch_fro2(w.Asym, n, ld, w.rowsq, w.scal, s));
+  int flag = 0;
+  double normF = 0.0;
+  HIPCHK(hipMemcpyAsync(&flag, w.flag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&normF, w.scal, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flag) return JE_ERR_NONFINITE;
+  S.normF = normF;
+  double thr;
+  if (o.abs_thr > 0.0) thr = o.abs_thr;
+  else if (o.stop == JE_STOP_CERT) thr = tol * normF / (2.0 * n * (double)(n - 1));
+  else thr = tol * normF;
+  S.thr = thr;
+
+  // ---- 2. preconditioner
+  double* Ajac = w.Asym;
+  double* Vw = w.Vw;
+  if (precond) {
+    int sweeps = 0;
+    HIPCHK(run_precond_f32(w.Asym, n, ld, w.Q, ld, w.f32, o.fp32_max_sweeps, &sweeps, s));
+    S.sweeps32 = sweeps;
+    // Newton-Schulz until ||I - Q^T Q||_F <= 4 n u (at most 6 steps)
+    double* X = w.Q;
+    double* Xalt = w.X;
+    for (int itn = 0; itn < 6; ++itn) {
+      double rn = 0.0;
+      int r = ns_step(X, Xalt, w.R, n, ld, w.rowsq, w.scal, &rn, s);
+      if (r) return r;
+      HIPCHK(hipStreamSynchronize(s));
+      if (rn <= 4.0 * n * 0x1p-53) break;
+    }
+    S.ms_precond = tp.stop();
+    Timer tg(s);
+    // A_hat = Q^T (A Q): T = A Q, A_hat = Q^T T, then exact symmetry
+    HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
+    HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
+    HIPCHK(launch_symmetrize(w.A, n, ld, s));
+    HIPCHK(hipMemcpyAsync(Vw, X, (size_t)n * ld * 8, hipMemcpyDeviceToDevice, s));
+    Ajac = w.A;
+    S.ms_gemm = tg.stop();
+  } else {
+    HIPCHK(launch_set_identity(Vw, n, ld, s));
+    S.ms_precond = tp.stop();
+  }
+
+  // ---- 3. pivoted Jacobi
+  Timer tj(s);
+  JDesc d{};
+  d.A = Ajac; d.n = n; d.ld = ld;
+  d.diag = w.diag; d.bs = w.bs; d.ba = w.ba; d.bv = w.bv; d.bst = w.bst;
+  d.cb = w.cb; d.ca = w.ca; d.cst = w.cst; d.off2 = w.off2; d.ts = w.ts;
+  d.log = w.log; d.log_cap = cap; d.ctl = w.ctl;
+  d.thr = thr; d.maxrot = maxrot; d.pivot = pivot; d.stop = o.stop;
+  if (precond) HIPCHK(launch_get_diag(Ajac, n, ld, w.diag, s));
+  HIPCHK(hipMemsetAsync(w.ctl, 0, sizeof(JCtl), s));
+  HIPCHK(launch_init_rows(d, s));
+  const bool lds = jacobi_fits_lds(n);
+  long long base_rot = 0;
+  JCtl hc{};
+  float ms_apply = 0.f;
+  for (;;) {
+    HIPCHK(launch_jacobi(d, base_rot, lds, s));
+    HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(JCtl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    long long m = hc.rotations - base_rot;
+    if (o.pivot_log && base_rot < o.pivot_log_cap) {
+      long long mm = std::min(m, o.pivot_log_cap - base_rot);
+      HIPCHK(launch_copy_pivots(w.log, mm, o.pivot_log + 2 * base_rot, s));
+    }
+    Timer ta(s);
+    HIPCHK(launch_apply_log(Vw, n, ld, w.log, m, s));
+    ms_apply += ta.stop();
+    base_rot = hc.rotations;
+    if (hc.done) break;
+  }
+  S.ms_jacobi = tj.stop() - ms_apply;
+  S.rotations = hc.rotations;
+  S.rescans = hc.rescans;
+  S.final_max_score = hc.final_cert;
+  S.final_off = hc.final_off;
+  S.status = hc.status == ST_MAXROT ? JE_WARN_MAXROT : (hc.status == ST_STALL ? JE_WARN_STALL : JE_OK);
+
+  // ---- 4. polish, sort, output
+  Timer tf(s);
+  if (V && o.polish_v) {
+    double* X = Vw;
+    double* Xalt = w.X;
+    int r = ns_step(X, Xalt, w.R, n, ld, w.rowsq, w.scal, nullptr, s);
+    if (r) return r;
+    Vw = X;
+  }
+  HIPCHK(launch_sort_output(w.diag, n, Vw, ld, W, V, ldv, w.rank, s));
+  HIPCHK(hipStreamSynchronize(s));
+  S.ms_finalize = tf.stop() + ms_apply;
+  if (st) *st = S;
+  return S.status;
+}
+
+int check_args(const double* A, int n, int lda, const double* W, const double* V, int ldv,
+               double tol, int pivot, int precond, const je_opts& o) {
+  if (!A && n > 0) return -1;
+  if (n < 0) return -2;
+  if (lda < std::max(1, n)) return -3;
+  if (!W && n > 0) return -4;
+  if (V && ldv < std::max(1, n)) return -6;
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    if (!(o.abs_thr > 0.0)) return -7;
+  }
+  if (pivot != JE_PIVOT_GREEDY && pivot != JE_PIVOT_GAP) return -8;
+  if (precond != JE_PRECOND_NONE && precond != JE_PRECOND_FP32) return -9;
+  if (o.stop < JE_STOP_CERT || o.stop > JE_STOP_SCORE) return -10;
+  if (o.fp32_max_sweeps < 0) return -10;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void je_opts_default(je_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->stop = JE_STOP_CERT;
+  o->polish_v = 1;
+  o->fp32_max_sweeps = 20;
+  o->max_rotations = 0;
+  o->abs_thr = 0.0;
+  o->pivot_log = nullptr;
+  o->pivot_log_cap = 0;
+}
+
+int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
+                   int pivot, int precond, const je_opts* opts, je_stats* stats,
+                   je_stream stream) {
+  je_opts o;
+  if (opts) o = *opts;
+  else je_opts_default(&o);
+  int a = check_args(A, n, lda, W, V, ldv, tol, pivot, precond, o);
+  if (a) return a;
+  if (n > JE_MAX_N) return JE_ERR_TOO_LARGE;
+  hipStream_t s = (hipStream_t)stream;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n == 0) return JE_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (n == 1) {
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, A, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!std::isfinite(v)) return JE_ERR_NONFINITE;
+    HIPCHK(hipMemcpyAsync(W, A, 8, hipMemcpyDeviceToDevice, s));
+    if (V) {
+      static const double one = 1.0;
+      HIPCHK(hipMemcpyAsync(V, &one, 8, hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) stats->normF = std::fabs(v);
+    return JE_OK;
+  }
+  return solve_one(A, n, lda, W, V, ldv, tol, pivot, precond, o, stats, s);
+}
+
+int jacobi_eigh(const double* A, int n, int lda, double* W, double* V, double tol, int pivot,
+                int precond) {
+  return jacobi_eigh_ex(A, n, lda, W, V, n, tol, pivot, precond, nullptr, nullptr, nullptr);
+}
+
+int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const int* lda,
+                        double* const* W, double* const* V, const int* ldv, double tol, int pivot,
+                        int precond, const je_opts* opts, int* info, je_stats* stats,
+                        je_stream stream) {
+  if (batch < 0) return -1;
+  if (batch > 0 && (!A || !n || !lda || !W || !info)) return -2;
+  je_opts o;
+  if (opts) o = *opts;
+  else je_opts_default(&o);
+  o.pivot_log = nullptr;
+  int worst = JE_OK;
+  for (int b = 0; b < batch; ++b) {
+    je_stats* sb = stats ? &stats[b] : nullptr;
+    int r = jacobi_eigh_ex(A[b], n[b], lda[b], W[b], V ? V[b] : nullptr, ldv ? ldv[b] : n[b], tol,
+                           pivot, precond, &o, sb, stream);
+    info[b] = r;
+    if (r < 0) return r;
+    worst = std::max(worst, r);  // errors (>= 3) rank above warnings (1, 2)
+  }
+  return worst;
+}
+
+size_t jacobi_workspace_size(int n, int precond) {
+  if (n <= 1) return 0;
+  return ws_bytes(n, precond ? 1 : 0, log_cap_for(n, default_maxrot(n)));
+}
+
+const char* jacobi_strerror(int status) {
+  if (status < 0) return "invalid argument";
+  switch (status) {
+    case JE_OK: return "ok";
+    case JE_WARN_MAXROT: return "rotation cap reached before the stop rule held";
+    case JE_WARN_STALL: return "best remaining pivot is zero before the stop rule held";
+    case JE_ERR_NONFINITE: return "input holds NaN or Inf";
+    case JE_ERR_NOMEM: return "device workspace allocation failed";
+    case JE_ERR_DEVICE: return "HIP runtime error";
+    case JE_ERR_TOO_LARGE: return "n exceeds JE_MAX_N";
+    default: return "unknown status";
+  }
+}
+
+void jacobi_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  (void)hipDeviceSynchronize();
+  for (auto& p : g_pools) {
+    if (p.ptr) (void)hipFree(p.ptr);
+    p.ptr = nullptr;
+    p.bytes = 0;
+  }
+}
+
+}  // extern "C"

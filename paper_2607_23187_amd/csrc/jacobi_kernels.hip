@@ -1,0 +1,754 @@
+// FP64 pivoted Jacobi phase of the preconditioned eigensolver (Algorithm 1 with the
+// greedy or the gap-aware pivot score of eq. (1)), for gfx950.
+//
+// Data layout (one problem):
+//   A      row-major n x ld FP64, full symmetric storage.  A rotation (p, q) rewrites
+//          rows p and q only (two coalesced row stores), never columns p and q.  Each row
+//          carries the rotation number ts[k] that last wrote it; the current value of
+//          entry (k, l) is A[k][l] if ts[k] >= ts[l] and A[l][k] otherwise.  This trades
+//          the 2n scattered column stores of a mirrored update for a per-element choice
+//          of address on load.
+//   diag   the diagonal lives in LDS / registers, never in A.
+//   caches per row k: best selection score over l != k (value, column, a_kl, stale flag)
+//          and, for greedy pivoting with the Theorem 1 stop rule, the best L_kl.  A stale
+//          row keeps an upper bound; it is rescanned only when it would win the argmax
+//          (Sec. 3.2: only O(n) scores change per rotation).
+//   V      is not touched by the Jacobi kernel: every rotation is appended to a log
+//          (p, q, c, s) and applied to the rows of V by a separate, fully parallel kernel.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace je {
+
+// ------------------------------------------------------------------ symmetric copy
+// Au (column-major, lda, upper triangle read) -> A (row-major, ld, full symmetric),
+// diag[k] = a_kk, nonfinite flag.
+constexpr int kTile = 32;
+
+__global__ __launch_bounds__(256) void k_symcopy(const double* __restrict__ Au, int n, int lda,
+                                                 double* __restrict__ A, int ld,
+                                                 double* __restrict__ diag, int* nonfinite) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  __shared__ double t[kTile][kTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int i0 = bi * kTile, j0 = bj * kTile;
+  bool bad = false;
+  for (int r = ty; r < kTile; r += 8) {
+    int i = i0 + tx, j = j0 + r;  // element (i, j) of Au, column-major -> coalesced in i
+    double v = 0.0;
+    if (i < n && j < n && (bi < bj || tx <= r)) {
+      v = Au[(size_t)j * lda + i];
+      if (!isfinite(v)) bad = true;
+    }
+    t[tx][r] = v;  // t[i_local][j_local]
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  __syncthreads();
+  for (int r = ty; r < kTile; r += 8) {
+    // row i0 + r of A, columns j0 + tx  (upper part, or mirrored lower part on diagonal tiles)
+    int i = i0 + r, j = j0 + tx;
+    if (i < n && j < n) {
+      double v = (bi < bj || r <= tx) ? t[r][tx] : t[tx][r];
+      A[(size_t)i * ld + j] = v;
+      if (i == j) diag[i] = v;
+    }
+    if (bi < bj) {  // mirror: row j0 + r, columns i0 + tx
+      int i2 = j0 + r, j2 = i0 + tx;
+      if (i2 < n && j2 < n) A[(size_t)i2 * ld + j2] = t[tx][r];
+    }
+  }
+}
+
+hipError_t launch_symcopy(const double* Au, int n, int lda, double* A, int ld, double* diag,
+                          double* rowsq, int* nonfinite, hipStream_t s) {
+  (void)rowsq;
+  int nb = (n + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_symcopy, dim3(nb, nb), dim3(256), 0, s, Au, n, lda, A, ld, diag,
+                     nonfinite);
+  return hipGetLastError();
+}
+
+__global__ void k_get_diag(const double* __restrict__ A, int n, int ld, double* __restrict__ diag) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) diag[k] = A[(size_t)k * ld + k];
+}
+
+hipError_t launch_get_diag(const double* A, int n, int ld, double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_get_diag, dim3((n + 255) / 256), dim3(256), 0, s, A, n, ld, diag);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ ||A||_F
+// Deterministic: per-row sums in a fixed order, then one block sums the rows in order.
+__global__ __launch_bounds__(256) void k_rowsq(const double* __restrict__ A, int n, int ld,
+                                               double* __restrict__ partial) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int l = lane; l < n; l += 64) {
+    double v = A[(size_t)row * ld + l];
+    s += v * v;
+  }
+  s = wave_sum_d(s);
+  if (lane == 0) partial[row] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ partial, int n,
+                                                  double* out) {
+  __shared__ double w[4];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += partial[k];
+  s = wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = sqrt(((w[0] + w[1]) + w[2]) + w[3]);
+}
+
+hipError_t launch_fro2(const double* A, int n, int ld, double* partial, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_rowsq, dim3((n + 3) / 4), dim3(256), 0, s, A, n, ld, partial);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partial, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normf(const double* rowsq, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, rowsq, n, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ J0: initial row scores
+// One wave per row: the best selection score over l != k (smallest l on ties), the best
+// L_kl (greedy + certificate only) and off2[k] = sum_{l != k} a_kl^2.
+template <bool GAP>
+__global__ __launch_bounds__(256) void k_init_rows(JDesc d, int use_cert) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= d.n) return;
+  const int n = d.n;
+  const double* row = d.A + (size_t)k * d.ld;
+  const double dkk = d.diag[k];
+  double bs = -1.0, bv = 0.0, cb = -1.0, o2 = 0.0;
+  int ba = -1, ca = -1;
+  for (int l = lane; l < n; l += 64) {
+    if (l == k) continue;
+    double a = row[l];
+    double dl = d.diag[l];
+    double s = sel_score<GAP>(dkk, dl, a);
+    if (s > bs) { bs = s; ba = l; bv = a; }
+    if (use_cert) {
+      double L = gap_score(dkk, dl, a);
+      if (L > cb) { cb = L; ca = l; }
+    }
+    o2 += a * a;
+  }
+  int w = wave_argmax_lane(bs, ba < 0 ? 0x7fffffff : ba);
+  double wbs = readlane_d(bs, w), wbv = readlane_d(bv, w);
+  int wba = readlane_i(ba, w);
+  double wcb = -1.0;
+  int wca = -1;
+  if (use_cert) {
+    int w2 = wave_argmax_lane(cb, ca < 0 ? 0x7fffffff : ca);
+    wcb = readlane_d(cb, w2);
+    wca = readlane_i(ca, w2);
+  }
+  o2 = wave_sum_d(o2);
+  if (lane == 0) {
+    d.bs[k] = wbs; d.ba[k] = wba; d.bv[k] = wbv; d.bst[k] = 0;
+    if (use_cert) { d.cb[k] = wcb; d.ca[k] = wca; d.cst[k] = 0; }
+    d.off2[k] = o2;
+    d.ts[k] = 0;
+  }
+}
+
+hipError_t launch_init_rows(const JDesc& d, hipStream_t s) {
+  int use_cert = (d.pivot == 0 && d.stop == STOP_CERT) ? 1 : 0;
+  dim3 g((d.n + 3) / 4), b(256);
+  if (d.pivot == 1) hipLaunchKernelGGL(k_init_rows<true>, g, b, 0, s, d, use_cert);
+  else hipLaunchKernelGGL(k_init_rows<false>, g, b, 0, s, d, use_cert);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ J1..J6: pivoted Jacobi
+// Slot indices of the per-wave partial results exchanged through LDS.
+enum {
+  SL_SEL = 0,   // best cached selection candidate over the wave's rows (rows p, q excluded)
+  SL_RP = 1,    // new row p: best (score, column) -- becomes row p's cache entry
+  SL_RQ = 2,    // new row q
+  SL_CERT = 3,  // best cached certificate value (greedy) over the wave's rows
+  SL_CP = 4,    // new row p, certificate
+  SL_CQ = 5,    // new row q, certificate
+  SL_OFF = 6,   // sum of off2 over the wave's rows (rows p, q excluded)
+  SL_OP = 7,    // sum of squares of the new row p
+  SL_OQ = 8,    // sum of squares of the new row q
+  SL_N = 9
+};
+
+struct Cand {
+  double s;  // score
+  int i;     // row (or column for row-p/q candidates)
+  int c;     // column
+  double a;  // matrix entry at (row, column)
+  int f;     // stale flag
+};
+
+template <int NW>
+struct Slots {
+  double s[2][SL_N][NW];
+  double a[2][SL_N][NW];
+  int i[2][SL_N][NW];
+  int c[2][SL_N][NW];
+  int f[2][SL_N][NW];
+};
+
+// Wave-level argmax of a candidate (score desc, key asc) -> uniform result.
+__device__ __forceinline__ Cand wave_best(const Cand& x, int key) {
+  int w = wave_argmax_lane(x.s, key);
+  Cand r;
+  r.s = readlane_d(x.s, w);
+  r.i = readlane_i(x.i, w);
+  r.c = readlane_i(x.c, w);
+  r.a = readlane_d(x.a, w);
+  r.f = readlane_i(x.f, w);
+  return r;
+}
+
+template <int NW>
+__device__ __forceinline__ void put_slot(Slots<NW>& S, int b, int k, int w, const Cand& x) {
+  S.s[b][k][w] = x.s; S.a[b][k][w] = x.a; S.i[b][k][w] = x.i; S.c[b][k][w] = x.c; S.f[b][k][w] = x.f;
+}
+
+// Cross-wave argmax of slot k; `by_col` selects the tie key (column for row-p/q candidates).
+template <int NW>
+__device__ __forceinline__ Cand reduce_slot(const Slots<NW>& S, int b, int k, bool by_col) {
+  const int lane = lane_id();
+  Cand x{-1.0, 0x7fffffff, 0x7fffffff, 0.0, 0};
+  if (lane < NW) {
+    x.s = S.s[b][k][lane]; x.a = S.a[b][k][lane]; x.i = S.i[b][k][lane];
+    x.c = S.c[b][k][lane]; x.f = S.f[b][k][lane];
+  }
+  int key = by_col ? x.c : x.i;
+  if (x.s < 0.0) key = 0x7fffffff - lane;  // keep keys distinct for empty lanes
+  return wave_best(x, key);
+}
+
+template <int NW>
+__device__ __forceinline__ double reduce_sum_slot(const Slots<NW>& S, int b, int k) {
+  double v = 0.0;
+  // fixed order: wave 0, 1, ... (every wave computes the same sum)
+  for (int w = 0; w < NW; ++w) v += S.s[b][k][w];
+  return v;
+}
+
+__device__ __forceinline__ bool better(double s1, int k1, double s2, int k2) {
+  return s1 > s2 || (s1 == s2 && k1 < k2);
+}
+
+// Refresh of one cached row entry after rotation (p, q) changed its entries at columns
+// p and q to scores sp, sq (matrix values xp, xq).
+__device__ __forceinline__ void refresh_entry(double& bs, int& ba, double& bv, int& bst, int p,
+                                              int q, double sp, double xp, double sq,
+                                              double xq) {
+  double v = sp, a = xp;
+  int col = p;
+  if (sq > v) { v = sq; a = xq; col = q; }
+  if (!bst) {
+    if (ba == p || ba == q) {
+      // the cached maximum itself moved; every other entry is still <= bs
+      if (v > bs || (v == bs && col <= ba)) { bs = v; ba = col; bv = a; }
+      else bst = 1;  // bs stays as an upper bound of the row
+    } else {
+      if (sp > bs || (sp == bs && p < ba)) { bs = sp; ba = p; bv = xp; }
+      if (sq > bs || (sq == bs && q < ba)) { bs = sq; ba = q; bv = xq; }
+    }
+  } else if (v > bs) {
+    // strictly above the bound on every other entry: exact again
+    bs = v; ba = col; bv = a; bst = 0;
+  }
+}
+
+template <int NT, int RM, bool GAP, bool LDSA>
+__global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
+  constexpr int NW = NT / kWave;
+  extern __shared__ double smem[];
+  __shared__ Slots<NW> S;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int n = d.n;
+  const bool use_cert = !GAP && d.stop == STOP_CERT;
+  const bool use_off = d.stop == STOP_OFF;
+
+  double* s_diag = smem;
+  int* s_ts = reinterpret_cast<int*>(s_diag + n);
+  double* s_A = s_diag + n + (n + 1) / 2;  // after the int array, 8-byte aligned
+  const int ldl = n | 1;
+  const int ld = d.ld;
+  double* gA = d.A;
+
+  auto ld_a = [&](int r, int c) -> double {
+    if constexpr (LDSA) return s_A[r * ldl + c];
+    else return gA[(size_t)r * ld + c];
+  };
+  auto st_a = [&](int r, int c, double v) {
+    if constexpr (LDSA) s_A[r * ldl + c] = v;
+    else gA[(size_t)r * ld + c] = v;
+  };
+
+  // ---- per-thread rows k = tid + i * NT
+  double dk[RM], bs[RM], bv[RM], cb[RM], of2[RM];
+  int ba[RM], bst[RM], ca[RM], cst[RM], tk[RM];
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    int k = tid + i * NT;
+    if (k < n) {
+      dk[i] = d.diag[k]; bs[i] = d.bs[k]; ba[i] = d.ba[k]; bv[i] = d.bv[k]; bst[i] = d.bst[k];
+      of2[i] = d.off2[k]; tk[i] = d.ts[k];
+      if (use_cert) { cb[i] = d.cb[k]; ca[i] = d.ca[k]; cst[i] = d.cst[k]; }
+      else { cb[i] = -1.0; ca[i] = -1; cst[i] = 0; }
+      s_diag[k] = dk[i];
+      s_ts[k] = tk[i];
+    } else {
+      dk[i] = 0.0; bs[i] = -1.0; ba[i] = -1; bv[i] = 0.0; bst[i] = 0; of2[i] = 0.0; tk[i] = 0;
+      cb[i] = -1.0; ca[i] = -1; cst[i] = 0;
+    }
+  }
+  if constexpr (LDSA) {
+    for (int idx = tid; idx < n * n; idx += NT) {
+      int r = idx / n, c = idx - r * n;
+      s_A[r * ldl + c] = gA[(size_t)r * ld + c];
+    }
+  }
+  __syncthreads();
+
+  long long rot = d.ctl->rotations;
+  long long rescans = 0;
+  int status = ST_OK, done = 0;
+  double thr = d.thr;
+  // last rotation (its diagonal entries and timestamps reach LDS one iteration later)
+  int lp = -1, lq = -1, lrot = 0;
+  double lapp = 0.0, laqq = 0.0;
+  bool pend = false;
+  // per-thread partials of the new rows p and q (filled by a rotation)
+  Cand rp{-1.0, 0, 0x7fffffff, 0.0, 0}, rq = rp, cp = rp, cq = rp;
+  double op = 0.0, oq = 0.0;
+  Cand W{-1.0, -1, -1, 0.0, 0}, C{-1.0, -1, -1, 0.0, 0};
+  double off_tot = 0.0;
+  int it = 0;
+
+  auto diag_of = [&](int x) -> double { return x == lp ? lapp : (x == lq ? laqq : s_diag[x]); };
+  auto ts_of = [&](int x) -> int { return (x == lp || x == lq) ? lrot : s_ts[x]; };
+
+  // Full rescan of row r's selection (which == 0) or certificate (which == 1) cache.
+  auto rescan = [&](int r, int which) {
+    const int b = it & 1;
+    const double arr = diag_of(r);
+    const int tr = ts_of(r);
+    Cand x{-1.0, r, 0x7fffffff, 0.0, 0};
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      int l = tid + i * NT;
+      if (l >= n || l == r) continue;
+      double v = (tk[i] > tr) ? ld_a(l, r) : ld_a(r, l);
+      double sc = which == 0 ? sel_score<GAP>(arr, dk[i], v) : gap_score(arr, dk[i], v);
+      if (sc > x.s) { x.s = sc; x.c = l; x.a = v; }
+    }
+    Cand wv = wave_best(x, x.c);
+    if (NW > 1) {
+      if (lane == 0) put_slot(S, b, SL_SEL, wid, wv);
+      __syncthreads();
+      wv = reduce_slot(S, b, SL_SEL, true);
+    }
+    ++it;
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      if (tid + i * NT == r) {
+        if (which == 0) { bs[i] = wv.s; ba[i] = wv.c; bv[i] = wv.a; bst[i] = 0; }
+        else { cb[i] = wv.s; ca[i] = wv.c; cst[i] = 0; }
+      }
+    }
+    ++rescans;
+  };
+
+  for (;;) {
+    const int b = it & 1;
+    // ---- per-thread candidates over own rows
+    Cand x1{-1.0, 0x7fffffff, 0, 0.0, 0}, x4{-1.0, 0x7fffffff, 0, 0.0, 0};
+    double o7 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      int k = tid + i * NT;
+      if (k >= n) continue;
+      if (pend && (k == lp || k == lq)) continue;
+      if (bs[i] > x1.s) { x1.s = bs[i]; x1.i = k; x1.c = ba[i]; x1.a = bv[i]; x1.f = bst[i]; }
+      if (use_cert && cb[i] > x4.s) { x4.s = cb[i]; x4.i = k; x4.c = ca[i]; x4.f = cst[i]; }
+      if (use_off) o7 += of2[i];
+    }
+    // ---- wave reductions
+    Cand w1 = wave_best(x1, x1.i), w2 = wave_best(rp, rp.c), w3 = wave_best(rq, rq.c);
+    Cand w4{-1.0, 0x7fffffff, 0, 0.0, 0}, w5 = w4, w6 = w4;
+    if (use_cert) { w4 = wave_best(x4, x4.i); w5 = wave_best(cp, cp.c); w6 = wave_best(cq, cq.c); }
+    double s7 = 0.0, s8 = 0.0, s9 = 0.0;
+    if (use_off) { s7 = wave_sum_d(o7); s8 = wave_sum_d(op); s9 = wave_sum_d(oq); }
+    if (NW > 1) {
+      if (lane == 0) {
+        put_slot(S, b, SL_SEL, wid, w1);
+        put_slot(S, b, SL_RP, wid, w2);
+        put_slot(S, b, SL_RQ, wid, w3);
+        if (use_cert) {
+          put_slot(S, b, SL_CERT, wid, w4);
+          put_slot(S, b, SL_CP, wid, w5);
+          put_slot(S, b, SL_CQ, wid, w6);
+        }
+        if (use_off) { S.s[b][SL_OFF][wid] = s7; S.s[b][SL_OP][wid] = s8; S.s[b][SL_OQ][wid] = s9; }
+      }
+      __syncthreads();
+      w1 = reduce_slot(S, b, SL_SEL, false);
+      w2 = reduce_slot(S, b, SL_RP, true);
+      w3 = reduce_slot(S, b, SL_RQ, true);
+      if (use_cert) {
+        w4 = reduce_slot(S, b, SL_CERT, false);
+        w5 = reduce_slot(S, b, SL_CP, true);
+        w6 = reduce_slot(S, b, SL_CQ, true);
+      }
+      if (use_off) {
+        s7 = reduce_sum_slot(S, b, SL_OFF);
+        s8 = reduce_sum_slot(S, b, SL_OP);
+        s9 = reduce_sum_slot(S, b, SL_OQ);
+      }
+    } else {
+      __syncthreads();
+    }
+    ++it;
+    // ---- fold in the rows of the last rotation
+    W = w1;
+    C = w4;
+    off_tot = s7;
+    if (pend) {
+      if (better(w2.s, lp, W.s, W.i)) W = Cand{w2.s, lp, w2.c, w2.a, 0};
+      if (better(w3.s, lq, W.s, W.i)) W = Cand{w3.s, lq, w3.c, w3.a, 0};
+      if (use_cert) {
+        if (better(w5.s, lp, C.s, C.i)) C = Cand{w5.s, lp, w5.c, 0.0, 0};
+        if (better(w6.s, lq, C.s, C.i)) C = Cand{w6.s, lq, w6.c, 0.0, 0};
+      }
+      off_tot = (s7 + s8) + s9;
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        int k = tid + i * NT;
+        if (k == lp) {
+          bs[i] = w2.s; ba[i] = w2.c; bv[i] = w2.a; bst[i] = 0; of2[i] = s8;
+          if (use_cert) { cb[i] = w5.s; ca[i] = w5.c; cst[i] = 0; }
+        } else if (k == lq) {
+          bs[i] = w3.s; ba[i] = w3.c; bv[i] = w3.a; bst[i] = 0; of2[i] = s9;
+          if (use_cert) { cb[i] = w6.s; ca[i] = w6.c; cst[i] = 0; }
+        }
+      }
+      if (tid == 0) {
+        s_diag[lp] = lapp; s_diag[lq] = laqq;
+        s_ts[lp] = lrot; s_ts[lq] = lrot;
+      }
+      pend = false;
+      rp = Cand{-1.0, 0, 0x7fffffff, 0.0, 0}; rq = rp; cp = rp; cq = rp;
+      op = 0.0; oq = 0.0;
+    }
+    if (n < 2) { done = 1; break; }
+    // ---- the winner must be exact
+    if (W.f) { rescan(W.i, 0); continue; }
+    // ---- stop rules (checked before every rotation)
+    if (d.stop == STOP_CERT) {
+      if (GAP) {
+        if (W.s <= thr) { done = 1; break; }
+      } else {
+        if (C.s <= thr) { done = 1; break; }
+        if (C.f) { rescan(C.i, 1); continue; }
+      }
+    } else if (d.stop == STOP_OFF) {
+      if (sqrt(off_tot) <= thr) { done = 1; break; }
+    } else {
+      if (W.s <= thr) { done = 1; break; }
+    }
+    if (rot >= d.maxrot) { status = ST_MAXROT; done = 1; break; }
+    if (W.a == 0.0) { status = ST_STALL; done = 1; break; }
+    if (rot - log_base >= d.log_cap) break;  // log full: drain and resume
+
+    // ---- rotation (p, q)
+    const int p = min(W.i, W.c), q = max(W.i, W.c);
+    const double apq = W.a;
+    const double app = diag_of(p), aqq = diag_of(q);
+    double t, c, s;
+    rot_params<double>(app, aqq, apq, t, c, s);
+    const double napp = app + t * apq;
+    const double naqq = aqq - t * apq;
+    const int tp = ts_of(p), tq = ts_of(q);
+    const int nts = (int)(rot + 1);
+    double xv[RM], yv[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      int k = tid + i * NT;
+      xv[i] = 0.0; yv[i] = 0.0;
+      if (k >= n || k == p || k == q) continue;
+      xv[i] = (tk[i] > tp) ? ld_a(k, p) : ld_a(p, k);
+      yv[i] = (tk[i] > tq) ? ld_a(k, q) : ld_a(q, k);
+    }
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      int k = tid + i * NT;
+      if (k >= n) continue;
+      if (k == p) {
+        st_a(q, p, 0.0);
+        dk[i] = napp; tk[i] = nts;
+        if (better(0.0, p, rq.s, rq.c)) rq = Cand{0.0, 0, p, 0.0, 0};
+        if (use_cert && better(0.0, p, cq.s, cq.c)) cq = Cand{0.0, 0, p, 0.0, 0};
+        continue;
+      }
+      if (k == q) {
+        st_a(p, q, 0.0);
+        dk[i] = naqq; tk[i] = nts;
+        if (better(0.0, q, rp.s, rp.c)) rp = Cand{0.0, 0, q, 0.0, 0};
+        if (use_cert && better(0.0, q, cp.s, cp.c)) cp = Cand{0.0, 0, q, 0.0, 0};
+        continue;
+      }
+      const double x = xv[i], y = yv[i];
+      const double xn = c * x + s * y;
+      const double yn = c * y - s * x;
+      st_a(p, k, xn);
+      st_a(q, k, yn);
+      const double sp = sel_score<GAP>(dk[i], napp, xn);
+      const double sq = sel_score<GAP>(dk[i], naqq, yn);
+      refresh_entry(bs[i], ba[i], bv[i], bst[i], p, q, sp, xn, sq, yn);
+      if (better(sp, k, rp.s, rp.c)) rp = Cand{sp, 0, k, xn, 0};
+      if (better(sq, k, rq.s, rq.c)) rq = Cand{sq, 0, k, yn, 0};
+      if (use_cert) {
+        const double lpv = gap_score(dk[i], napp, xn);
+        const double lqv = gap_score(dk[i], naqq, yn);
+        double dummy = 0.0;
+        refresh_entry(cb[i], ca[i], dummy, cst[i], p, q, lpv, 0.0, lqv, 0.0);
+        if (better(lpv, k, cp.s, cp.c)) cp = Cand{lpv, 0, k, 0.0, 0};
+        if (better(lqv, k, cq.s, cq.c)) cq = Cand{lqv, 0, k, 0.0, 0};
+      }
+      if (use_off) { op += xn * xn; oq += yn * yn; }
+    }
+    if (tid == 0) d.log[rot - log_base] = RotEntry{p, q, c, s};
+    lp = p; lq = q; lapp = napp; laqq = naqq; lrot = nts;
+    pend = true;
+    ++rot;
+  }
+
+  // ---- write the state back (a later launch may resume from it)
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    int k = tid + i * NT;
+    if (k < n) {
+      d.diag[k] = dk[i]; d.bs[k] = bs[i]; d.ba[k] = ba[i]; d.bv[k] = bv[i]; d.bst[k] = bst[i];
+      d.off2[k] = of2[i]; d.ts[k] = tk[i];
+      if (use_cert) { d.cb[k] = cb[i]; d.ca[k] = ca[i]; d.cst[k] = cst[i]; }
+    }
+  }
+  if constexpr (LDSA) {
+    if (!done) {
+      for (int idx = tid; idx < n * n; idx += NT) {
+        int r = idx / n, c = idx - r * n;
+        gA[(size_t)r * ld + c] = s_A[r * ldl + c];
+      }
+    }
+  }
+  if (tid == 0) {
+    JCtl* ctl = d.ctl;
+    ctl->rotations = rot;
+    ctl->rescans += rescans;
+    ctl->status = status;
+    ctl->done = done;
+    ctl->final_sel = W.s;
+    ctl->final_cert = GAP ? W.s : C.s;
+    ctl->final_off = sqrt(off_tot);
+  }
+}
+
+// LDS budget of the LDS-resident variant (A, diagonal and timestamps).
+static size_t lds_bytes(int n, bool ldsa) {
+  size_t b = (size_t)n * 8 + (size_t)((n + 1) / 2) * 8;
+  if (ldsa) b += (size_t)n * (size_t)(n | 1) * 8;
+  return b;
+}
+
+static int g_max_lds = -1;
+
+static int max_lds() {
+  if (g_max_lds < 0) {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      g_max_lds = v;
+    else
+      g_max_lds = 65536;
+  }
+  return g_max_lds;
+}
+
+bool jacobi_fits_lds(int n) {
+  return n <= 128 && lds_bytes(n, true) + 4096 <= (size_t)max_lds();
+}
+
+template <int NT, int RM, bool GAP, bool LDSA>
+static hipError_t launch_one(const JDesc& d, long long log_base, hipStream_t s) {
+  size_t sh = lds_bytes(d.n, LDSA);
+  auto fn = k_jacobi<NT, RM, GAP, LDSA>;
+  if (sh > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(1), dim3(NT), sh, s, d, log_base);
+  return hipGetLastError();
+}
+
+template <bool GAP>
+static hipError_t launch_jacobi_t(const JDesc& d, long long log_base, bool lds, hipStream_t s) {
+  const int n = d.n;
+  if (lds) {
+    if (n <= 64) return launch_one<64, 1, GAP, true>(d, log_base, s);
+    return launch_one<64, 2, GAP, true>(d, log_base, s);
+  }
+  if (n <= 256) return launch_one<256, 1, GAP, false>(d, log_base, s);
+  if (n <= 1024) return launch_one<256, 4, GAP, false>(d, log_base, s);
+  if (n <= 4096) return launch_one<512, 8, GAP, false>(d, log_base, s);
+  return launch_one<1024, 8, GAP, false>(d, log_base, s);
+}
+
+hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, hipStream_t s) {
+  if (d.pivot == 1) return launch_jacobi_t<true>(d, log_base, lds_mode, s);
+  return launch_jacobi_t<false>(d, log_base, lds_mode, s);
+}
+
+// ------------------------------------------------------------------ J5: apply the log to V
+// Each block holds `R` rows of V in LDS, transposed (column index major) so that lane r
+// touches row r's entries p and q in consecutive banks; the log is read with scalar loads.
+__global__ __launch_bounds__(64) void k_apply_log(double* __restrict__ V, int n, int ldv,
+                                                  const RotEntry* __restrict__ log,
+                                                  long long m, int R) {
+  extern __shared__ double tile[];  // tile[j * R + r]
+  const int r0 = blockIdx.x * R;
+  const int lane = threadIdx.x;
+  const int rows = min(R, n - r0);
+  for (int idx = lane; idx < rows * n; idx += 64) {
+    int r = idx / n, j = idx - r * n;
+    tile[j * R + r] = V[(size_t)(r0 + r) * ldv + j];
+  }
+  __syncthreads();
+  if (lane < rows) {
+    for (long long e = 0; e < m; ++e) {
+      const RotEntry g = log[e];
+      double* xp = tile + g.p * R + lane;
+      double* xq = tile + g.q * R + lane;
+      const double x = *xp, y = *xq;
+      *xp = g.c * x + g.s * y;
+      *xq = g.c * y - g.s * x;
+    }
+  }
+  __syncthreads();
+  for (int idx = lane; idx < rows * n; idx += 64) {
+    int r = idx / n, j = idx - r * n;
+    V[(size_t)(r0 + r) * ldv + j] = tile[j * R + r];
+  }
+}
+
+hipError_t launch_apply_log(double* V, int n, int ldv, const RotEntry* log, long long m,
+                            hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  int R = (int)(65536 / ((size_t)n * 8));
+  if (R > 64) R = 64;
+  if (R < 1) R = 1;
+  size_t sh = (size_t)R * n * 8;
+  if (sh > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_apply_log,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_apply_log, dim3((n + R - 1) / R), dim3(64), sh, s, V, n, ldv, log, m, R);
+  return hipGetLastError();
+}
+
+__global__ void k_set_identity(double* V, int n, int ldv) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
+  V[(size_t)i * ldv + j] = (i == j) ? 1.0 : 0.0;
+}
+
+hipError_t launch_set_identity(double* V, int n, int ldv, hipStream_t s) {
+  size_t tot = (size_t)n * n;
+  hipLaunchKernelGGL(k_set_identity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, n,
+                     ldv);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ J7: sort and output
+// rank[k] = #{l : d_l < d_k} + #{l < k : d_l == d_k}  (ascending, stable)
+__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ diag, int n,
+                                              int* __restrict__ rank, double* __restrict__ W) {
+  extern __shared__ double sd[];
+  for (int l = threadIdx.x; l < n; l += 256) sd[l] = diag[l];
+  __syncthreads();
+  int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  double v = sd[k];
+  int r = 0;
+  for (int l = 0; l < n; ++l) {
+    double u = sd[l];
+    r += (u < v) || (u == v && l < k);
+  }
+  rank[k] = r;
+  W[r] = v;
+}
+
+// Vout[i + rank[k] * ldvo] = Vw[i][k]   (32 x 32 tiles through LDS)
+__global__ __launch_bounds__(256) void k_permute_out(const double* __restrict__ Vw, int n, int ldw,
+                                                     const int* __restrict__ rank,
+                                                     double* __restrict__ Vout, int ldvo) {
+  __shared__ double t[kTile][kTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
+  for (int r = ty; r < kTile; r += 8) {
+    int i = i0 + r, k = k0 + tx;
+    t[r][tx] = (i < n && k < n) ? Vw[(size_t)i * ldw + k] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < kTile; r += 8) {
+    int k = k0 + r, i = i0 + tx;
+    if (i < n && k < n) Vout[(size_t)rank[k] * ldvo + i] = t[tx][r];
+  }
+}
+
+hipError_t launch_sort_output(const double* diag, int n, const double* Vw, int ldw, double* W,
+                              double* Vout, int ldvo, int* rank, hipStream_t s) {
+  size_t sh = (size_t)n * 8;
+  if (sh > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rank,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_rank, dim3((n + 255) / 256), dim3(256), sh, s, diag, n, rank, W);
+  if (Vout) {
+    int nb = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_permute_out, dim3(nb, nb), dim3(256), 0, s, Vw, n, ldw, rank, Vout,
+                       ldvo);
+  }
+  return hipGetLastError();
+}
+
+__global__ void k_copy_pivots(const RotEntry* __restrict__ log, long long m, int* __restrict__ out) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  out[2 * e] = log[e].p;
+  out[2 * e + 1] = log[e].q;
+}
+
+hipError_t launch_copy_pivots(const RotEntry* log, long long m, int* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_pivots, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, log, m,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace je

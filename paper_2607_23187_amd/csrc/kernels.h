@@ -1,0 +1,85 @@
+// Internal interface between the host API (api.hip) and the kernel files.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace je {
+
+enum { STOP_CERT = 0, STOP_OFF = 1, STOP_SCORE = 2 };
+enum { ST_OK = 0, ST_MAXROT = 1, ST_STALL = 2 };
+
+// One entry of the rotation log written by the pivoted Jacobi kernel: the rotation
+// G(c, s, p, q) of Sec. 2 applied at that step.
+struct RotEntry {
+  int p, q;
+  double c, s;
+};
+
+// Control block of one FP64 Jacobi phase (device memory).
+struct JCtl {
+  long long rotations;   // absolute rotation count so far
+  long long rescans;
+  int status;            // ST_*
+  int done;              // 1 once the stop rule, the rotation cap or a stall ended it
+  double final_sel;      // selection score of the best remaining pivot at exit
+  double final_cert;     // certificate value (max L_ij, an upper bound) at exit
+  double final_off;      // off(A) from the per-row sums at exit
+};
+
+// Device state of one FP64 pivoted-Jacobi problem.  A is row-major with leading
+// dimension ld; entry (i, j) is current in row i if ts[i] >= ts[j], else in row j
+// (rows are only ever written whole; see the Jacobi kernel).
+struct JDesc {
+  double* A;
+  int n, ld;
+  double* diag;                 // [n]
+  double* bs; int* ba; double* bv; int* bst;   // per-row selection cache
+  double* cb; int* ca; int* cst;               // per-row certificate (L) cache, greedy only
+  double* off2;                 // [n] sum_{l != k} a_kl^2
+  int* ts;                      // [n] rotation number that last wrote row k (0 = input)
+  RotEntry* log;                // rotation log
+  long long log_cap;
+  JCtl* ctl;
+  double thr;
+  long long maxrot;
+  int pivot, stop;
+};
+
+// Kernel launchers (all asynchronous on `s`).
+hipError_t launch_symcopy(const double* Au, int n, int lda, double* A, int ld, double* diag,
+                          double* rowsq, int* nonfinite, hipStream_t s);
+hipError_t launch_normf(const double* rowsq, int n, double* out, hipStream_t s);
+hipError_t launch_init_rows(const JDesc& d, hipStream_t s);
+hipError_t launch_get_diag(const double* A, int n, int ld, double* diag, hipStream_t s);
+// Runs the pivoted Jacobi until the stop rule holds, the cap is reached or the log is
+// full (then ctl->done stays 0 and the launch can be repeated after the log is drained).
+hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, hipStream_t s);
+bool jacobi_fits_lds(int n);
+// V[i][:] <- V[i][:] * G_1 ... G_m for every row (rotations of `log`, in order).
+hipError_t launch_apply_log(double* V, int n, int ldv, const RotEntry* log, long long m,
+                            hipStream_t s);
+hipError_t launch_set_identity(double* V, int n, int ldv, hipStream_t s);
+hipError_t launch_sort_output(const double* diag, int n, const double* Vw, int ldw, double* W,
+                              double* Vout, int ldvo, int* perm, hipStream_t s);
+hipError_t launch_copy_pivots(const RotEntry* log, long long m, int* out, hipStream_t s);
+
+// FP64 GEMM on MFMA: C = alpha * op(A) * B + beta * Cin (all row-major, square n).
+// op(A) = A if transA == 0 else A^T.  Cin may equal C only if beta == 0 or the tiles
+// of C are only read by their own block (always true here).
+hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int lda,
+                        const double* B, int ldb, double beta, const double* Cin, int ldcin,
+                        double* C, int ldc, hipStream_t s);
+hipError_t launch_add_identity(double* C, int n, int ldc, double scale, hipStream_t s);
+hipError_t launch_symmetrize(double* A, int n, int ld, hipStream_t s);
+hipError_t launch_fro2(const double* A, int n, int ld, double* partial, double* out,
+                       hipStream_t s);
+
+// FP32 preconditioner.
+size_t precond_f32_bytes(int n);
+hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq,
+                           void* scratch, int max_sweeps, int* sweeps, hipStream_t s);
+hipError_t launch_f64_to_f32(const double* A, int n, int lda, float* B, int ldb, hipStream_t s);
+
+}  // namespace je

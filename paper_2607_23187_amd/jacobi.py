@@ -1,0 +1,195 @@
+"""ctypes binding of the C ABI in ``include/jacobi.h`` (argument marshalling only).
+
+Device memory and streams come from torch; every step of the solve runs in the HIP
+library.  There is no fallback: without the built library or without a GPU every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjacobi.so")
+
+GREEDY, GAP = 0, 1
+PRECOND_NONE, PRECOND_FP32 = 0, 1
+STOP_CERT, STOP_OFF, STOP_SCORE = 0, 1, 2
+OK, WARN_MAXROT, WARN_STALL, ERR_NONFINITE, ERR_NOMEM, ERR_DEVICE, ERR_TOO_LARGE = range(7)
+MAX_N = 8192
+
+_PIVOTS = {"greedy": GREEDY, "gap": GAP, GREEDY: GREEDY, GAP: GAP}
+_PRECONDS = {"none": PRECOND_NONE, "fp32": PRECOND_FP32, None: PRECOND_NONE,
+             PRECOND_NONE: PRECOND_NONE, PRECOND_FP32: PRECOND_FP32}
+_STOPS = {"cert": STOP_CERT, "off": STOP_OFF, "score": STOP_SCORE,
+          STOP_CERT: STOP_CERT, STOP_OFF: STOP_OFF, STOP_SCORE: STOP_SCORE}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("stop", ctypes.c_int), ("polish_v", ctypes.c_int),
+                ("fp32_max_sweeps", ctypes.c_int), ("max_rotations", ctypes.c_longlong),
+                ("abs_thr", ctypes.c_double), ("pivot_log", ctypes.c_void_p),
+                ("pivot_log_cap", ctypes.c_longlong)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rotations", ctypes.c_longlong), ("rescans", ctypes.c_longlong),
+                ("final_max_score", ctypes.c_double), ("final_off", ctypes.c_double),
+                ("normF", ctypes.c_double), ("thr", ctypes.c_double),
+                ("sweeps32", ctypes.c_int), ("status", ctypes.c_int),
+                ("ms_precond", ctypes.c_float), ("ms_gemm", ctypes.c_float),
+                ("ms_jacobi", ctypes.c_float), ("ms_finalize", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["je_opts_default", "jacobi_eigh", "jacobi_eigh_ex", "jacobi_eigh_batched",
+           "jacobi_workspace_size", "jacobi_strerror", "jacobi_release"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libjacobi.so and declare the C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2607_23187_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.je_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    L.je_opts_default.restype = None
+    L.jacobi_eigh.argtypes = [vp, ip, ip, vp, vp, dp, ip, ip]
+    L.jacobi_eigh.restype = ctypes.c_int
+    L.jacobi_eigh_ex.argtypes = [vp, ip, ip, vp, vp, ip, dp, ip, ip, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(Stats), vp]
+    L.jacobi_eigh_ex.restype = ctypes.c_int
+    L.jacobi_eigh_batched.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(ip),
+                                      ctypes.POINTER(ip), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(ip), dp, ip, ip, ctypes.POINTER(Opts),
+                                      ctypes.POINTER(ip), ctypes.POINTER(Stats), vp]
+    L.jacobi_eigh_batched.restype = ctypes.c_int
+    L.jacobi_workspace_size.argtypes = [ip, ip]
+    L.jacobi_workspace_size.restype = ctypes.c_size_t
+    L.jacobi_strerror.argtypes = [ip]
+    L.jacobi_strerror.restype = ctypes.c_char_p
+    L.jacobi_release.argtypes = []
+    L.jacobi_release.restype = None
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return load().jacobi_strerror(int(status)).decode()
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    load().je_opts_default(ctypes.byref(o))
+    return o
+
+
+@dataclass
+class Result:
+    w: torch.Tensor                  # (n,) ascending eigenvalues, float64, device
+    v: torch.Tensor | None           # (n, n): v[:, k] is the eigenvector of w[k]
+    status: int
+    stats: dict
+    pivots: torch.Tensor | None      # (rotations, 2) int32 pivot log, 0-based
+
+
+def _check_device_tensor(a: torch.Tensor):
+    if not isinstance(a, torch.Tensor) or not a.is_cuda:
+        raise TypeError("A must be a torch CUDA (HIP) tensor")
+    if a.dtype != torch.float64:
+        raise TypeError("A must be float64")
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("A must be square")
+
+
+def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop="cert",
+         want_v: bool = True, abs_thr: float = 0.0, max_rotations: int = 0,
+         polish_v: bool = True, fp32_max_sweeps: int = 20, pivot_log_cap: int = 0,
+         stream: torch.cuda.Stream | None = None, check: bool = True) -> Result:
+    """Eigen-decomposition of the symmetric float64 CUDA tensor ``a``.
+
+    The library reads the upper triangle of ``a`` in column-major terms (``a[j, i]`` for
+    i <= j of the row-major tensor); for a symmetric tensor this is the whole matrix.
+    """
+    _check_device_tensor(a)
+    L = load()
+    n = a.shape[0]
+    a = a.contiguous()
+    w = torch.empty(n, dtype=torch.float64, device=a.device)
+    vt = torch.empty((n, n), dtype=torch.float64, device=a.device) if want_v else None
+    o = default_opts()
+    o.stop = _STOPS[stop]
+    o.polish_v = 1 if polish_v else 0
+    o.fp32_max_sweeps = int(fp32_max_sweeps)
+    o.max_rotations = int(max_rotations)
+    o.abs_thr = float(abs_thr)
+    plog = None
+    if pivot_log_cap > 0:
+        plog = torch.full((pivot_log_cap, 2), -1, dtype=torch.int32, device=a.device)
+        o.pivot_log = plog.data_ptr()
+        o.pivot_log_cap = int(pivot_log_cap)
+    st = Stats()
+    s = stream if stream is not None else torch.cuda.current_stream(a.device)
+    with torch.cuda.device(a.device):
+        status = L.jacobi_eigh_ex(a.data_ptr(), n, max(1, n), w.data_ptr(),
+                                  vt.data_ptr() if vt is not None else None, max(1, n), float(tol),
+                                  _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o),
+                                  ctypes.byref(st), ctypes.c_void_p(s.cuda_stream))
+    if check and (status < 0 or status >= ERR_NONFINITE):
+        raise RuntimeError(f"jacobi_eigh_ex failed: {status} ({strerror(status)})")
+    if plog is not None:
+        plog = plog[: min(st.rotations, pivot_log_cap)]
+    return Result(w, vt.t() if vt is not None else None, status, st.as_dict(), plog)
+
+
+def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", precond="fp32",
+                 stop="cert", want_v: bool = True, max_rotations: int = 0,
+                 stream: torch.cuda.Stream | None = None):
+    """Batch of independent problems of possibly different sizes."""
+    L = load()
+    b = len(mats)
+    for m in mats:
+        _check_device_tensor(m)
+    mats = [m.contiguous() for m in mats]
+    ws = [torch.empty(m.shape[0], dtype=torch.float64, device=m.device) for m in mats]
+    vs = [torch.empty_like(m) for m in mats] if want_v else None
+    VP = ctypes.c_void_p * b
+    IA = ctypes.c_int * b
+    a_p = VP(*[m.data_ptr() for m in mats])
+    w_p = VP(*[x.data_ptr() for x in ws])
+    v_p = VP(*[x.data_ptr() for x in vs]) if vs is not None else None
+    ns = IA(*[m.shape[0] for m in mats])
+    info = IA()
+    stats = (Stats * b)()
+    o = default_opts()
+    o.stop = _STOPS[stop]
+    o.max_rotations = int(max_rotations)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    status = L.jacobi_eigh_batched(b, a_p, ns, ns, w_p, v_p, ns, float(tol), _PIVOTS[pivot],
+                                   _PRECONDS[precond], ctypes.byref(o), info, stats,
+                                   ctypes.c_void_p(s.cuda_stream))
+    if status < 0:
+        raise RuntimeError(f"jacobi_eigh_batched: argument {-status} invalid")
+    out = []
+    for i in range(b):
+        out.append(Result(ws[i], vs[i].t() if vs is not None else None, int(info[i]),
+                          stats[i].as_dict(), None))
+    return status, out
+
+
+def workspace_size(n: int, precond="fp32") -> int:
+    return int(load().jacobi_workspace_size(int(n), _PRECONDS[precond]))
+
+
+def release():
+    load().jacobi_release()

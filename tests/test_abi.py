@@ -1,0 +1,70 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/jacobi.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2607_23187_amd import jacobi as J
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jacobi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_header_declares_the_expected_entry_points():
+    assert declared_functions() == sorted(J.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = J.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_defaults_and_strings():
+    o = J.default_opts()
+    assert (o.stop, o.polish_v, o.fp32_max_sweeps, o.max_rotations, o.abs_thr) == (0, 1, 20, 0, 0.0)
+    assert J.strerror(0) == "ok"
+    assert "NaN" in J.strerror(J.ERR_NONFINITE)
+    assert J.strerror(-3) == "invalid argument"
+    assert J.workspace_size(0) == 0 and J.workspace_size(1) == 0
+    assert J.workspace_size(1024, "fp32") > J.workspace_size(1024, "none") > 8 * 1024 * 1024
+
+
+def _ex(A, n, lda, W, V, ldv, tol, pivot=1, precond=1, opts=None):
+    L = J.load()
+    return L.jacobi_eigh_ex(A, n, lda, W, V, ldv, tol, pivot, precond,
+                            ctypes.byref(opts) if opts is not None else None, None, None)
+
+
+def test_argument_errors_follow_lapack_info_convention():
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert _ex(None, 4, 4, fake, None, 4, 1e-12) == -1
+    assert _ex(fake, -1, 4, fake, None, 4, 1e-12) == -2
+    assert _ex(fake, 4, 3, fake, None, 4, 1e-12) == -3
+    assert _ex(fake, 4, 4, None, None, 4, 1e-12) == -4
+    assert _ex(fake, 4, 4, fake, fake, 2, 1e-12) == -6
+    assert _ex(fake, 4, 4, fake, None, 4, 0.0) == -7
+    assert _ex(fake, 4, 4, fake, None, 4, float("nan")) == -7
+    assert _ex(fake, 4, 4, fake, None, 4, 1e-12, pivot=7) == -8
+    assert _ex(fake, 4, 4, fake, None, 4, 1e-12, precond=5) == -9
+    o = J.default_opts()
+    o.stop = 9
+    assert _ex(fake, 4, 4, fake, None, 4, 1e-12, opts=o) == -10
+    # n = 0 is a no-op that needs no device
+    assert _ex(fake, 0, 1, fake, None, 1, 1e-12) == 0
+    # too large
+    assert _ex(fake, J.MAX_N + 1, J.MAX_N + 1, fake, None, J.MAX_N + 1, 1e-12) == J.ERR_TOO_LARGE
+    L = J.load()
+    IA = ctypes.c_int * 1
+    assert L.jacobi_eigh_batched(-1, None, None, None, None, None, None, 1e-12, 1, 1, None,
+                                 None, None, None) == -1

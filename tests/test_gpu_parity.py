@@ -1,0 +1,207 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+* FP64 pivoted Jacobi on the same input bytes (precond='none'): identical pivot
+  sequence, identical rotation count and bit-identical eigenvalues -- both sides use the
+  same IEEE operations in the same order, so nothing is left to rounding.
+* Whole preconditioned solves: eigenvalues within 10 n u ||A||_2 of the oracle's and of
+  the known spectrum, ||V^T V - I||_F <= 10 n u.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_23187_amd import inputs as I
+from paper_2607_23187_amd import jacobi as J
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cert_thr(a, lam_max, n):
+    """Theorem 1 threshold for tau = 10 n u ||A||_2, computed on the host."""
+    return 10 * n * U * lam_max / (2.0 * n * (n - 1))
+
+
+def oracle_a_hat(p):
+    """A_hat = Q^T A Q formed by the oracle's own preconditioner (FP32 Jacobi + QR)."""
+    n = p.a.shape[0]
+    e = O.eigh(p.a, tol=1.0, pivot=O.GAP, precond="fp32", stop=O.STOP_SCORE, maxrot=0,
+               want_v=False)
+    return e.a_hat
+
+
+def test_gpu_present():
+    assert torch.cuda.is_available()
+    J.load()
+
+
+def test_worked_example_on_gpu():
+    a = I.worked_example().a
+    for pivot, first, count in ((J.GREEDY, (0, 1), 2), (J.GAP, (2, 3), 1)):
+        say("worked example", pivot)
+        r = J.eigh(gpu(a), precond="none", pivot=pivot, stop="cert", abs_thr=1e-15,
+                   pivot_log_cap=16)
+        assert r.status == J.OK
+        assert r.stats["rotations"] == count
+        assert tuple(r.pivots[0].tolist()) == first
+        ref = O.jacobi(a, pivot=pivot, stop=O.STOP_CERT, thr=1e-15, scan=1)
+        assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a)))
+
+
+def _parity_case(a, pivot, stop, thr, capmul=40):
+    n = a.shape[0]
+    cap = capmul * n * n + 64
+    r = J.eigh(gpu(a), precond="none", pivot=pivot, stop=stop, abs_thr=thr,
+               pivot_log_cap=cap, polish_v=True)
+    so = {"cert": O.STOP_CERT, "off": O.STOP_OFF, "score": O.STOP_SCORE}[stop]
+    ref = O.jacobi(a, pivot=pivot, stop=so, thr=thr, scan=1, want_vj=False)
+    return r, ref
+
+
+SIZES = [2, 3, 5, 17, 40, 64, 100, 128, 129, 200, 300]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("pivot", [J.GREEDY, J.GAP])
+def test_pivot_sequence_identical_dense(n, pivot):
+    """Plain Jacobi from a dense clustered matrix: every kernel variant (LDS-resident
+    single wave, HBM-resident 256/512 threads, ragged row counts)."""
+    say("dense parity", n, pivot)
+    p = I.clustered(n, seed=2000 + n, size=4, offset=1e-9) if n >= 4 else None
+    a = p.a if p else I.random_symmetric(n, seed=n)
+    lam = np.linalg.eigvalsh(a)
+    thr = cert_thr(a, np.max(np.abs(lam)), n)
+    r, ref = _parity_case(a, pivot, "cert", thr)
+    assert r.status == J.OK
+    assert r.stats["rotations"] == ref.rotations
+    assert np.array_equal(r.pivots.cpu().numpy(), ref.pivots)
+    w = r.w.cpu().numpy()
+    assert np.array_equal(w, np.sort(np.diag(ref.a)))
+    assert np.max(np.abs(w - lam)) <= 10 * n * U * np.max(np.abs(lam))
+    v = r.v.cpu().numpy()
+    assert np.linalg.norm(v.T @ v - np.eye(n)) <= 10 * n * U
+
+
+@pytest.mark.parametrize("n", [64, 200, 520])
+@pytest.mark.parametrize("pivot", [J.GREEDY, J.GAP])
+def test_pivot_sequence_identical_preconditioned(n, pivot):
+    """The hot path proper: FP64 Jacobi on an oracle-formed preconditioned matrix."""
+    say("preconditioned parity", n, pivot)
+    p = I.clustered(n, seed=3000 + n, size=8, offset=1e-10)
+    ah = oracle_a_hat(p)
+    thr = cert_thr(ah, np.max(np.abs(p.lam)), n)
+    r, ref = _parity_case(ah, pivot, "cert", thr)
+    assert r.status == J.OK
+    assert r.stats["rotations"] == ref.rotations
+    assert np.array_equal(r.pivots.cpu().numpy(), ref.pivots)
+    assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a)))
+
+
+@pytest.mark.parametrize("n", [64, 150])
+def test_off_stop_rule(n):
+    """off(A) <= tol ||A||_F: the per-row sums are added in a different order on the two
+    sides, so the stop may differ by a rotation; the pivots agree up to there."""
+    say("off stop", n)
+    p = I.clustered(n, seed=4000 + n)
+    ah = oracle_a_hat(p)
+    thr = 1e-15 * np.linalg.norm(ah)
+    for pivot in (J.GREEDY, J.GAP):
+        r, ref = _parity_case(ah, pivot, "off", thr)
+        assert r.status == J.OK
+        m = min(r.stats["rotations"], ref.rotations)
+        assert abs(r.stats["rotations"] - ref.rotations) <= max(1, 0.01 * ref.rotations)
+        assert np.array_equal(r.pivots.cpu().numpy()[:m], ref.pivots[:m])
+        assert r.stats["final_off"] <= thr * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("n,seed", [(64, I.SEED_C1), (256, 11), (400, 12)])
+@pytest.mark.parametrize("pivot", ["greedy", "gap"])
+def test_full_pipeline_against_oracle(n, seed, pivot):
+    say("pipeline", n, pivot)
+    p = I.clustered(n, seed=seed)
+    lam2 = np.max(np.abs(p.lam))
+    tol = 10 * n * U * lam2 / np.linalg.norm(p.a)
+    r = J.eigh(gpu(p.a), tol=tol, pivot=pivot, precond="fp32", stop="cert")
+    assert r.status == J.OK
+    w = r.w.cpu().numpy()
+    v = r.v.cpu().numpy()
+    ref = O.eigh(p.a, tol=tol, pivot=O.GAP if pivot == "gap" else O.GREEDY, precond="fp32")
+    bound = 10 * n * U * lam2
+    assert np.max(np.abs(w - p.lam)) <= bound
+    assert np.max(np.abs(w - ref.w)) <= bound
+    assert np.linalg.norm(v.T @ v - np.eye(n)) <= 10 * n * U
+    # eigenvector residual is bounded by what the certificate leaves off the diagonal
+    res = np.linalg.norm(p.a @ v - v * w[None, :]) / np.linalg.norm(p.a)
+    assert res <= 1e-6
+    # the preconditioner leaves few rotations (gap: well under n^2)
+    assert r.stats["rotations"] < 2 * n * n
+    assert r.stats["sweeps32"] >= 1
+
+
+def test_c2_spectrum_pipeline():
+    """Half clustered (relative spread 1e-8), half log-uniform over six decades."""
+    n = 512
+    p = I.config_c2(n=n)
+    lam2 = np.max(np.abs(p.lam))
+    tol = 10 * n * U * lam2 / np.linalg.norm(p.a)
+    say("c2 pipeline", n)
+    for pivot in ("gap", "greedy"):
+        r = J.eigh(gpu(p.a), tol=tol, pivot=pivot, precond="fp32")
+        w = r.w.cpu().numpy()
+        v = r.v.cpu().numpy()
+        assert r.status == J.OK
+        assert np.max(np.abs(w - p.lam)) <= 10 * n * U * lam2
+        assert np.linalg.norm(v.T @ v - np.eye(n)) <= 10 * n * U
+
+
+def test_degenerate_and_error_cases():
+    say("edge cases")
+    r = J.eigh(torch.zeros((0, 0), dtype=torch.float64, device="cuda"))
+    assert r.status == 0 and r.w.numel() == 0
+    r = J.eigh(gpu(np.array([[2.5]])))
+    assert r.w.tolist() == [2.5] and r.v.tolist() == [[1.0]]
+    d = np.diag([3.0, 1.0, 2.0, 1.0])
+    r = J.eigh(gpu(d), precond="none")
+    assert r.w.tolist() == [1.0, 1.0, 2.0, 3.0] and r.stats["rotations"] == 0
+    assert np.array_equal(np.abs(r.v.cpu().numpy()), np.eye(4)[:, [1, 3, 2, 0]])
+    a = I.random_symmetric(20, seed=5)
+    # the library reads element (i, j), i <= j, of the column-major matrix, which is
+    # t[j, i] of a row-major tensor t: its lower triangle
+    bad = a.copy()
+    bad[7, 3] = np.nan
+    r = J.eigh(gpu(bad), check=False)
+    assert r.status == J.ERR_NONFINITE
+    unread = a.copy()
+    unread[3, 7] = np.inf
+    r = J.eigh(gpu(unread), check=False, precond="none")
+    assert r.status == J.OK
+    assert torch.equal(r.w, J.eigh(gpu(a), precond="none").w)
+    r = J.eigh(gpu(a), precond="none", max_rotations=5, check=False)
+    assert r.status == J.WARN_MAXROT and r.stats["rotations"] == 5
+    v = r.v.cpu().numpy()
+    assert np.linalg.norm(v.T @ v - np.eye(20)) <= 10 * 20 * U
+    # the partial result is the oracle's partial result
+    ref = O.jacobi(a, pivot=O.GAP, stop=O.STOP_CERT, thr=0.0, maxrot=5, scan=1)
+    assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a)))
+
+
+def test_repeatable_bitwise():
+    say("repeatable")
+    p = I.clustered(300, seed=77)
+    tol = 1e-12
+    r1 = J.eigh(gpu(p.a), tol=tol)
+    r2 = J.eigh(gpu(p.a), tol=tol)
+    assert torch.equal(r1.w, r2.w) and torch.equal(r1.v, r2.v)
+    assert r1.stats["rotations"] == r2.stats["rotations"]
