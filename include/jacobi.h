@@ -16,7 +16,10 @@
  * Preconditioner (Sec. 2.1): with JE_PRECOND_FP32 the library first computes an FP32
  * spectral decomposition by a parallel cyclic Jacobi in FP32, re-orthogonalises its
  * eigenvector matrix in FP64 by Newton-Schulz, and runs the FP64 pivoted Jacobi on
- * Q^T A Q, whose off-diagonal entries are O(||A|| u_32).
+ * Q^T A Q, whose off-diagonal entries are O(||A|| u_32).  By default the FP32
+ * decomposition is refined once (fp32_passes = 2): the FP32 Jacobi runs again on
+ * fl32(Q^T A Q) and Q <- Q V_2, re-orthogonalised; fp32_passes = 1 is the single FP32
+ * decomposition.
  *
  * Stop rule (default, Theorem 1): stop once max_{i != j} L_ij <= eps with
  *   eps = tol * ||A||_F / (2 n (n - 1)),
@@ -84,7 +87,8 @@ enum je_status {
 typedef struct je_opts {
   int stop;                  /* enum je_stop                              (JE_STOP_CERT) */
   int polish_v;              /* 1: one FP64 Newton-Schulz step on V             (1)   */
-  int fp32_max_sweeps;       /* sweeps cap of the FP32 preconditioner          (20)   */
+  int fp32_max_sweeps;       /* sweeps cap of each FP32 preconditioner pass     (20)   */
+  int fp32_passes;           /* FP32 decompositions (1 or 2)                    (2)    */
   long long max_rotations;   /* <= 0: 40 n^2 + 64                              (0)    */
   double abs_thr;            /* > 0: absolute threshold of the stop rule,             */
                              /*      overriding the one derived from tol         (0)  */
@@ -101,12 +105,14 @@ typedef struct je_stats {
   double final_off;          /* off(A) of the final iterate                         */
   double normF;              /* ||A||_F of the input                                */
   double thr;                /* absolute stop threshold used                        */
-  int sweeps32;              /* FP32 preconditioner sweeps                          */
+  int sweeps32;              /* FP32 preconditioner sweeps (all passes)             */
   int status;
   float ms_precond;          /* FP32 Jacobi + re-orthogonalisation                  */
   float ms_gemm;             /* Q^T A Q contraction                                 */
   float ms_jacobi;           /* FP64 pivoted Jacobi (initial scores + rotations)    */
   float ms_finalize;         /* eigenvectors, polish, sort                          */
+  float ms_jacobi_kernel;    /* the persistent Jacobi kernel launches alone (HIP    */
+                             /* events on `stream` around each launch)             */
 } je_stats;
 
 void je_opts_default(je_opts* opts);

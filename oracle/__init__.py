@@ -9,7 +9,9 @@ Pipeline (Shao & Nakatsukasa, Sec. 2.1 and Algorithm 1):
 1. read the upper triangle of A and mirror it (Algorithm 1 input: a symmetric matrix);
 2. ``precond='fp32'``: cyclic FP32 Jacobi -> V_l (Sec. 2.1, low-precision spectral
    decomposition), re-orthogonalised in FP64 by Householder QR with diag(R) > 0 (the
-   experiments of Sec. 4 use Householder QR), then A_hat = Q^T (A Q), symmetrised;
+   experiments of Sec. 4 use Householder QR).  With ``passes=2`` (default) the FP32
+   decomposition is refined once: FP32 Jacobi again on fl32(Q^T A Q), Q <- QR(Q V_2).
+   Then A_hat = Q^T (A Q), symmetrised;
 3. FP64 Jacobi on A_hat with greedy or gap-aware pivots (eq. (1)) until the chosen stop
    rule holds (Theorem 1 certificate by default);
 4. V = Q V_J, optionally polished by one Newton-Schulz step; eigenvalues =
@@ -190,7 +192,7 @@ def threshold(stop: int, tol: float, n: int, normF: float) -> float:
 def eigh(a: np.ndarray, tol: float, pivot: int = GAP, precond: str = "fp32",
          stop: int = STOP_CERT, abs_thr: float | None = None, want_v: bool = True,
          maxrot: int | None = None, scan: int = 1, sweeps32: int = 20,
-         polish_v: bool = True) -> EighResult:
+         polish_v: bool = True, passes: int = 2) -> EighResult:
     """Whole preconditioned solve: returns ascending eigenvalues and eigenvectors."""
     a = symmetric_from_upper(a)
     n = a.shape[0]
@@ -204,6 +206,12 @@ def eigh(a: np.ndarray, tol: float, pivot: int = GAP, precond: str = "fp32",
     if precond == "fp32" and n > 1:
         _, v32, sw = jacobi_f32(a, max_sweeps=sweeps32)
         q = householder_q(v32.astype(np.float64))
+        for _ in range(passes - 1):
+            a1 = q.T @ (a @ q)
+            a1 = 0.5 * (a1 + a1.T)
+            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32)
+            sw += sw2
+            q = householder_q(q @ v2.astype(np.float64))
         a_hat = q.T @ (a @ q)
         a_hat = 0.5 * (a_hat + a_hat.T)
     else:

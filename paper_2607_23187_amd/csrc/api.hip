@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -61,6 +63,7 @@ struct WS {
   double *Asym, *A, *Q, *X, *T, *R, *Vw;
   double *diag, *bs, *bv, *cb, *off2, *rowsq, *scal;
   int *ba, *bst, *ca, *cst, *ts, *rank, *flag;
+  long long* prof;
   JCtl* ctl;
   RotEntry* log;
   void* f32;
@@ -79,6 +82,7 @@ size_t ws_bytes(int n, int precond, long long log_cap) {
   b += al(64);                    // scalars
   b += 7 * al((size_t)n * 4);     // ba bst ca cst ts rank flag
   b += al(sizeof(JCtl));
+  b += al(64);                    // phase timers
   b += al((size_t)log_cap * sizeof(RotEntry));
   if (precond) b += al(precond_f32_bytes(n));
   return b;
@@ -120,6 +124,7 @@ WS ws_carve(void* base, int n, int precond, long long log_cap) {
   w.rank = (int*)take((size_t)n * 4);
   w.flag = (int*)take((size_t)n * 4);
   w.ctl = (JCtl*)take(sizeof(JCtl));
+  w.prof = (long long*)take(64);
   w.log = (RotEntry*)take((size_t)log_cap * sizeof(RotEntry));
   w.f32 = precond ? take(precond_f32_bytes(n)) : nullptr;
   w.log_cap = log_cap;
@@ -170,6 +175,20 @@ int ns_step(double*& X, double*& Xalt, double* R, int n, int ld, double* part, d
   return JE_OK;
 }
 
+// Newton-Schulz steps on X until ||I - X^T X||_F <= 4 n u (at most 6); X may be swapped
+// with Xalt.
+int orthonormalize(double*& X, double*& Xalt, double* R, int n, int ld, double* part,
+                   double* scal, hipStream_t s) {
+  for (int itn = 0; itn < 6; ++itn) {
+    double rn = 0.0;
+    int r = ns_step(X, Xalt, R, n, ld, part, scal, &rn, s);
+    if (r) return r;
+    HIPCHK(hipStreamSynchronize(s));
+    if (rn <= 4.0 * n * 0x1p-53) break;
+  }
+  return JE_OK;
+}
+
 int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, double tol,
               int pivot, int precond, const je_opts& o, je_stats* st, hipStream_t s) {
   const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
@@ -203,22 +222,30 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   double* Ajac = w.Asym;
   double* Vw = w.Vw;
   if (precond) {
-    int sweeps = 0;
-    HIPCHK(run_precond_f32(w.Asym, n, ld, w.Q, ld, w.f32, o.fp32_max_sweeps, &sweeps, s));
-    S.sweeps32 = sweeps;
-    // Newton-Schulz until ||I - Q^T Q||_F <= 4 n u (at most 6 steps)
+    int sweeps = 0, sw = 0;
+    // pass 1: FP32 decomposition of fl32(A) -> B1, Newton-Schulz -> X
     double* X = w.Q;
-    double* Xalt = w.X;
-    for (int itn = 0; itn < 6; ++itn) {
-      double rn = 0.0;
-      int r = ns_step(X, Xalt, w.R, n, ld, w.rowsq, w.scal, &rn, s);
+    double* Xo = w.X;
+    HIPCHK(run_precond_f32(w.Asym, n, ld, X, ld, w.f32, o.fp32_max_sweeps, &sw, s));
+    sweeps += sw;
+    int r = orthonormalize(X, Xo, w.R, n, ld, w.rowsq, w.scal, s);
+    if (r) return r;
+    for (int pass = 1; pass < o.fp32_passes; ++pass) {
+      // pass 2: FP32 decomposition of fl32(X^T A X) -> V2 (in T), X <- X V2
+      HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
+      HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
+      HIPCHK(launch_symmetrize(w.A, n, ld, s));
+      HIPCHK(run_precond_f32(w.A, n, ld, w.T, ld, w.f32, o.fp32_max_sweeps, &sw, s));
+      sweeps += sw;
+      HIPCHK(launch_dgemm(n, 0, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, Xo, ld, s));
+      std::swap(X, Xo);
+      r = orthonormalize(X, Xo, w.R, n, ld, w.rowsq, w.scal, s);
       if (r) return r;
-      HIPCHK(hipStreamSynchronize(s));
-      if (rn <= 4.0 * n * 0x1p-53) break;
     }
+    S.sweeps32 = sweeps;
     S.ms_precond = tp.stop();
     Timer tg(s);
-    // A_hat = Q^T (A Q): T = A Q, A_hat = Q^T T, then exact symmetry
+    // A_hat = X^T (A X): T = A X, A_hat = X^T T, then exact symmetry
     HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
     HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
     HIPCHK(launch_symmetrize(w.A, n, ld, s));
@@ -240,13 +267,22 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   d.thr = thr; d.maxrot = maxrot; d.pivot = pivot; d.stop = o.stop;
   if (precond) HIPCHK(launch_get_diag(Ajac, n, ld, w.diag, s));
   HIPCHK(hipMemsetAsync(w.ctl, 0, sizeof(JCtl), s));
+  // JE_PROFILE=1: per-phase timers of the Jacobi kernel, printed to stderr per solve
+  static const bool profile = std::getenv("JE_PROFILE") != nullptr;
+  if (profile) {
+    HIPCHK(hipMemsetAsync(w.prof, 0, 64, s));
+    d.prof = w.prof;
+  }
   HIPCHK(launch_init_rows(d, s));
   const bool lds = jacobi_fits_lds(n);
   long long base_rot = 0;
   JCtl hc{};
   float ms_apply = 0.f;
+  float ms_kernel = 0.f;
   for (;;) {
+    Timer tk(s);
     HIPCHK(launch_jacobi(d, base_rot, lds, s));
+    ms_kernel += tk.stop();
     HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(JCtl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     long long m = hc.rotations - base_rot;
@@ -261,6 +297,19 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
     if (hc.done) break;
   }
   S.ms_jacobi = tj.stop() - ms_apply;
+  if (profile) {
+    long long pr[8];
+    HIPCHK(hipMemcpy(pr, w.prof, 64, hipMemcpyDeviceToHost));
+    double r = (double)std::max<long long>(1, hc.rotations);
+    std::fprintf(stderr,
+                 "JE_PROFILE n=%d rot=%lld rescans=%lld ns/rot: wave %.0f barrier %.0f cross %.0f "
+                 "rescan %.0f params %.0f rotate %.0f total %.0f  shader-clock %.0f MHz\n",
+                 n, hc.rotations, hc.rescans, pr[0] * 10 / r, pr[1] * 10 / r, pr[2] * 10 / r,
+                 pr[3] * 10 / r, pr[4] * 10 / r, pr[5] * 10 / r,
+                 (pr[0] + pr[1] + pr[2] + pr[3] + pr[4] + pr[5]) * 10 / r,
+                 pr[7] > 0 ? (double)pr[6] / (pr[7] * 10.0) * 1000.0 : 0.0);
+  }
+  S.ms_jacobi_kernel = ms_kernel;
   S.rotations = hc.rotations;
   S.rescans = hc.rescans;
   S.final_max_score = hc.final_cert;
@@ -296,7 +345,7 @@ int check_args(const double* A, int n, int lda, const double* W, const double* V
   if (pivot != JE_PIVOT_GREEDY && pivot != JE_PIVOT_GAP) return -8;
   if (precond != JE_PRECOND_NONE && precond != JE_PRECOND_FP32) return -9;
   if (o.stop < JE_STOP_CERT || o.stop > JE_STOP_SCORE) return -10;
-  if (o.fp32_max_sweeps < 0) return -10;
+  if (o.fp32_max_sweeps < 0 || o.fp32_passes < 1 || o.fp32_passes > 2) return -10;
   return 0;
 }
 
@@ -310,6 +359,7 @@ void je_opts_default(je_opts* o) {
   o->stop = JE_STOP_CERT;
   o->polish_v = 1;
   o->fp32_max_sweeps = 20;
+  o->fp32_passes = 2;
   o->max_rotations = 0;
   o->abs_thr = 0.0;
   o->pivot_log = nullptr;

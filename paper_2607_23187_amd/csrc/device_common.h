@@ -102,10 +102,34 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// DPP move of a double (two 32-bit halves) within rows of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave-uniform maximum: butterfly inside each row of 16 lanes on the DPP network
+// (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror), then the
+// four row results through v_readlane.
+__device__ __forceinline__ double wave_max_fast(double m) {
+  m = fmax(m, dpp_d<0xB1>(m));
+  m = fmax(m, dpp_d<0x4E>(m));
+  m = fmax(m, dpp_d<0x141>(m));
+  m = fmax(m, dpp_d<0x140>(m));
+  double r0 = readlane_d(m, 0), r1 = readlane_d(m, 16), r2 = readlane_d(m, 32),
+         r3 = readlane_d(m, 48);
+  return fmax(fmax(r0, r1), fmax(r2, r3));
+}
+
 // Lane holding the largest score, the smallest key among equal scores.  Keys of lanes
-// are distinct.  The result is wave-uniform.  Lanes with nothing to offer pass -1.
+// holding a candidate are distinct; lanes with nothing to offer pass a negative score.
+// The result is wave-uniform; -1 when no lane has a candidate.
 __device__ __forceinline__ int wave_argmax_lane(double score, int key) {
-  double m = wave_max_d(score);
+  double m = wave_max_fast(score);
+  if (m < 0.0) return -1;
   unsigned long long b = __ballot(score == m);
   if (__popcll(b) == 1) return __ffsll((long long)b) - 1;
   int k = wave_min_i(score == m ? key : 0x7fffffff);

@@ -16,6 +16,7 @@
 //   V      is not touched by the Jacobi kernel: every rotation is appended to a log
 //          (p, q, c, s) and applied to the rows of V by a separate, fully parallel kernel.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -146,14 +147,14 @@ __global__ __launch_bounds__(256) void k_init_rows(JDesc d, int use_cert) {
     o2 += a * a;
   }
   int w = wave_argmax_lane(bs, ba < 0 ? 0x7fffffff : ba);
-  double wbs = readlane_d(bs, w), wbv = readlane_d(bv, w);
-  int wba = readlane_i(ba, w);
+  double wbs = -1.0, wbv = 0.0;
+  int wba = -1;
+  if (w >= 0) { wbs = readlane_d(bs, w); wbv = readlane_d(bv, w); wba = readlane_i(ba, w); }
   double wcb = -1.0;
   int wca = -1;
   if (use_cert) {
     int w2 = wave_argmax_lane(cb, ca < 0 ? 0x7fffffff : ca);
-    wcb = readlane_d(cb, w2);
-    wca = readlane_i(ca, w2);
+    if (w2 >= 0) { wcb = readlane_d(cb, w2); wca = readlane_i(ca, w2); }
   }
   o2 = wave_sum_d(o2);
   if (lane == 0) {
@@ -181,65 +182,59 @@ enum {
   SL_CERT = 3,  // best cached certificate value (greedy) over the wave's rows
   SL_CP = 4,    // new row p, certificate
   SL_CQ = 5,    // new row q, certificate
-  SL_OFF = 6,   // sum of off2 over the wave's rows (rows p, q excluded)
-  SL_OP = 7,    // sum of squares of the new row p
-  SL_OQ = 8,    // sum of squares of the new row q
-  SL_N = 9
+  SL_N = 6
 };
 
 struct Cand {
-  double s;  // score
-  int i;     // row (or column for row-p/q candidates)
-  int c;     // column
+  double s;  // score (negative: no candidate)
   double a;  // matrix entry at (row, column)
+  int i;     // row (or 0 for row-p/q candidates)
+  int c;     // column
   int f;     // stale flag
+  int pad;
 };
 
 template <int NW>
 struct Slots {
-  double s[2][SL_N][NW];
-  double a[2][SL_N][NW];
-  int i[2][SL_N][NW];
-  int c[2][SL_N][NW];
-  int f[2][SL_N][NW];
+  Cand c[2][SL_N][NW];
+  double sum[2][3][NW];  // off2 of the wave's rows, of the new row p, of the new row q
 };
+
+__device__ __forceinline__ Cand empty_cand() { return Cand{-1.0, 0.0, 0x7fffffff, 0x7fffffff, 0, 0}; }
 
 // Wave-level argmax of a candidate (score desc, key asc) -> uniform result.
 __device__ __forceinline__ Cand wave_best(const Cand& x, int key) {
   int w = wave_argmax_lane(x.s, key);
+  if (w < 0) return empty_cand();
   Cand r;
   r.s = readlane_d(x.s, w);
+  r.a = readlane_d(x.a, w);
   r.i = readlane_i(x.i, w);
   r.c = readlane_i(x.c, w);
-  r.a = readlane_d(x.a, w);
   r.f = readlane_i(x.f, w);
+  r.pad = 0;
   return r;
 }
 
-template <int NW>
-__device__ __forceinline__ void put_slot(Slots<NW>& S, int b, int k, int w, const Cand& x) {
-  S.s[b][k][w] = x.s; S.a[b][k][w] = x.a; S.i[b][k][w] = x.i; S.c[b][k][w] = x.c; S.f[b][k][w] = x.f;
-}
-
-// Cross-wave argmax of slot k; `by_col` selects the tie key (column for row-p/q candidates).
+// Cross-wave argmax of slot k over the NW waves: every lane scans the same NW entries
+// (broadcast LDS reads), keeping the first maximum in (score desc, key asc) order.
 template <int NW>
 __device__ __forceinline__ Cand reduce_slot(const Slots<NW>& S, int b, int k, bool by_col) {
-  const int lane = lane_id();
-  Cand x{-1.0, 0x7fffffff, 0x7fffffff, 0.0, 0};
-  if (lane < NW) {
-    x.s = S.s[b][k][lane]; x.a = S.a[b][k][lane]; x.i = S.i[b][k][lane];
-    x.c = S.c[b][k][lane]; x.f = S.f[b][k][lane];
+  Cand best = S.c[b][k][0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    const Cand x = S.c[b][k][w];
+    const int kx = by_col ? x.c : x.i, kb = by_col ? best.c : best.i;
+    if (x.s > best.s || (x.s == best.s && kx < kb)) best = x;
   }
-  int key = by_col ? x.c : x.i;
-  if (x.s < 0.0) key = 0x7fffffff - lane;  // keep keys distinct for empty lanes
-  return wave_best(x, key);
+  return best;
 }
 
 template <int NW>
 __device__ __forceinline__ double reduce_sum_slot(const Slots<NW>& S, int b, int k) {
   double v = 0.0;
-  // fixed order: wave 0, 1, ... (every wave computes the same sum)
-  for (int w = 0; w < NW; ++w) v += S.s[b][k][w];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) v += S.sum[b][k][w];  // fixed order: wave 0, 1, ...
   return v;
 }
 
@@ -270,7 +265,11 @@ __device__ __forceinline__ void refresh_entry(double& bs, int& ba, double& bv, i
   }
 }
 
-template <int NT, int RM, bool GAP, bool LDSA>
+// NT threads (NW waves), RM rows per thread (row k = tid + i * NT).  LDSA: A lives in
+// LDS.  MIR: columns p and q are stored as well (mirrored update; rows are then always
+// current and every load is a contiguous row segment); otherwise rows only, with the
+// per-row write timestamps choosing the current copy of each entry.
+template <int NT, int RM, bool GAP, bool LDSA, bool MIR>
 __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
   constexpr int NW = NT / kWave;
   extern __shared__ double smem[];
@@ -325,38 +324,54 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
   long long rot = d.ctl->rotations;
   long long rescans = 0;
   int status = ST_OK, done = 0;
-  double thr = d.thr;
+  const double thr = d.thr;
   // last rotation (its diagonal entries and timestamps reach LDS one iteration later)
   int lp = -1, lq = -1, lrot = 0;
   double lapp = 0.0, laqq = 0.0;
   bool pend = false;
   // per-thread partials of the new rows p and q (filled by a rotation)
-  Cand rp{-1.0, 0, 0x7fffffff, 0.0, 0}, rq = rp, cp = rp, cq = rp;
+  Cand rp = empty_cand(), rq = rp, cp = rp, cq = rp;
   double op = 0.0, oq = 0.0;
-  Cand W{-1.0, -1, -1, 0.0, 0}, C{-1.0, -1, -1, 0.0, 0};
+  Cand W = empty_cand(), C = empty_cand();
   double off_tot = 0.0;
   int it = 0;
 
   auto diag_of = [&](int x) -> double { return x == lp ? lapp : (x == lq ? laqq : s_diag[x]); };
   auto ts_of = [&](int x) -> int { return (x == lp || x == lq) ? lrot : s_ts[x]; };
+  // current value of entry (r, l), l owned by this thread with timestamp tl
+  auto entry = [&](int r, int l, int tl, int tr) -> double {
+    if constexpr (MIR) return ld_a(r, l);
+    else return (tl > tr) ? ld_a(l, r) : ld_a(r, l);
+  };
+  // optional phase timers: wave reductions, barrier, cross-wave, rescans, rotation
+  const bool prof = d.prof != nullptr;
+  long long tw = 0, tb = 0, tx = 0, tr = 0, tp = 0, tu = 0, tmark = 0;
+  auto tick = [&]() -> long long { return prof ? (long long)wall_clock64() : 0; };
+  const long long clk0 = prof ? (long long)clock64() : 0, wall0 = tick();
 
   // Full rescan of row r's selection (which == 0) or certificate (which == 1) cache.
   auto rescan = [&](int r, int which) {
     const int b = it & 1;
     const double arr = diag_of(r);
-    const int tr = ts_of(r);
-    Cand x{-1.0, r, 0x7fffffff, 0.0, 0};
+    const int trr = MIR ? 0 : ts_of(r);
+    double vals[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      int l = tid + i * NT;
+      vals[i] = (l < n && l != r) ? entry(r, l, tk[i], trr) : 0.0;
+    }
+    Cand x = empty_cand();
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
       int l = tid + i * NT;
       if (l >= n || l == r) continue;
-      double v = (tk[i] > tr) ? ld_a(l, r) : ld_a(r, l);
+      double v = vals[i];
       double sc = which == 0 ? sel_score<GAP>(arr, dk[i], v) : gap_score(arr, dk[i], v);
-      if (sc > x.s) { x.s = sc; x.c = l; x.a = v; }
+      if (sc > x.s) { x.s = sc; x.c = l; x.a = v; x.i = r; }
     }
     Cand wv = wave_best(x, x.c);
     if (NW > 1) {
-      if (lane == 0) put_slot(S, b, SL_SEL, wid, wv);
+      if (lane == 0) S.c[b][SL_SEL][wid] = wv;
       __syncthreads();
       wv = reduce_slot(S, b, SL_SEL, true);
     }
@@ -373,8 +388,9 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
 
   for (;;) {
     const int b = it & 1;
+    tmark = tick();
     // ---- per-thread candidates over own rows
-    Cand x1{-1.0, 0x7fffffff, 0, 0.0, 0}, x4{-1.0, 0x7fffffff, 0, 0.0, 0};
+    Cand x1 = empty_cand(), x4 = empty_cand();
     double o7 = 0.0;
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
@@ -386,36 +402,40 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
       if (use_off) o7 += of2[i];
     }
     // ---- wave reductions
-    Cand w1 = wave_best(x1, x1.i), w2 = wave_best(rp, rp.c), w3 = wave_best(rq, rq.c);
-    Cand w4{-1.0, 0x7fffffff, 0, 0.0, 0}, w5 = w4, w6 = w4;
-    if (use_cert) { w4 = wave_best(x4, x4.i); w5 = wave_best(cp, cp.c); w6 = wave_best(cq, cq.c); }
+    Cand w1 = wave_best(x1, x1.i);
+    Cand w2 = empty_cand(), w3 = w2, w4 = w2, w5 = w2, w6 = w2;
+    if (pend) { w2 = wave_best(rp, rp.c); w3 = wave_best(rq, rq.c); }
+    if (use_cert) {
+      w4 = wave_best(x4, x4.i);
+      if (pend) { w5 = wave_best(cp, cp.c); w6 = wave_best(cq, cq.c); }
+    }
     double s7 = 0.0, s8 = 0.0, s9 = 0.0;
-    if (use_off) { s7 = wave_sum_d(o7); s8 = wave_sum_d(op); s9 = wave_sum_d(oq); }
+    if (use_off) {
+      s7 = wave_sum_d(o7);
+      if (pend) { s8 = wave_sum_d(op); s9 = wave_sum_d(oq); }
+    }
+    if (prof) { long long t = tick(); tw += t - tmark; tmark = t; }
     if (NW > 1) {
       if (lane == 0) {
-        put_slot(S, b, SL_SEL, wid, w1);
-        put_slot(S, b, SL_RP, wid, w2);
-        put_slot(S, b, SL_RQ, wid, w3);
+        S.c[b][SL_SEL][wid] = w1;
+        if (pend) { S.c[b][SL_RP][wid] = w2; S.c[b][SL_RQ][wid] = w3; }
         if (use_cert) {
-          put_slot(S, b, SL_CERT, wid, w4);
-          put_slot(S, b, SL_CP, wid, w5);
-          put_slot(S, b, SL_CQ, wid, w6);
+          S.c[b][SL_CERT][wid] = w4;
+          if (pend) { S.c[b][SL_CP][wid] = w5; S.c[b][SL_CQ][wid] = w6; }
         }
-        if (use_off) { S.s[b][SL_OFF][wid] = s7; S.s[b][SL_OP][wid] = s8; S.s[b][SL_OQ][wid] = s9; }
+        if (use_off) { S.sum[b][0][wid] = s7; S.sum[b][1][wid] = s8; S.sum[b][2][wid] = s9; }
       }
       __syncthreads();
+      if (prof) { long long t = tick(); tb += t - tmark; tmark = t; }
       w1 = reduce_slot(S, b, SL_SEL, false);
-      w2 = reduce_slot(S, b, SL_RP, true);
-      w3 = reduce_slot(S, b, SL_RQ, true);
+      if (pend) { w2 = reduce_slot(S, b, SL_RP, true); w3 = reduce_slot(S, b, SL_RQ, true); }
       if (use_cert) {
         w4 = reduce_slot(S, b, SL_CERT, false);
-        w5 = reduce_slot(S, b, SL_CP, true);
-        w6 = reduce_slot(S, b, SL_CQ, true);
+        if (pend) { w5 = reduce_slot(S, b, SL_CP, true); w6 = reduce_slot(S, b, SL_CQ, true); }
       }
       if (use_off) {
-        s7 = reduce_sum_slot(S, b, SL_OFF);
-        s8 = reduce_sum_slot(S, b, SL_OP);
-        s9 = reduce_sum_slot(S, b, SL_OQ);
+        s7 = reduce_sum_slot(S, b, 0);
+        if (pend) { s8 = reduce_sum_slot(S, b, 1); s9 = reduce_sum_slot(S, b, 2); }
       }
     } else {
       __syncthreads();
@@ -426,11 +446,11 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
     C = w4;
     off_tot = s7;
     if (pend) {
-      if (better(w2.s, lp, W.s, W.i)) W = Cand{w2.s, lp, w2.c, w2.a, 0};
-      if (better(w3.s, lq, W.s, W.i)) W = Cand{w3.s, lq, w3.c, w3.a, 0};
+      if (better(w2.s, lp, W.s, W.i)) W = Cand{w2.s, w2.a, lp, w2.c, 0, 0};
+      if (better(w3.s, lq, W.s, W.i)) W = Cand{w3.s, w3.a, lq, w3.c, 0, 0};
       if (use_cert) {
-        if (better(w5.s, lp, C.s, C.i)) C = Cand{w5.s, lp, w5.c, 0.0, 0};
-        if (better(w6.s, lq, C.s, C.i)) C = Cand{w6.s, lq, w6.c, 0.0, 0};
+        if (better(w5.s, lp, C.s, C.i)) C = Cand{w5.s, 0.0, lp, w5.c, 0, 0};
+        if (better(w6.s, lq, C.s, C.i)) C = Cand{w6.s, 0.0, lq, w6.c, 0, 0};
       }
       off_tot = (s7 + s8) + s9;
 #pragma unroll
@@ -449,19 +469,28 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
         s_ts[lp] = lrot; s_ts[lq] = lrot;
       }
       pend = false;
-      rp = Cand{-1.0, 0, 0x7fffffff, 0.0, 0}; rq = rp; cp = rp; cq = rp;
+      rp = empty_cand(); rq = rp; cp = rp; cq = rp;
       op = 0.0; oq = 0.0;
     }
+    if (prof) { long long t = tick(); tx += t - tmark; tmark = t; }
     if (n < 2) { done = 1; break; }
     // ---- the winner must be exact
-    if (W.f) { rescan(W.i, 0); continue; }
+    if (W.f) {
+      rescan(W.i, 0);
+      if (prof) { long long t = tick(); tr += t - tmark; }
+      continue;
+    }
     // ---- stop rules (checked before every rotation)
     if (d.stop == STOP_CERT) {
       if (GAP) {
         if (W.s <= thr) { done = 1; break; }
       } else {
         if (C.s <= thr) { done = 1; break; }
-        if (C.f) { rescan(C.i, 1); continue; }
+        if (C.f) {
+          rescan(C.i, 1);
+          if (prof) { long long t = tick(); tr += t - tmark; }
+          continue;
+        }
       }
     } else if (d.stop == STOP_OFF) {
       if (sqrt(off_tot) <= thr) { done = 1; break; }
@@ -472,41 +501,43 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
     if (W.a == 0.0) { status = ST_STALL; done = 1; break; }
     if (rot - log_base >= d.log_cap) break;  // log full: drain and resume
 
-    // ---- rotation (p, q)
+    // ---- rotation (p, q): issue the row loads first, the parameters overlap them
     const int p = min(W.i, W.c), q = max(W.i, W.c);
-    const double apq = W.a;
-    const double app = diag_of(p), aqq = diag_of(q);
-    double t, c, s;
-    rot_params<double>(app, aqq, apq, t, c, s);
-    const double napp = app + t * apq;
-    const double naqq = aqq - t * apq;
-    const int tp = ts_of(p), tq = ts_of(q);
-    const int nts = (int)(rot + 1);
+    const int tsp = MIR ? 0 : ts_of(p), tsq = MIR ? 0 : ts_of(q);
     double xv[RM], yv[RM];
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
       int k = tid + i * NT;
       xv[i] = 0.0; yv[i] = 0.0;
       if (k >= n || k == p || k == q) continue;
-      xv[i] = (tk[i] > tp) ? ld_a(k, p) : ld_a(p, k);
-      yv[i] = (tk[i] > tq) ? ld_a(k, q) : ld_a(q, k);
+      xv[i] = entry(p, k, tk[i], tsp);
+      yv[i] = entry(q, k, tk[i], tsq);
     }
+    const double apq = W.a;
+    const double app = diag_of(p), aqq = diag_of(q);
+    double t, c, s;
+    rot_params<double>(app, aqq, apq, t, c, s);
+    const double napp = app + t * apq;
+    const double naqq = aqq - t * apq;
+    const int nts = (int)(rot + 1);
+    if (prof) { long long tt = tick(); tp += tt - tmark; tmark = tt; }
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
       int k = tid + i * NT;
       if (k >= n) continue;
       if (k == p) {
         st_a(q, p, 0.0);
+        if (MIR) st_a(p, q, 0.0);
         dk[i] = napp; tk[i] = nts;
-        if (better(0.0, p, rq.s, rq.c)) rq = Cand{0.0, 0, p, 0.0, 0};
-        if (use_cert && better(0.0, p, cq.s, cq.c)) cq = Cand{0.0, 0, p, 0.0, 0};
+        if (better(0.0, p, rq.s, rq.c)) rq = Cand{0.0, 0.0, 0, p, 0, 0};
+        if (use_cert && better(0.0, p, cq.s, cq.c)) cq = Cand{0.0, 0.0, 0, p, 0, 0};
         continue;
       }
       if (k == q) {
-        st_a(p, q, 0.0);
+        if (!MIR) st_a(p, q, 0.0);
         dk[i] = naqq; tk[i] = nts;
-        if (better(0.0, q, rp.s, rp.c)) rp = Cand{0.0, 0, q, 0.0, 0};
-        if (use_cert && better(0.0, q, cp.s, cp.c)) cp = Cand{0.0, 0, q, 0.0, 0};
+        if (better(0.0, q, rp.s, rp.c)) rp = Cand{0.0, 0.0, 0, q, 0, 0};
+        if (use_cert && better(0.0, q, cp.s, cp.c)) cp = Cand{0.0, 0.0, 0, q, 0, 0};
         continue;
       }
       const double x = xv[i], y = yv[i];
@@ -514,22 +545,24 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
       const double yn = c * y - s * x;
       st_a(p, k, xn);
       st_a(q, k, yn);
+      if (MIR) { st_a(k, p, xn); st_a(k, q, yn); }
       const double sp = sel_score<GAP>(dk[i], napp, xn);
       const double sq = sel_score<GAP>(dk[i], naqq, yn);
       refresh_entry(bs[i], ba[i], bv[i], bst[i], p, q, sp, xn, sq, yn);
-      if (better(sp, k, rp.s, rp.c)) rp = Cand{sp, 0, k, xn, 0};
-      if (better(sq, k, rq.s, rq.c)) rq = Cand{sq, 0, k, yn, 0};
+      if (better(sp, k, rp.s, rp.c)) rp = Cand{sp, xn, 0, k, 0, 0};
+      if (better(sq, k, rq.s, rq.c)) rq = Cand{sq, yn, 0, k, 0, 0};
       if (use_cert) {
         const double lpv = gap_score(dk[i], napp, xn);
         const double lqv = gap_score(dk[i], naqq, yn);
         double dummy = 0.0;
         refresh_entry(cb[i], ca[i], dummy, cst[i], p, q, lpv, 0.0, lqv, 0.0);
-        if (better(lpv, k, cp.s, cp.c)) cp = Cand{lpv, 0, k, 0.0, 0};
-        if (better(lqv, k, cq.s, cq.c)) cq = Cand{lqv, 0, k, 0.0, 0};
+        if (better(lpv, k, cp.s, cp.c)) cp = Cand{lpv, 0.0, 0, k, 0, 0};
+        if (better(lqv, k, cq.s, cq.c)) cq = Cand{lqv, 0.0, 0, k, 0, 0};
       }
       if (use_off) { op += xn * xn; oq += yn * yn; }
     }
     if (tid == 0) d.log[rot - log_base] = RotEntry{p, q, c, s};
+    if (prof) { long long tt = tick(); tu += tt - tmark; }
     lp = p; lq = q; lapp = napp; laqq = naqq; lrot = nts;
     pend = true;
     ++rot;
@@ -547,11 +580,18 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
   }
   if constexpr (LDSA) {
     if (!done) {
+      __syncthreads();
       for (int idx = tid; idx < n * n; idx += NT) {
         int r = idx / n, c = idx - r * n;
         gA[(size_t)r * ld + c] = s_A[r * ldl + c];
       }
     }
+  }
+  if (prof && tid == 0) {
+    d.prof[0] += tw; d.prof[1] += tb; d.prof[2] += tx; d.prof[3] += tr; d.prof[4] += tp;
+    d.prof[5] += tu;
+    d.prof[6] += (long long)clock64() - clk0;
+    d.prof[7] += tick() - wall0;
   }
   if (tid == 0) {
     JCtl* ctl = d.ctl;
@@ -565,7 +605,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
   }
 }
 
-// LDS budget of the LDS-resident variant (A, diagonal and timestamps).
+// LDS budget of the kernel's dynamic part (diagonal, timestamps, and A if LDS-resident).
 static size_t lds_bytes(int n, bool ldsa) {
   size_t b = (size_t)n * 8 + (size_t)((n + 1) / 2) * 8;
   if (ldsa) b += (size_t)n * (size_t)(n | 1) * 8;
@@ -587,13 +627,13 @@ static int max_lds() {
 }
 
 bool jacobi_fits_lds(int n) {
-  return n <= 128 && lds_bytes(n, true) + 4096 <= (size_t)max_lds();
+  return n <= 128 && lds_bytes(n, true) + 8192 <= (size_t)max_lds();
 }
 
-template <int NT, int RM, bool GAP, bool LDSA>
+template <int NT, int RM, bool GAP, bool LDSA, bool MIR>
 static hipError_t launch_one(const JDesc& d, long long log_base, hipStream_t s) {
   size_t sh = lds_bytes(d.n, LDSA);
-  auto fn = k_jacobi<NT, RM, GAP, LDSA>;
+  auto fn = k_jacobi<NT, RM, GAP, LDSA, MIR>;
   if (sh > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
@@ -603,17 +643,33 @@ static hipError_t launch_one(const JDesc& d, long long log_base, hipStream_t s) 
   return hipGetLastError();
 }
 
+static int mirror_mode() {
+  static int m = -1;
+  if (m < 0) {
+    const char* e = getenv("JE_MIRROR");
+    m = (e && e[0] == '1') ? 1 : 0;
+  }
+  return m;
+}
+
+template <bool GAP, bool MIR>
+static hipError_t launch_global(const JDesc& d, long long log_base, hipStream_t s) {
+  const int n = d.n;
+  if (n <= 256) return launch_one<256, 1, GAP, false, MIR>(d, log_base, s);
+  if (n <= 1024) return launch_one<256, 4, GAP, false, MIR>(d, log_base, s);
+  if (n <= 4096) return launch_one<512, 8, GAP, false, MIR>(d, log_base, s);
+  return launch_one<1024, 8, GAP, false, MIR>(d, log_base, s);
+}
+
 template <bool GAP>
 static hipError_t launch_jacobi_t(const JDesc& d, long long log_base, bool lds, hipStream_t s) {
   const int n = d.n;
   if (lds) {
-    if (n <= 64) return launch_one<64, 1, GAP, true>(d, log_base, s);
-    return launch_one<64, 2, GAP, true>(d, log_base, s);
+    if (n <= 64) return launch_one<64, 1, GAP, true, true>(d, log_base, s);
+    return launch_one<64, 2, GAP, true, true>(d, log_base, s);
   }
-  if (n <= 256) return launch_one<256, 1, GAP, false>(d, log_base, s);
-  if (n <= 1024) return launch_one<256, 4, GAP, false>(d, log_base, s);
-  if (n <= 4096) return launch_one<512, 8, GAP, false>(d, log_base, s);
-  return launch_one<1024, 8, GAP, false>(d, log_base, s);
+  if (mirror_mode()) return launch_global<GAP, true>(d, log_base, s);
+  return launch_global<GAP, false>(d, log_base, s);
 }
 
 hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, hipStream_t s) {

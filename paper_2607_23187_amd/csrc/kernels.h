@@ -45,6 +45,7 @@ struct JDesc {
   double thr;
   long long maxrot;
   int pivot, stop;
+  long long* prof;              // optional [8] phase timers (10 ns ticks), accumulated
 };
 
 // Kernel launchers (all asynchronous on `s`).
