@@ -13,9 +13,9 @@
 //
 // Readings of points the paper leaves open (every one is also listed in the design notes):
 //   * score when a_ij^2 == 0 in FP64: defined as 0 (eq. (1) is 0/0 when also a_ii == a_jj);
-//   * rotation: the small-angle root of t^2 + 2 theta t - 1 = 0 with
-//     theta = (a_pp - a_qq) / (2 a_pq), sgn(0) = +1, and t = 1/(2 theta) once
-//     |theta| > 2^500 (theta^2 would overflow);
+//   * rotation: the small-angle root of t^2 + 2 theta t - 1 = 0, theta = (a_pp - a_qq)/(2 a_pq),
+//     evaluated as t = sgn(delta) 2 a_pq / (|delta| + sqrt(delta^2 + 4 a_pq^2)),
+//     delta = a_pp - a_qq, sgn(0) = +1 (no division by a_pq, no theta^2 overflow);
 //   * argmax ties: the lexicographically smallest (i, j), i < j;
 //   * stop rules: certificate max_{i!=j} L_ij <= thr (Theorem 1), off(A) <= thr, or
 //     the selection score of the best pivot <= thr.
@@ -41,35 +41,29 @@ double gap_score(double aii, double ajj, double aij) {
 double greedy_score(double aij) { return std::fabs(aij); }
 
 // c, s such that G^T [[app, apq], [apq, aqq]] G is diagonal, G = [[c, -s], [s, c]] (Sec. 2).
+// t = s / c is the root of modulus <= 1 of t^2 + 2 theta t - 1 = 0, theta = (app - aqq)/(2 apq),
+// written without theta: t = sgn(delta) 2 apq / (|delta| + sqrt(delta^2 + 4 apq^2)),
+// delta = app - aqq, sgn(0) = +1.  t depends only on the ratio delta : apq, so when both
+// are tiny or huge they are first scaled by the same power of two (exactly) to keep the
+// squares in range.  Then c = 1/sqrt(1 + t^2), s = t c, and the new diagonal entries are
+// app + t apq and aqq - t apq.
 template <typename T>
 void rotation(T app, T aqq, T apq, T* t, T* c, T* s) {
-  T theta = (app - aqq) / (T(2) * apq);
-  T tt;
-  if (std::fabs(theta) > T(0x1p500)) {
-    tt = T(1) / (T(2) * theta);
-  } else {
-    tt = T(1) / (std::fabs(theta) + std::sqrt(T(1) + theta * theta));
-    if (theta < T(0)) tt = -tt;
+  const T lo = sizeof(T) == 8 ? T(0x1p-400) : T(0x1p-50);
+  const T hi = sizeof(T) == 8 ? T(0x1p400) : T(0x1p50);
+  T d = app - aqq;
+  T a = apq;
+  T m = std::max(std::fabs(d), std::fabs(a));
+  if (m < lo || m > hi) {
+    int e;
+    (void)std::frexp(m, &e);
+    d = std::ldexp(d, -e);
+    a = std::ldexp(a, -e);
   }
+  T den = std::fabs(d) + std::sqrt(d * d + T(4) * (a * a));
+  T tt = (T(2) * a) / den;
+  if (d < T(0)) tt = -tt;
   T cc = T(1) / std::sqrt(T(1) + tt * tt);
-  *t = tt;
-  *c = cc;
-  *s = tt * cc;
-}
-
-// float version of the 2^500 guard cannot be represented; for float the guard value is
-// 2^60 (theta^2 overflows float beyond 2^64).
-template <>
-void rotation<float>(float app, float aqq, float apq, float* t, float* c, float* s) {
-  float theta = (app - aqq) / (2.0f * apq);
-  float tt;
-  if (std::fabs(theta) > 0x1p60f) {
-    tt = 1.0f / (2.0f * theta);
-  } else {
-    tt = 1.0f / (std::fabs(theta) + std::sqrt(1.0f + theta * theta));
-    if (theta < 0.0f) tt = -tt;
-  }
-  float cc = 1.0f / std::sqrt(1.0f + tt * tt);
   *t = tt;
   *c = cc;
   *s = tt * cc;

@@ -61,7 +61,7 @@ long long default_maxrot(int n) { return 40ll * n * n + 64; }
 // Workspace carving for one problem of size n.
 struct WS {
   double *Asym, *A, *Q, *X, *T, *R, *Vw;
-  double *diag, *bs, *bv, *cb, *off2, *rowsq, *scal;
+  double *diag, *bs, *bv, *cb, *off2, *rowsq, *scal, *bu, *cu;
   int *ba, *bst, *ca, *cst, *ts, *rank, *flag;
   long long* prof;
   JCtl* ctl;
@@ -78,7 +78,7 @@ size_t ws_bytes(int n, int precond, long long log_cap) {
   b += mat;                       // Vw
   if (precond) b += 5 * mat;      // A, Q, X, T, R
   else b += 2 * mat;              // X, R (polish)
-  b += 6 * al((size_t)n * 8);     // diag bs bv cb off2 rowsq
+  b += 8 * al((size_t)n * 8);     // diag bs bv cb off2 rowsq bu cu
   b += al(64);                    // scalars
   b += 7 * al((size_t)n * 4);     // ba bst ca cst ts rank flag
   b += al(sizeof(JCtl));
@@ -115,6 +115,8 @@ WS ws_carve(void* base, int n, int precond, long long log_cap) {
   w.cb = (double*)take((size_t)n * 8);
   w.off2 = (double*)take((size_t)n * 8);
   w.rowsq = (double*)take((size_t)n * 8);
+  w.bu = (double*)take((size_t)n * 8);
+  w.cu = (double*)take((size_t)n * 8);
   w.scal = (double*)take(64);
   w.ba = (int*)take((size_t)n * 4);
   w.bst = (int*)take((size_t)n * 4);
@@ -263,6 +265,7 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   d.A = Ajac; d.n = n; d.ld = ld;
   d.diag = w.diag; d.bs = w.bs; d.ba = w.ba; d.bv = w.bv; d.bst = w.bst;
   d.cb = w.cb; d.ca = w.ca; d.cst = w.cst; d.off2 = w.off2; d.ts = w.ts;
+  d.bu = w.bu; d.cu = w.cu;
   d.log = w.log; d.log_cap = cap; d.ctl = w.ctl;
   d.thr = thr; d.maxrot = maxrot; d.pivot = pivot; d.stop = o.stop;
   if (precond) HIPCHK(launch_get_diag(Ajac, n, ld, w.diag, s));

@@ -32,23 +32,30 @@ __device__ __forceinline__ double sel_score(double aii, double ajj, double aij) 
 }
 
 // Rotation G = [[c, -s], [s, c]] with G^T [[app, apq], [apq, aqq]] G diagonal (Sec. 2):
-// t = tan of the rotation angle is the root of t^2 + 2 theta t - 1 = 0 of modulus <= 1,
-// theta = (app - aqq) / (2 apq), sgn(0) = +1; t = 1/(2 theta) once |theta| > 2^500.
-// Afterwards app' = app + t apq and aqq' = aqq - t apq.
+// t = s / c is the root of modulus <= 1 of t^2 + 2 theta t - 1 = 0 with
+// theta = (app - aqq) / (2 apq), evaluated as
+//   t = sgn(delta) 2 apq / (|delta| + sqrt(delta^2 + 4 apq^2)),  delta = app - aqq,
+// sgn(0) = +1 (one division fewer than going through theta).  t depends only on the ratio
+// delta : apq, so when both are tiny or huge they are scaled by the same power of two
+// first (exact).  c = 1/sqrt(1 + t^2), s = t c; the new diagonal entries are app + t apq
+// and aqq - t apq.
 template <typename T>
 __device__ __forceinline__ void rot_params(T app, T aqq, T apq, T& t, T& c, T& s);
 
 template <>
 __device__ __forceinline__ void rot_params<double>(double app, double aqq, double apq, double& t,
                                                    double& c, double& s) {
-  double theta = (app - aqq) / (2.0 * apq);
-  double tt;
-  if (fabs(theta) > 0x1p500) {
-    tt = 1.0 / (2.0 * theta);
-  } else {
-    tt = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-    if (theta < 0.0) tt = -tt;
+  double d = app - aqq, a = apq;
+  double m = fmax(fabs(d), fabs(a));
+  if (m < 0x1p-400 || m > 0x1p400) {
+    int e;
+    (void)frexp(m, &e);
+    d = ldexp(d, -e);
+    a = ldexp(a, -e);
   }
+  double den = fabs(d) + sqrt(d * d + 4.0 * (a * a));
+  double tt = (2.0 * a) / den;
+  if (d < 0.0) tt = -tt;
   c = 1.0 / sqrt(1.0 + tt * tt);
   s = tt * c;
   t = tt;
@@ -57,14 +64,17 @@ __device__ __forceinline__ void rot_params<double>(double app, double aqq, doubl
 template <>
 __device__ __forceinline__ void rot_params<float>(float app, float aqq, float apq, float& t,
                                                   float& c, float& s) {
-  float theta = (app - aqq) / (2.0f * apq);
-  float tt;
-  if (fabsf(theta) > 0x1p60f) {
-    tt = 1.0f / (2.0f * theta);
-  } else {
-    tt = 1.0f / (fabsf(theta) + sqrtf(1.0f + theta * theta));
-    if (theta < 0.0f) tt = -tt;
+  float d = app - aqq, a = apq;
+  float m = fmaxf(fabsf(d), fabsf(a));
+  if (m < 0x1p-50f || m > 0x1p50f) {
+    int e;
+    (void)frexpf(m, &e);
+    d = ldexpf(d, -e);
+    a = ldexpf(a, -e);
   }
+  float den = fabsf(d) + sqrtf(d * d + 4.0f * (a * a));
+  float tt = (2.0f * a) / den;
+  if (d < 0.0f) tt = -tt;
   c = 1.0f / sqrtf(1.0f + tt * tt);
   s = tt * c;
   t = tt;
@@ -111,9 +121,64 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Wave-uniform maximum: butterfly inside each row of 16 lanes on the DPP network
-// (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror), then the
-// four row results through v_readlane.
+// (bound_ctrl set: the patterns used here never leave the row, and in this form the move
+// folds into the consuming VALU instruction as a DPP operand)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+
+// Monotone 32-bit key of a score: the bits of its float rounding (non-decreasing in the
+// score for scores >= 0), -1 for "no candidate".
+__device__ __forceinline__ int key32(double s) { return s >= 0.0 ? __float_as_int((float)s) : -1; }
+
+// Wave-uniform maximum of 32-bit keys: butterfly inside each row of 16 lanes on the DPP
+// network (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror; each a
+// single v_max_i32 with a DPP operand), then the four row results on the scalar unit.
+__device__ __forceinline__ int wave_max_i(int m) {
+  m = max(m, dpp_i<0xB1>(m));
+  m = max(m, dpp_i<0x4E>(m));
+  m = max(m, dpp_i<0x141>(m));
+  m = max(m, dpp_i<0x140>(m));
+  int r0 = __builtin_amdgcn_readlane(m, 0), r1 = __builtin_amdgcn_readlane(m, 16);
+  int r2 = __builtin_amdgcn_readlane(m, 32), r3 = __builtin_amdgcn_readlane(m, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+// Lane holding the largest score, the smallest key among equal scores (keys of lanes with
+// a candidate are distinct); -1 when no lane has a candidate (negative scores).  The float
+// keys find the lanes that can hold the maximum; equal float keys are settled exactly in
+// FP64 on the scalar path.  The result is wave-uniform.
+__device__ __forceinline__ int wave_argmax_lane(double score, int key) {
+  const int k32 = key32(score);
+  const int m = wave_max_i(k32);
+  if (m < 0) return -1;
+  unsigned long long b = __ballot(k32 == m);
+  int w = __ffsll((long long)b) - 1;
+  b &= b - 1;
+  if (b) {
+    double bs = readlane_d(score, w);
+    int bk = __builtin_amdgcn_readlane(key, w);
+    while (b) {
+      int l = __ffsll((long long)b) - 1;
+      b &= b - 1;
+      double x = readlane_d(score, l);
+      int kx = __builtin_amdgcn_readlane(key, l);
+      if (x > bs || (x == bs && kx < bk)) { bs = x; bk = kx; w = l; }
+    }
+  }
+  return w;
+}
+
+// Wave-uniform upper bound of max(v) (the float rounding of the maximum, widened by
+// 2^-22 relative); -1 when every lane passes a negative value.
+__device__ __forceinline__ double wave_max_ub(double v) {
+  const int m = wave_max_i(key32(v));
+  if (m < 0) return -1.0;
+  return (double)__int_as_float(m) * (1.0 + 0x1p-22);
+}
+
+// Wave-uniform maximum of doubles (exact).
 __device__ __forceinline__ double wave_max_fast(double m) {
   m = fmax(m, dpp_d<0xB1>(m));
   m = fmax(m, dpp_d<0x4E>(m));
@@ -124,17 +189,15 @@ __device__ __forceinline__ double wave_max_fast(double m) {
   return fmax(fmax(r0, r1), fmax(r2, r3));
 }
 
-// Lane holding the largest score, the smallest key among equal scores.  Keys of lanes
-// holding a candidate are distinct; lanes with nothing to offer pass a negative score.
-// The result is wave-uniform; -1 when no lane has a candidate.
-__device__ __forceinline__ int wave_argmax_lane(double score, int key) {
-  double m = wave_max_fast(score);
-  if (m < 0.0) return -1;
-  unsigned long long b = __ballot(score == m);
-  if (__popcll(b) == 1) return __ffsll((long long)b) - 1;
-  int k = wave_min_i(score == m ? key : 0x7fffffff);
-  b = __ballot(score == m && key == k);
-  return __ffsll((long long)b) - 1;
+// Wave-uniform sum of doubles (butterfly in rows, then the four row sums in order).
+__device__ __forceinline__ double wave_sum_fast(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  double r0 = readlane_d(v, 0), r1 = readlane_d(v, 16), r2 = readlane_d(v, 32),
+         r3 = readlane_d(v, 48);
+  return ((r0 + r1) + r2) + r3;
 }
 
 }  // namespace je

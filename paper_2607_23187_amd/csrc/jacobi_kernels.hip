@@ -122,8 +122,23 @@ hipError_t launch_normf(const double* rowsq, int n, double* out, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------ J0: initial row scores
-// One wave per row: the best selection score over l != k (smallest l on ties), the best
-// L_kl (greedy + certificate only) and off2[k] = sum_{l != k} a_kl^2.
+// Per-lane top two of a row: value and column of the best (smallest column on ties, since
+// columns arrive in ascending order), and the best value among the other columns.
+__device__ __forceinline__ void top2(double v, int col, double a, double& s1, int& c1, double& a1,
+                                     double& s2) {
+  if (v > s1) { s2 = s1; s1 = v; c1 = col; a1 = a; }
+  else if (v > s2) s2 = v;
+}
+
+// Wave-uniform bound of all values except the winner's: the winner lane offers its second
+// value, every other lane its best.
+__device__ __forceinline__ double wave_second(double s1, double s2, int wlane) {
+  return wave_max_ub(lane_id() == wlane ? s2 : s1);
+}
+
+// One wave per row: best selection score over l != k (smallest l on ties) and the largest
+// score over the other columns; the same for L_kl (greedy + certificate only);
+// off2[k] = sum_{l != k} a_kl^2.
 template <bool GAP>
 __global__ __launch_bounds__(256) void k_init_rows(JDesc d, int use_cert) {
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -132,34 +147,33 @@ __global__ __launch_bounds__(256) void k_init_rows(JDesc d, int use_cert) {
   const int n = d.n;
   const double* row = d.A + (size_t)k * d.ld;
   const double dkk = d.diag[k];
-  double bs = -1.0, bv = 0.0, cb = -1.0, o2 = 0.0;
-  int ba = -1, ca = -1;
+  double bs = -1.0, bv = 0.0, b2 = -1.0, cb = -1.0, cav = 0.0, c2 = -1.0, o2 = 0.0;
+  int ba = 0x7fffffff, ca = 0x7fffffff;
   for (int l = lane; l < n; l += 64) {
     if (l == k) continue;
     double a = row[l];
     double dl = d.diag[l];
-    double s = sel_score<GAP>(dkk, dl, a);
-    if (s > bs) { bs = s; ba = l; bv = a; }
-    if (use_cert) {
-      double L = gap_score(dkk, dl, a);
-      if (L > cb) { cb = L; ca = l; }
-    }
+    top2(sel_score<GAP>(dkk, dl, a), l, a, bs, ba, bv, b2);
+    if (use_cert) top2(gap_score(dkk, dl, a), l, 0.0, cb, ca, cav, c2);
     o2 += a * a;
   }
-  int w = wave_argmax_lane(bs, ba < 0 ? 0x7fffffff : ba);
-  double wbs = -1.0, wbv = 0.0;
+  int w = wave_argmax_lane(bs, ba);
+  double wbs = -1.0, wbv = 0.0, wbu = -1.0;
   int wba = -1;
-  if (w >= 0) { wbs = readlane_d(bs, w); wbv = readlane_d(bv, w); wba = readlane_i(ba, w); }
-  double wcb = -1.0;
+  if (w >= 0) {
+    wbs = readlane_d(bs, w); wbv = readlane_d(bv, w); wba = readlane_i(ba, w);
+    wbu = wave_second(bs, b2, w);
+  }
+  double wcb = -1.0, wcu = -1.0;
   int wca = -1;
   if (use_cert) {
-    int w2 = wave_argmax_lane(cb, ca < 0 ? 0x7fffffff : ca);
-    if (w2 >= 0) { wcb = readlane_d(cb, w2); wca = readlane_i(ca, w2); }
+    int w2 = wave_argmax_lane(cb, ca);
+    if (w2 >= 0) { wcb = readlane_d(cb, w2); wca = readlane_i(ca, w2); wcu = wave_second(cb, c2, w2); }
   }
-  o2 = wave_sum_d(o2);
+  o2 = wave_sum_fast(o2);
   if (lane == 0) {
-    d.bs[k] = wbs; d.ba[k] = wba; d.bv[k] = wbv; d.bst[k] = 0;
-    if (use_cert) { d.cb[k] = wcb; d.ca[k] = wca; d.cst[k] = 0; }
+    d.bs[k] = wbs; d.ba[k] = wba; d.bv[k] = wbv; d.bst[k] = 0; d.bu[k] = wbu;
+    if (use_cert) { d.cb[k] = wcb; d.ca[k] = wca; d.cst[k] = 0; d.cu[k] = wcu; }
     d.off2[k] = o2;
     d.ts[k] = 0;
   }
@@ -177,7 +191,7 @@ hipError_t launch_init_rows(const JDesc& d, hipStream_t s) {
 // Slot indices of the per-wave partial results exchanged through LDS.
 enum {
   SL_SEL = 0,   // best cached selection candidate over the wave's rows (rows p, q excluded)
-  SL_RP = 1,    // new row p: best (score, column) -- becomes row p's cache entry
+  SL_RP = 1,    // new row p: best (score, column) and bound of its other scores
   SL_RQ = 2,    // new row q
   SL_CERT = 3,  // best cached certificate value (greedy) over the wave's rows
   SL_CP = 4,    // new row p, certificate
@@ -188,7 +202,8 @@ enum {
 struct Cand {
   double s;  // score (negative: no candidate)
   double a;  // matrix entry at (row, column)
-  int i;     // row (or 0 for row-p/q candidates)
+  double u;  // bound of the row's other scores (row-p/q candidates)
+  int i;     // row
   int c;     // column
   int f;     // stale flag
   int pad;
@@ -200,33 +215,117 @@ struct Slots {
   double sum[2][3][NW];  // off2 of the wave's rows, of the new row p, of the new row q
 };
 
-__device__ __forceinline__ Cand empty_cand() { return Cand{-1.0, 0.0, 0x7fffffff, 0x7fffffff, 0, 0}; }
+__device__ __forceinline__ Cand empty_cand() {
+  return Cand{-1.0, 0.0, -1.0, 0x7fffffff, 0x7fffffff, 0, 0};
+}
 
-// Wave-level argmax of a candidate (score desc, key asc) -> uniform result.
-__device__ __forceinline__ Cand wave_best(const Cand& x, int key) {
-  int w = wave_argmax_lane(x.s, key);
+__device__ __forceinline__ bool better(double s1, int k1, double s2, int k2) {
+  return s1 > s2 || (s1 == s2 && k1 < k2);
+}
+
+// Payload of lane w, wave-uniform.  Row and column (< 2^13) and the stale flag travel as
+// one packed 32-bit value.
+__device__ __forceinline__ Cand read_cand(const Cand& x, int w, bool with_u) {
   if (w < 0) return empty_cand();
   Cand r;
   r.s = readlane_d(x.s, w);
   r.a = readlane_d(x.a, w);
-  r.i = readlane_i(x.i, w);
-  r.c = readlane_i(x.c, w);
-  r.f = readlane_i(x.f, w);
+  r.u = with_u ? readlane_d(x.u, w) : -1.0;
+  const int pk = readlane_i((x.i & 0x1fff) | ((x.c & 0x1fff) << 13) | (x.f << 26), w);
+  r.i = pk & 0x1fff;
+  r.c = (pk >> 13) & 0x1fff;
+  r.f = pk >> 26;
   r.pad = 0;
   return r;
 }
 
+// Wave-uniform argmax of three candidates at once (independent chains interleave).  For b
+// and c the result's u bounds every value but the winner's: the winning lane offers its
+// second value, the others their best.
+__device__ __forceinline__ void wave_best3(Cand& a, int ka, Cand& b, int kb, Cand& c, int kc) {
+  const int la = wave_argmax_lane(a.s, ka), lb = wave_argmax_lane(b.s, kb),
+            lc = wave_argmax_lane(c.s, kc);
+  const int lane = lane_id();
+  const double ub = wave_max_ub(lane == lb ? b.u : b.s);
+  const double uc = wave_max_ub(lane == lc ? c.u : c.s);
+  a = read_cand(a, la, false);
+  b = read_cand(b, lb, false);
+  c = read_cand(c, lc, false);
+  b.u = ub;
+  c.u = uc;
+}
+
+// Cross-wave reduction of three slot groups at once: lane 16 g + w holds entry w of group
+// g (g = 0, 1, 2; w < NW <= 16).  One DPP butterfly inside each 16-lane row yields the
+// three group maxima; ties of the float keys are settled exactly.  Group 0 is keyed by
+// row, groups 1 and 2 by column; for groups 1 and 2 u bounds every value but the winner's.
+template <int NW>
+__device__ __forceinline__ void reduce_groups3(const Cand* g0, const Cand* g1, const Cand* g2,
+                                               Cand& r0, Cand& r1, Cand& r2) {
+  const int lane = lane_id();
+  const int grp = lane >> 4, w = lane & 15;
+  Cand x = empty_cand();
+  if (w < NW && grp < 3) x = (grp == 0 ? g0 : (grp == 1 ? g1 : g2))[w];
+  const int key = (grp == 0) ? x.i : x.c;
+  const int k32 = key32(x.s);
+  int m = k32;
+  m = max(m, dpp_i<0xB1>(m));
+  m = max(m, dpp_i<0x4E>(m));
+  m = max(m, dpp_i<0x141>(m));
+  m = max(m, dpp_i<0x140>(m));
+  const unsigned long long hit = __ballot(k32 == m && x.s >= 0.0);
+  int win[3];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    unsigned long long b = hit & (0xffffull << (16 * g));
+    int wl = b ? __ffsll((long long)b) - 1 : -1;
+    if (b & (b - 1)) {  // equal float keys: exact comparison
+      double bs = readlane_d(x.s, wl);
+      int bk = readlane_i(key, wl);
+      b &= b - 1;
+      while (b) {
+        int l = __ffsll((long long)b) - 1;
+        b &= b - 1;
+        double v = readlane_d(x.s, l);
+        int kv = readlane_i(key, l);
+        if (v > bs || (v == bs && kv < bk)) { bs = v; bk = kv; wl = l; }
+      }
+    }
+    win[g] = wl;
+  }
+  // bound of the other values in groups 1 and 2: the winner offers its u, the rest their s
+  const bool mine = (grp == 1 && lane == win[1]) || (grp == 2 && lane == win[2]);
+  int mu = key32(mine ? x.u : x.s);
+  mu = max(mu, dpp_i<0xB1>(mu));
+  mu = max(mu, dpp_i<0x4E>(mu));
+  mu = max(mu, dpp_i<0x141>(mu));
+  mu = max(mu, dpp_i<0x140>(mu));
+  const int mu1 = readlane_i(mu, 16), mu2 = readlane_i(mu, 32);
+  r0 = read_cand(x, win[0], false);
+  r1 = read_cand(x, win[1], false);
+  r2 = read_cand(x, win[2], false);
+  r1.u = mu1 < 0 ? -1.0 : (double)__int_as_float(mu1) * (1.0 + 0x1p-22);
+  r2.u = mu2 < 0 ? -1.0 : (double)__int_as_float(mu2) * (1.0 + 0x1p-22);
+}
+
 // Cross-wave argmax of slot k over the NW waves: every lane scans the same NW entries
-// (broadcast LDS reads), keeping the first maximum in (score desc, key asc) order.
+// (broadcast LDS reads), keeping the first maximum in (score desc, key asc) order; u is
+// the bound of all values but the winner's.
 template <int NW>
 __device__ __forceinline__ Cand reduce_slot(const Slots<NW>& S, int b, int k, bool by_col) {
   Cand best = S.c[b][k][0];
+  int bw = 0;
 #pragma unroll
   for (int w = 1; w < NW; ++w) {
     const Cand x = S.c[b][k][w];
     const int kx = by_col ? x.c : x.i, kb = by_col ? best.c : best.i;
-    if (x.s > best.s || (x.s == best.s && kx < kb)) best = x;
+    if (better(x.s, kx, best.s, kb)) { best = x; bw = w; }
   }
+  double u = best.u;
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+    if (w != bw) u = fmax(u, S.c[b][k][w].s);
+  best.u = u;
   return best;
 }
 
@@ -238,31 +337,46 @@ __device__ __forceinline__ double reduce_sum_slot(const Slots<NW>& S, int b, int
   return v;
 }
 
-__device__ __forceinline__ bool better(double s1, int k1, double s2, int k2) {
-  return s1 > s2 || (s1 == s2 && k1 < k2);
+// Refresh of one row's cache after rotation (p, q) changed its entries at columns p and q
+// to scores sp, sq (matrix values xp, xq).  Fresh row: bs/ba/bv is its exact best and bu
+// bounds its other scores.  Stale row: bs bounds all its scores.  Straight-line code: all
+// cases are evaluated and selected.
+__device__ __forceinline__ void refresh_entry(double& bs, int& ba, double& bv, double& bu,
+                                              int& bst, int p, int q, double sp, double xp,
+                                              double sq, double xq) {
+  const bool qb = sq > sp;
+  const double v = qb ? sq : sp, a = qb ? xq : xp, o = qb ? sp : sq;
+  const int col = qb ? q : p;
+  // fresh row whose best column moved: exact when above the bound of the other entries
+  const bool hit = (ba == p) || (ba == q);
+  const bool up = v > bu;
+  // fresh row, best column untouched: insert (sp, p) then (sq, q)
+  const bool b1 = better(sp, p, bs, ba);
+  const double bs1 = b1 ? sp : bs, bv1 = b1 ? xp : bv, bu1 = fmax(bu, b1 ? bs : sp);
+  const int ba1 = b1 ? p : ba;
+  const bool b2 = better(sq, q, bs1, ba1);
+  const double bs2 = b2 ? sq : bs1, bv2 = b2 ? xq : bv1, bu2 = fmax(bu1, b2 ? bs1 : sq);
+  const int ba2 = b2 ? q : ba1;
+  // stale row: exact again when strictly above its bound
+  const bool sup = v > bs;
+  double nbs, nbv, nbu;
+  int nba, nst;
+  if (bst) {
+    nbs = sup ? v : bs; nbv = sup ? a : bv; nbu = sup ? fmax(bs, o) : bu; nba = sup ? col : ba;
+    nst = sup ? 0 : 1;
+  } else if (hit) {
+    nbs = up ? v : bu; nbv = up ? a : bv; nbu = up ? fmax(bu, o) : bu; nba = up ? col : ba;
+    nst = up ? 0 : 1;
+  } else {
+    nbs = bs2; nbv = bv2; nbu = bu2; nba = ba2; nst = 0;
+  }
+  bs = nbs; bv = nbv; bu = nbu; ba = nba; bst = nst;
 }
 
-// Refresh of one cached row entry after rotation (p, q) changed its entries at columns
-// p and q to scores sp, sq (matrix values xp, xq).
-__device__ __forceinline__ void refresh_entry(double& bs, int& ba, double& bv, int& bst, int p,
-                                              int q, double sp, double xp, double sq,
-                                              double xq) {
-  double v = sp, a = xp;
-  int col = p;
-  if (sq > v) { v = sq; a = xq; col = q; }
-  if (!bst) {
-    if (ba == p || ba == q) {
-      // the cached maximum itself moved; every other entry is still <= bs
-      if (v > bs || (v == bs && col <= ba)) { bs = v; ba = col; bv = a; }
-      else bst = 1;  // bs stays as an upper bound of the row
-    } else {
-      if (sp > bs || (sp == bs && p < ba)) { bs = sp; ba = p; bv = xp; }
-      if (sq > bs || (sq == bs && q < ba)) { bs = sq; ba = q; bv = xq; }
-    }
-  } else if (v > bs) {
-    // strictly above the bound on every other entry: exact again
-    bs = v; ba = col; bv = a; bst = 0;
-  }
+// Per-thread top two of the new row p (or q): best (score, column, value), second value.
+__device__ __forceinline__ void cand_top2(Cand& x, double v, int col, double a) {
+  if (better(v, col, x.s, x.c)) { x.u = fmax(x.u, x.s); x.s = v; x.c = col; x.a = a; }
+  else x.u = fmax(x.u, v);
 }
 
 // NT threads (NW waves), RM rows per thread (row k = tid + i * NT).  LDSA: A lives in
@@ -294,23 +408,26 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
     if constexpr (LDSA) s_A[r * ldl + c] = v;
     else gA[(size_t)r * ld + c] = v;
   };
+  auto sync = [&]() {
+    if constexpr (NW > 1) __syncthreads();
+  };
 
   // ---- per-thread rows k = tid + i * NT
-  double dk[RM], bs[RM], bv[RM], cb[RM], of2[RM];
+  double dk[RM], bs[RM], bv[RM], bu[RM], cb[RM], cu[RM], of2[RM];
   int ba[RM], bst[RM], ca[RM], cst[RM], tk[RM];
 #pragma unroll
   for (int i = 0; i < RM; ++i) {
     int k = tid + i * NT;
     if (k < n) {
       dk[i] = d.diag[k]; bs[i] = d.bs[k]; ba[i] = d.ba[k]; bv[i] = d.bv[k]; bst[i] = d.bst[k];
-      of2[i] = d.off2[k]; tk[i] = d.ts[k];
-      if (use_cert) { cb[i] = d.cb[k]; ca[i] = d.ca[k]; cst[i] = d.cst[k]; }
-      else { cb[i] = -1.0; ca[i] = -1; cst[i] = 0; }
+      bu[i] = d.bu[k]; of2[i] = d.off2[k]; tk[i] = d.ts[k];
+      if (use_cert) { cb[i] = d.cb[k]; ca[i] = d.ca[k]; cst[i] = d.cst[k]; cu[i] = d.cu[k]; }
+      else { cb[i] = -1.0; ca[i] = -1; cst[i] = 0; cu[i] = -1.0; }
       s_diag[k] = dk[i];
       s_ts[k] = tk[i];
     } else {
-      dk[i] = 0.0; bs[i] = -1.0; ba[i] = -1; bv[i] = 0.0; bst[i] = 0; of2[i] = 0.0; tk[i] = 0;
-      cb[i] = -1.0; ca[i] = -1; cst[i] = 0;
+      dk[i] = 0.0; bs[i] = -1.0; ba[i] = -1; bv[i] = 0.0; bst[i] = 0; bu[i] = -1.0; of2[i] = 0.0;
+      tk[i] = 0; cb[i] = -1.0; ca[i] = -1; cst[i] = 0; cu[i] = -1.0;
     }
   }
   if constexpr (LDSA) {
@@ -329,7 +446,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
   int lp = -1, lq = -1, lrot = 0;
   double lapp = 0.0, laqq = 0.0;
   bool pend = false;
-  // per-thread partials of the new rows p and q (filled by a rotation)
+  // per-thread top two of the new rows p and q (filled by a rotation)
   Cand rp = empty_cand(), rq = rp, cp = rp, cq = rp;
   double op = 0.0, oq = 0.0;
   Cand W = empty_cand(), C = empty_cand();
@@ -349,7 +466,8 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
   auto tick = [&]() -> long long { return prof ? (long long)wall_clock64() : 0; };
   const long long clk0 = prof ? (long long)clock64() : 0, wall0 = tick();
 
-  // Full rescan of row r's selection (which == 0) or certificate (which == 1) cache.
+  // Full rescan of row r's selection (which == 0) or certificate (which == 1) cache:
+  // exact best and the bound of the other scores.
   auto rescan = [&](int r, int which) {
     const int b = it & 1;
     const double arr = diag_of(r);
@@ -367,20 +485,21 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
       if (l >= n || l == r) continue;
       double v = vals[i];
       double sc = which == 0 ? sel_score<GAP>(arr, dk[i], v) : gap_score(arr, dk[i], v);
-      if (sc > x.s) { x.s = sc; x.c = l; x.a = v; x.i = r; }
+      cand_top2(x, sc, l, v);
     }
-    Cand wv = wave_best(x, x.c);
+    Cand e1 = empty_cand(), e2 = empty_cand();
+    wave_best3(e1, 0, x, x.c, e2, 0);
     if (NW > 1) {
-      if (lane == 0) S.c[b][SL_SEL][wid] = wv;
+      if (lane == 0) S.c[b][SL_RP][wid] = x;
       __syncthreads();
-      wv = reduce_slot(S, b, SL_SEL, true);
+      x = reduce_slot(S, b, SL_RP, true);
     }
     ++it;
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
       if (tid + i * NT == r) {
-        if (which == 0) { bs[i] = wv.s; ba[i] = wv.c; bv[i] = wv.a; bst[i] = 0; }
-        else { cb[i] = wv.s; ca[i] = wv.c; cst[i] = 0; }
+        if (which == 0) { bs[i] = x.s; ba[i] = x.c; bv[i] = x.a; bu[i] = x.u; bst[i] = 0; }
+        else { cb[i] = x.s; ca[i] = x.c; cu[i] = x.u; cst[i] = 0; }
       }
     }
     ++rescans;
@@ -401,44 +520,29 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
       if (use_cert && cb[i] > x4.s) { x4.s = cb[i]; x4.i = k; x4.c = ca[i]; x4.f = cst[i]; }
       if (use_off) o7 += of2[i];
     }
-    // ---- wave reductions
-    Cand w1 = wave_best(x1, x1.i);
-    Cand w2 = empty_cand(), w3 = w2, w4 = w2, w5 = w2, w6 = w2;
-    if (pend) { w2 = wave_best(rp, rp.c); w3 = wave_best(rq, rq.c); }
-    if (use_cert) {
-      w4 = wave_best(x4, x4.i);
-      if (pend) { w5 = wave_best(cp, cp.c); w6 = wave_best(cq, cq.c); }
-    }
+    // ---- wave reductions (rp, rq, cp, cq are empty unless a rotation is pending)
+    Cand w1 = x1, w2 = rp, w3 = rq, w4 = x4, w5 = cp, w6 = cq;
+    wave_best3(w1, x1.i, w2, rp.c, w3, rq.c);
+    if (use_cert) wave_best3(w4, x4.i, w5, cp.c, w6, cq.c);
     double s7 = 0.0, s8 = 0.0, s9 = 0.0;
-    if (use_off) {
-      s7 = wave_sum_d(o7);
-      if (pend) { s8 = wave_sum_d(op); s9 = wave_sum_d(oq); }
-    }
+    if (use_off) { s7 = wave_sum_fast(o7); s8 = wave_sum_fast(op); s9 = wave_sum_fast(oq); }
     if (prof) { long long t = tick(); tw += t - tmark; tmark = t; }
-    if (NW > 1) {
+    if constexpr (NW > 1) {
       if (lane == 0) {
-        S.c[b][SL_SEL][wid] = w1;
-        if (pend) { S.c[b][SL_RP][wid] = w2; S.c[b][SL_RQ][wid] = w3; }
-        if (use_cert) {
-          S.c[b][SL_CERT][wid] = w4;
-          if (pend) { S.c[b][SL_CP][wid] = w5; S.c[b][SL_CQ][wid] = w6; }
-        }
+        S.c[b][SL_SEL][wid] = w1; S.c[b][SL_RP][wid] = w2; S.c[b][SL_RQ][wid] = w3;
+        if (use_cert) { S.c[b][SL_CERT][wid] = w4; S.c[b][SL_CP][wid] = w5; S.c[b][SL_CQ][wid] = w6; }
         if (use_off) { S.sum[b][0][wid] = s7; S.sum[b][1][wid] = s8; S.sum[b][2][wid] = s9; }
       }
       __syncthreads();
       if (prof) { long long t = tick(); tb += t - tmark; tmark = t; }
-      w1 = reduce_slot(S, b, SL_SEL, false);
-      if (pend) { w2 = reduce_slot(S, b, SL_RP, true); w3 = reduce_slot(S, b, SL_RQ, true); }
-      if (use_cert) {
-        w4 = reduce_slot(S, b, SL_CERT, false);
-        if (pend) { w5 = reduce_slot(S, b, SL_CP, true); w6 = reduce_slot(S, b, SL_CQ, true); }
-      }
+      reduce_groups3<NW>(S.c[b][SL_SEL], S.c[b][SL_RP], S.c[b][SL_RQ], w1, w2, w3);
+      if (use_cert)
+        reduce_groups3<NW>(S.c[b][SL_CERT], S.c[b][SL_CP], S.c[b][SL_CQ], w4, w5, w6);
       if (use_off) {
         s7 = reduce_sum_slot(S, b, 0);
-        if (pend) { s8 = reduce_sum_slot(S, b, 1); s9 = reduce_sum_slot(S, b, 2); }
+        s8 = reduce_sum_slot(S, b, 1);
+        s9 = reduce_sum_slot(S, b, 2);
       }
-    } else {
-      __syncthreads();
     }
     ++it;
     // ---- fold in the rows of the last rotation
@@ -446,22 +550,22 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
     C = w4;
     off_tot = s7;
     if (pend) {
-      if (better(w2.s, lp, W.s, W.i)) W = Cand{w2.s, w2.a, lp, w2.c, 0, 0};
-      if (better(w3.s, lq, W.s, W.i)) W = Cand{w3.s, w3.a, lq, w3.c, 0, 0};
+      if (better(w2.s, lp, W.s, W.i)) W = Cand{w2.s, w2.a, w2.u, lp, w2.c, 0, 0};
+      if (better(w3.s, lq, W.s, W.i)) W = Cand{w3.s, w3.a, w3.u, lq, w3.c, 0, 0};
       if (use_cert) {
-        if (better(w5.s, lp, C.s, C.i)) C = Cand{w5.s, 0.0, lp, w5.c, 0, 0};
-        if (better(w6.s, lq, C.s, C.i)) C = Cand{w6.s, 0.0, lq, w6.c, 0, 0};
+        if (better(w5.s, lp, C.s, C.i)) C = Cand{w5.s, 0.0, w5.u, lp, w5.c, 0, 0};
+        if (better(w6.s, lq, C.s, C.i)) C = Cand{w6.s, 0.0, w6.u, lq, w6.c, 0, 0};
       }
       off_tot = (s7 + s8) + s9;
 #pragma unroll
       for (int i = 0; i < RM; ++i) {
         int k = tid + i * NT;
         if (k == lp) {
-          bs[i] = w2.s; ba[i] = w2.c; bv[i] = w2.a; bst[i] = 0; of2[i] = s8;
-          if (use_cert) { cb[i] = w5.s; ca[i] = w5.c; cst[i] = 0; }
+          bs[i] = w2.s; ba[i] = w2.c; bv[i] = w2.a; bu[i] = w2.u; bst[i] = 0; of2[i] = s8;
+          if (use_cert) { cb[i] = w5.s; ca[i] = w5.c; cu[i] = w5.u; cst[i] = 0; }
         } else if (k == lq) {
-          bs[i] = w3.s; ba[i] = w3.c; bv[i] = w3.a; bst[i] = 0; of2[i] = s9;
-          if (use_cert) { cb[i] = w6.s; ca[i] = w6.c; cst[i] = 0; }
+          bs[i] = w3.s; ba[i] = w3.c; bv[i] = w3.a; bu[i] = w3.u; bst[i] = 0; of2[i] = s9;
+          if (use_cert) { cb[i] = w6.s; ca[i] = w6.c; cu[i] = w6.u; cst[i] = 0; }
         }
       }
       if (tid == 0) {
@@ -529,15 +633,15 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
         st_a(q, p, 0.0);
         if (MIR) st_a(p, q, 0.0);
         dk[i] = napp; tk[i] = nts;
-        if (better(0.0, p, rq.s, rq.c)) rq = Cand{0.0, 0.0, 0, p, 0, 0};
-        if (use_cert && better(0.0, p, cq.s, cq.c)) cq = Cand{0.0, 0.0, 0, p, 0, 0};
+        cand_top2(rq, 0.0, p, 0.0);
+        if (use_cert) cand_top2(cq, 0.0, p, 0.0);
         continue;
       }
       if (k == q) {
         if (!MIR) st_a(p, q, 0.0);
         dk[i] = naqq; tk[i] = nts;
-        if (better(0.0, q, rp.s, rp.c)) rp = Cand{0.0, 0.0, 0, q, 0, 0};
-        if (use_cert && better(0.0, q, cp.s, cp.c)) cp = Cand{0.0, 0.0, 0, q, 0, 0};
+        cand_top2(rp, 0.0, q, 0.0);
+        if (use_cert) cand_top2(cp, 0.0, q, 0.0);
         continue;
       }
       const double x = xv[i], y = yv[i];
@@ -548,16 +652,16 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
       if (MIR) { st_a(k, p, xn); st_a(k, q, yn); }
       const double sp = sel_score<GAP>(dk[i], napp, xn);
       const double sq = sel_score<GAP>(dk[i], naqq, yn);
-      refresh_entry(bs[i], ba[i], bv[i], bst[i], p, q, sp, xn, sq, yn);
-      if (better(sp, k, rp.s, rp.c)) rp = Cand{sp, xn, 0, k, 0, 0};
-      if (better(sq, k, rq.s, rq.c)) rq = Cand{sq, yn, 0, k, 0, 0};
+      refresh_entry(bs[i], ba[i], bv[i], bu[i], bst[i], p, q, sp, xn, sq, yn);
+      cand_top2(rp, sp, k, xn);
+      cand_top2(rq, sq, k, yn);
       if (use_cert) {
         const double lpv = gap_score(dk[i], napp, xn);
         const double lqv = gap_score(dk[i], naqq, yn);
         double dummy = 0.0;
-        refresh_entry(cb[i], ca[i], dummy, cst[i], p, q, lpv, 0.0, lqv, 0.0);
-        if (better(lpv, k, cp.s, cp.c)) cp = Cand{lpv, 0.0, 0, k, 0, 0};
-        if (better(lqv, k, cq.s, cq.c)) cq = Cand{lqv, 0.0, 0, k, 0, 0};
+        refresh_entry(cb[i], ca[i], dummy, cu[i], cst[i], p, q, lpv, 0.0, lqv, 0.0);
+        cand_top2(cp, lpv, k, 0.0);
+        cand_top2(cq, lqv, k, 0.0);
       }
       if (use_off) { op += xn * xn; oq += yn * yn; }
     }
@@ -574,8 +678,8 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
     int k = tid + i * NT;
     if (k < n) {
       d.diag[k] = dk[i]; d.bs[k] = bs[i]; d.ba[k] = ba[i]; d.bv[k] = bv[i]; d.bst[k] = bst[i];
-      d.off2[k] = of2[i]; d.ts[k] = tk[i];
-      if (use_cert) { d.cb[k] = cb[i]; d.ca[k] = ca[i]; d.cst[k] = cst[i]; }
+      d.bu[k] = bu[i]; d.off2[k] = of2[i]; d.ts[k] = tk[i];
+      if (use_cert) { d.cb[k] = cb[i]; d.ca[k] = ca[i]; d.cst[k] = cst[i]; d.cu[k] = cu[i]; }
     }
   }
   if constexpr (LDSA) {
@@ -652,11 +756,33 @@ static int mirror_mode() {
   return m;
 }
 
+static int threads_override() {
+  static int t = -1;
+  if (t < 0) {
+    const char* e = getenv("JE_NT");
+    t = e ? atoi(e) : 0;
+  }
+  return t;
+}
+
+// Threads per workgroup for the HBM-resident kernel: 512 (two waves per SIMD, 256 VGPRs
+// per lane) unless overridden; rows per thread RM = ceil(n / NT).
 template <bool GAP, bool MIR>
 static hipError_t launch_global(const JDesc& d, long long log_base, hipStream_t s) {
   const int n = d.n;
+  const int nt = threads_override();
   if (n <= 256) return launch_one<256, 1, GAP, false, MIR>(d, log_base, s);
-  if (n <= 1024) return launch_one<256, 4, GAP, false, MIR>(d, log_base, s);
+  if (nt == 1024) {
+    if (n <= 1024) return launch_one<1024, 1, GAP, false, MIR>(d, log_base, s);
+    if (n <= 2048) return launch_one<1024, 2, GAP, false, MIR>(d, log_base, s);
+    if (n <= 4096) return launch_one<1024, 4, GAP, false, MIR>(d, log_base, s);
+  }
+  if (nt == 256) {
+    if (n <= 1024) return launch_one<256, 4, GAP, false, MIR>(d, log_base, s);
+  }
+  if (n <= 512) return launch_one<512, 1, GAP, false, MIR>(d, log_base, s);
+  if (n <= 1024) return launch_one<512, 2, GAP, false, MIR>(d, log_base, s);
+  if (n <= 2048) return launch_one<512, 4, GAP, false, MIR>(d, log_base, s);
   if (n <= 4096) return launch_one<512, 8, GAP, false, MIR>(d, log_base, s);
   return launch_one<1024, 8, GAP, false, MIR>(d, log_base, s);
 }

@@ -36,7 +36,9 @@ struct JDesc {
   int n, ld;
   double* diag;                 // [n]
   double* bs; int* ba; double* bv; int* bst;   // per-row selection cache
+  double* bu;                   // per row: upper bound of the row's scores off its best column
   double* cb; int* ca; int* cst;               // per-row certificate (L) cache, greedy only
+  double* cu;                   // certificate analogue of bu
   double* off2;                 // [n] sum_{l != k} a_kl^2
   int* ts;                      // [n] rotation number that last wrote row k (0 = input)
   RotEntry* log;                // rotation log

@@ -137,11 +137,22 @@ def test_one_rotation_diagonalises_2x2():
         assert np.allclose(v.T @ m @ v, r.a, atol=8 * U * scale)
 
 
-def test_rotation_small_angle_and_overflow_guard():
-    t, c, s = O.rotation(1.0, 1.0, 0.3)       # equal diagonal: 45 degrees, sgn(0) = +1
+def test_rotation_small_angle_and_extremes():
+    t, c, s = O.rotation(1.0, 1.0, 0.3)       # equal diagonal: 45 degrees
     assert t == 1.0 and c == pytest.approx(np.sqrt(0.5), rel=2 * U) and s == c
-    t, c, s = O.rotation(1e300, -1e300, 1e-300)  # |theta| beyond 2^500
+    t, c, s = O.rotation(1.0, 1.0, -0.3)
+    assert t == -1.0 and s == -c
+    t, c, s = O.rotation(1e300, -1e300, 1e-300)  # a huge gap: the rotation is the identity
     assert c == 1.0 and np.isfinite(t) and abs(t) < 1e-300
+    # t solves t^2 + 2 theta t - 1 = 0 (theta = (app - aqq)/(2 apq)) and |t| <= 1
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        app, aqq = rng.uniform(-2, 2, 2)
+        apq = rng.choice([1.0, 1e-6]) * rng.standard_normal()
+        t, c, s = O.rotation(app, aqq, apq)
+        th = mpmath.mpf(app - aqq) / (2 * mpmath.mpf(apq))
+        assert abs(t * t + 2 * th * t - 1) <= 1e-14 * max(1, abs(th * t))
+        assert abs(t) <= 1.0
     for args in [(2.0, 1.0, 0.5), (1.0, 2.0, 0.5), (1.0, 2.0, -0.5), (3.0, -1.0, 2.0)]:
         t, c, s = O.rotation(*args)
         assert abs(t) <= 1.0 and c * c + s * s == pytest.approx(1.0, abs=4 * U)
