@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-compare", action="store_true", help="skip greedy / plain Jacobi")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for counter runs: one device copy of 256 MiB (a reference kernel of "
+                         "known traffic) followed by one solve, no timing output")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the FP64 Jacobi phase of one matrix does not "
@@ -161,6 +164,15 @@ def main():
     tol = 10 * n * U * lam2 / float(np.linalg.norm(prob.a))
     a = torch.from_numpy(prob.a).to("cuda:0")
     torch.cuda.synchronize()
+    if args.profile_run:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        r, ms = solve(J, a, tol, "gap", "fp32")
+        log(f"profile run: copy 268435456 B; solve {ms:.1f} ms, {r.stats['rotations']} rotations")
+        return
 
     for i in range(args.warmup):
         r, ms = solve(J, a, tol, "gap", "fp32")
