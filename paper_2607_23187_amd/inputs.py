@@ -174,6 +174,19 @@ def c5_problem(i: int, n: int, seed: int = SEED_C5) -> Problem:
     return Problem(from_spectrum(lam, rng), np.sort(lam), f"c5_{i}_n{n}")
 
 
+def nearly_diagonal(n: int, seed: int, eps: float = 1e-7, spectrum: str = "c2") -> Problem:
+    """A matrix shaped like the output of a low-precision preconditioner: the diagonal is a
+    spectrum (the recipe of the 1024-size benchmark by default, clusters of 8 otherwise) and
+    the off-diagonal entries are symmetric N(0, (eps * ||lam||_inf)^2).  ``lam`` is the
+    diagonal, not the exact spectrum."""
+    rng = rng_for(seed)
+    lam = spectrum_c2(n, rng) if spectrum == "c2" else spectrum_clusters(n, 8, rng)
+    e = rng.standard_normal((n, n)) * (eps * float(np.max(np.abs(lam))))
+    a = 0.5 * (e + e.T)
+    a[np.diag_indices(n)] = lam
+    return Problem(np.ascontiguousarray(a), np.sort(lam), f"nearly_diagonal_{spectrum}_n{n}")
+
+
 def random_symmetric(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """Dense symmetric matrix with N(0, scale^2) entries (no special spectrum)."""
     rng = rng_for(seed)
