@@ -1,8 +1,9 @@
 // Host side of the C ABI declared in include/jacobi.h: argument checking, the per-device
 // workspace pool and the order of the phases of one solve:
 //   1. symmetric FP64 copy of the upper triangle, finiteness check, ||A||_F
-//   2. (FP32 preconditioner) parallel cyclic FP32 Jacobi -> V_l, FP64 Newton-Schulz -> Q,
-//      A_hat = Q^T (A Q) on the matrix cores, symmetrised                     (Sec. 2.1)
+//   2. (FP32 preconditioner) blocked parallel FP32 Jacobi -> V_l, FP64 Newton-Schulz -> Q;
+//      a refinement pass repeats this on fl32(Q^T A Q); A_hat = Q^T (A Q) on the matrix
+//      cores, symmetrised                                                       (Sec. 2.1)
 //   3. initial per-row scores, persistent pivoted Jacobi (greedy or eq. (1)), stop rule of
 //      Theorem 1 (or off-norm / raw score); the rotation log is drained into V = Q G_1 G_2...
 //   4. one Newton-Schulz polish of V, eigenvalues sorted ascending, V permuted to match.
@@ -57,6 +58,13 @@ long long log_cap_for(int n, long long maxrot) {
 }
 
 long long default_maxrot(int n) { return 40ll * n * n + 64; }
+
+// FP32 sweep stop rules.  The first pass works on fl32(A), whose rounding puts a floor of
+// about u_32 ||A||_F under off(A32): stop at 2^-22 ||A||_F or when a sweep stops helping.
+// A refinement pass works on a nearly diagonal fl32(Q^T A Q) whose off-diagonal entries FP32
+// holds with full relative precision; it sweeps until a sweep no longer halves off(A32).
+constexpr double kF32Tol1 = 0x1p-22, kF32Rho1 = 1.0;
+constexpr double kF32Tol2 = 0.0, kF32Rho2 = 0.5;
 
 // Workspace carving for one problem of size n.
 struct WS {
@@ -228,7 +236,8 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
     // pass 1: FP32 decomposition of fl32(A) -> B1, Newton-Schulz -> X
     double* X = w.Q;
     double* Xo = w.X;
-    HIPCHK(run_precond_f32(w.Asym, n, ld, X, ld, w.f32, o.fp32_max_sweeps, &sw, s));
+    HIPCHK(run_precond_f32(w.Asym, n, ld, X, ld, w.f32, o.fp32_max_sweeps, kF32Tol1, kF32Rho1,
+                           &sw, s));
     sweeps += sw;
     int r = orthonormalize(X, Xo, w.R, n, ld, w.rowsq, w.scal, s);
     if (r) return r;
@@ -237,7 +246,8 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
       HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
       HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
       HIPCHK(launch_symmetrize(w.A, n, ld, s));
-      HIPCHK(run_precond_f32(w.A, n, ld, w.T, ld, w.f32, o.fp32_max_sweeps, &sw, s));
+      HIPCHK(run_precond_f32(w.A, n, ld, w.T, ld, w.f32, o.fp32_max_sweeps, kF32Tol2, kF32Rho2,
+                             &sw, s));
       sweeps += sw;
       HIPCHK(launch_dgemm(n, 0, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, Xo, ld, s));
       std::swap(X, Xo);

@@ -81,8 +81,10 @@ hipError_t launch_fro2(const double* A, int n, int ld, double* partial, double* 
 
 // FP32 preconditioner.
 size_t precond_f32_bytes(int n);
+// Sweeps stop at off(A32) <= tol ||A32||_F, when a sweep leaves off(A32) >= rho times its
+// value before the sweep, or after max_sweeps.
 hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq,
-                           void* scratch, int max_sweeps, int* sweeps, hipStream_t s);
-hipError_t launch_f64_to_f32(const double* A, int n, int lda, float* B, int ldb, hipStream_t s);
+                           void* scratch, int max_sweeps, double tol, double rho, int* sweeps,
+                           hipStream_t s);
 
 }  // namespace je

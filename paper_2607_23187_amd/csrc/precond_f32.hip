@@ -1,126 +1,278 @@
-// Low-precision spectral decomposition of the preconditioner (Sec. 2.1): a parallel
-// cyclic two-sided Jacobi in FP32 followed (in the host driver) by FP64 Newton-Schulz
-// re-orthogonalisation of the eigenvector matrix.
+// Low-precision spectral decomposition of the preconditioner (Sec. 2.1): a blocked
+// two-sided Jacobi in FP32 (the eigenvector matrix is re-orthogonalised in FP64 by the host
+// driver afterwards).
 //
-// Ordering: round-robin (circle method).  The matrix is kept in "pair order": in every
-// round the pairs are the storage positions (2a, 2a+1), a = 0..m-1, m = n2/2 (n2 = n
-// rounded up to even; an odd n gets one zero dummy index whose rotations are the
-// identity).  One kernel per round applies all m disjoint rotations,
-// A <- J^T A J and V <- V J, and writes the result permuted for the next round: position
-// 0 stays, the top positions (even) move one pair to the right, the bottom positions (odd)
-// one pair to the left, with the circle closing at both ends.  After n2 - 1 rounds every
-// pair of indices has met once (one sweep).  Every 2x2 block is read and written as two
-// float2 values, so all traffic is coalesced.
+// The matrix (padded with zero rows/columns to np = a multiple of 64) is split into
+// 32-row blocks.  A sweep visits every pair of blocks once in round-robin (circle method)
+// order: nb - 1 rounds of nb/2 disjoint block pairs.  For each pair (I, J) of a round one
+// workgroup diagonalises the 64 x 64 subproblem [[A_II, A_IJ], [A_JI, A_JJ]] in LDS with
+// the same scalar Jacobi rotations in FP32 (parallel round-robin inside the block),
+// accumulating its orthogonal factor U_IJ; then every 64 x 64 block of A is replaced by
+// U_P^T A_PR U_R and the columns of V by V U_R.  Each round reads and writes A and V once,
+// so a sweep costs nb - 1 passes over memory instead of np - 1.  For n <= 64 the single
+// block pair is the whole matrix and the subproblem solve is the whole decomposition.
 #include <hip/hip_runtime.h>
+
+#include <vector>
 
 #include "device_common.h"
 #include "kernels.h"
 
 namespace je {
 
-// New storage position of the index at position x after one round (m pairs).
-__device__ __host__ __forceinline__ int rr_next(int x, int m) {
-  if (m == 1) return x;
-  if (x == 0) return 0;
-  if (x & 1) {
-    int a = (x - 1) >> 1;
-    return a == 0 ? 2 : x - 2;
-  }
-  int a = x >> 1;
-  return a == m - 1 ? 2 * m - 1 : x + 2;
+constexpr int PB = 32;          // block rows
+constexpr int PM = 64;          // subproblem size (two blocks)
+constexpr int PL = PM + 4;      // LDS row stride (floats), rows stay 16-byte aligned
+
+// Index pair k of round r of the circle method on 64 indices (index 63 fixed).
+__device__ __forceinline__ void circle64(int r, int k, int& p, int& q) {
+  int x, y;
+  if (k == 0) { x = 63; y = r; }
+  else { x = (r + k) % 63; y = (r - k + 63) % 63; }
+  p = min(x, y);
+  q = max(x, y);
 }
 
-struct PairRot {
-  float c, s, t, app, aqq, apq;
-};
-
-__device__ __forceinline__ PairRot pair_rot(const float* __restrict__ A, int ld, int a) {
-  PairRot r;
-  const float2 d0 = *reinterpret_cast<const float2*>(A + (size_t)(2 * a) * ld + 2 * a);
-  const float2 d1 = *reinterpret_cast<const float2*>(A + (size_t)(2 * a + 1) * ld + 2 * a);
-  r.app = d0.x;
-  r.apq = d0.y;
-  r.aqq = d1.y;
-  if (r.apq == 0.0f) {
-    r.c = 1.0f; r.s = 0.0f; r.t = 0.0f;
-  } else {
-    rot_params<float>(r.app, r.aqq, r.apq, r.t, r.c, r.s);
-  }
-  return r;
+__device__ __forceinline__ int blk_row(int I, int J, int i) {
+  return i < PB ? I * PB + i : J * PB + (i - PB);
 }
 
-// Blocks [0, nbA) update 16 x 16 pair-blocks of A; blocks [nbA, ...) update V.
-__global__ __launch_bounds__(256) void k_rr_round(const float* __restrict__ Ain,
-                                                  float* __restrict__ Aout, int ld,
-                                                  const float* __restrict__ Vin,
-                                                  float* __restrict__ Vout, int ldv, int nrows,
-                                                  int m, int nbA1, int nbA) {
-  __shared__ PairRot rr[16], rc[16];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  int bid = blockIdx.x;
-  if (bid < nbA) {
-    const int ba = bid / nbA1, bb = bid - ba * nbA1;
-    if (threadIdx.x < 16) {
-      int a = ba * 16 + threadIdx.x;
-      if (a < m) rr[threadIdx.x] = pair_rot(Ain, ld, a);
-    } else if (threadIdx.x < 32) {
-      int b = bb * 16 + threadIdx.x - 16;
-      if (b < m) rc[threadIdx.x - 16] = pair_rot(Ain, ld, b);
-    }
-    __syncthreads();
-    const int a = ba * 16 + ty, b = bb * 16 + tx;
-    if (a >= m || b >= m) return;
-    const PairRot& R = rr[ty];
-    const PairRot& Cc = rc[tx];
-    float o00, o01, o10, o11;
-    if (a == b) {
-      o00 = R.app + R.t * R.apq;
-      o11 = R.aqq - R.t * R.apq;
-      o01 = 0.0f;
-      o10 = 0.0f;
-    } else {
-      const float2 m0 = *reinterpret_cast<const float2*>(Ain + (size_t)(2 * a) * ld + 2 * b);
-      const float2 m1 = *reinterpret_cast<const float2*>(Ain + (size_t)(2 * a + 1) * ld + 2 * b);
-      // rows: G_a^T M
-      const float r00 = R.c * m0.x + R.s * m1.x, r01 = R.c * m0.y + R.s * m1.y;
-      const float r10 = R.c * m1.x - R.s * m0.x, r11 = R.c * m1.y - R.s * m0.y;
-      // columns: (G_a^T M) G_b
-      o00 = Cc.c * r00 + Cc.s * r01;
-      o01 = Cc.c * r01 - Cc.s * r00;
-      o10 = Cc.c * r10 + Cc.s * r11;
-      o11 = Cc.c * r11 - Cc.s * r10;
-    }
-    const int ra = rr_next(2 * a, m), rb = rr_next(2 * a + 1, m);
-    const int ca = rr_next(2 * b, m), cb = rr_next(2 * b + 1, m);
-    Aout[(size_t)ra * ld + ca] = o00;
-    Aout[(size_t)ra * ld + cb] = o01;
-    Aout[(size_t)rb * ld + ca] = o10;
-    Aout[(size_t)rb * ld + cb] = o11;
-    return;
-  }
-  // V part: block covers 16 rows x 16 column pairs
-  bid -= nbA;
-  const int nbc = (m + 15) / 16;
-  const int bi = bid / nbc, bb = bid - bi * nbc;
-  if (threadIdx.x < 16) {
-    int b = bb * 16 + threadIdx.x;
-    if (b < m) rc[threadIdx.x] = pair_rot(Ain, ld, b);
+// One workgroup per block pair: Jacobi on the 64 x 64 subproblem in LDS.  The solved block
+// goes back into A (upper triangle, mirrored, so A stays exactly symmetric) and its
+// orthogonal factor U = product of the rotations into U.  Every rotation ends like the
+// scalar method's: the pivot entry becomes exactly 0 and the diagonal app + t apq,
+// aqq - t apq, so the diagonal blocks keep the entry-wise accuracy of scalar Jacobi.
+//
+// A rotation is skipped when both a_pq and a_pp - a_qq are at the rounding level of the
+// diagonal (|.| <= 2^-22 (|a_pp| + |a_qq|)): FP32 cannot tell such eigenvalues apart, its
+// rotation angle would be set by rounding noise, and the large noise-driven rotations
+// inside a cluster would keep re-mixing the cluster's couplings to the rest of the matrix,
+// so that they only decay linearly.  Those entries are left for the FP64 phase.
+constexpr int SNT = 512;
+constexpr float kNoise = 0x1p-22f;
+
+__device__ __forceinline__ bool f32_noise_pair(float app, float aqq, float apq) {
+  const float nz = kNoise * (fabsf(app) + fabsf(aqq));
+  return fabsf(app - aqq) <= nz && fabsf(apq) <= nz;
+}
+
+__global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int np,
+                                                     const int2* __restrict__ pairs,
+                                                     float* __restrict__ U, int inner_max,
+                                                     float tol2, float rho2) {
+  __shared__ __align__(16) float S[PM][PL];
+  __shared__ __align__(16) float Um[PM][PL];
+  __shared__ float cs_c[32], cs_s[32], cs_dp[32], cs_dq[32], cs_z[32];
+  __shared__ int cs_p[32], cs_q[32];
+  __shared__ float red[2][SNT / 64];
+  const int tid = threadIdx.x;
+  const int2 pr = pairs[blockIdx.x];
+  for (int e = tid; e < PM * PM; e += SNT) {
+    int i = e / PM, j = e % PM;
+    S[i][j] = A[(size_t)blk_row(pr.x, pr.y, i) * np + blk_row(pr.x, pr.y, j)];
+    Um[i][j] = (i == j) ? 1.0f : 0.0f;
   }
   __syncthreads();
-  const int i = bi * 16 + ty, b = bb * 16 + tx;
-  if (i >= nrows || b >= m) return;
-  const PairRot& Cc = rc[tx];
-  const float2 v = *reinterpret_cast<const float2*>(Vin + (size_t)i * ldv + 2 * b);
-  Vout[(size_t)i * ldv + rr_next(2 * b, m)] = Cc.c * v.x + Cc.s * v.y;
-  Vout[(size_t)i * ldv + rr_next(2 * b + 1, m)] = Cc.c * v.y - Cc.s * v.x;
+  // row phase: pair kb, columns jb .. jb+3; column phase: pair kc, rows ic .. ic+3
+  const int kb = tid >> 4, jb = (tid & 15) * 4;
+  const int kc = tid & 31, ic = (tid >> 5) * 4;
+  float prev_off = 3.4e38f;
+  for (int sw = 0; sw < inner_max; ++sw) {
+    for (int r = 0; r < 63; ++r) {
+      if (tid < 32) {
+        int p, q;
+        circle64(r, tid, p, q);
+        float app = S[p][p], aqq = S[q][q], apq = S[p][q], c = 1.0f, s = 0.0f;
+        const bool skip = apq == 0.0f || f32_noise_pair(app, aqq, apq);
+        if (!skip) {
+          float t;
+          rot_params<float>(app, aqq, apq, t, c, s);
+          app = app + t * apq;
+          aqq = aqq - t * apq;
+        }
+        cs_c[tid] = c; cs_s[tid] = s; cs_p[tid] = p; cs_q[tid] = q;
+        cs_dp[tid] = app;
+        cs_dq[tid] = aqq;
+        cs_z[tid] = skip ? apq : 0.0f;
+      }
+      __syncthreads();
+      {
+        const int p = cs_p[kb], q = cs_q[kb];
+        const float c = cs_c[kb], s = cs_s[kb];
+        float4 x = *reinterpret_cast<const float4*>(&S[p][jb]);
+        float4 y = *reinterpret_cast<const float4*>(&S[q][jb]);
+        float4 xo, yo;
+        xo.x = c * x.x + s * y.x; yo.x = c * y.x - s * x.x;
+        xo.y = c * x.y + s * y.y; yo.y = c * y.y - s * x.y;
+        xo.z = c * x.z + s * y.z; yo.z = c * y.z - s * x.z;
+        xo.w = c * x.w + s * y.w; yo.w = c * y.w - s * x.w;
+        *reinterpret_cast<float4*>(&S[p][jb]) = xo;
+        *reinterpret_cast<float4*>(&S[q][jb]) = yo;
+      }
+      __syncthreads();
+      {
+        const int p = cs_p[kc], q = cs_q[kc];
+        const float c = cs_c[kc], s = cs_s[kc];
+        float sx[4], sy[4], ux[4], uy[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          sx[k] = S[ic + k][p]; sy[k] = S[ic + k][q];
+          ux[k] = Um[ic + k][p]; uy[k] = Um[ic + k][q];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = ic + k;
+          float op = c * sx[k] + s * sy[k], oq = c * sy[k] - s * sx[k];
+          if (i == p) { op = cs_dp[kc]; oq = cs_z[kc]; }
+          if (i == q) { op = cs_z[kc]; oq = cs_dq[kc]; }
+          S[i][p] = op;
+          S[i][q] = oq;
+          Um[i][p] = c * ux[k] + s * uy[k];
+          Um[i][q] = c * uy[k] - s * ux[k];
+        }
+      }
+      __syncthreads();
+    }
+    if (sw + 1 < inner_max) {
+      // off(S) and ||S||_F decide whether another inner sweep pays
+      float so = 0.0f, sd = 0.0f;
+      for (int e = tid; e < PM * PM; e += SNT) {
+        int i = e / PM, j = e % PM;
+        float v = S[i][j] * S[i][j];
+        if (i == j) sd += v; else so += v;
+      }
+      for (int o = 32; o > 0; o >>= 1) { so += __shfl_xor(so, o); sd += __shfl_xor(sd, o); }
+      if ((tid & 63) == 0) { red[0][tid >> 6] = so; red[1][tid >> 6] = sd; }
+      __syncthreads();
+      float off = 0.0f, dg = 0.0f;
+      for (int w = 0; w < SNT / 64; ++w) { off += red[0][w]; dg += red[1][w]; }
+      __syncthreads();
+      if (off <= tol2 * (off + dg) || off >= rho2 * prev_off) break;
+      prev_off = off;
+    }
+  }
+  float* Uo = U + (size_t)blockIdx.x * PM * PM;
+  for (int e = tid; e < PM * PM; e += SNT) {
+    int i = e / PM, j = e % PM;
+    Uo[e] = Um[i][j];
+    float v = (i <= j) ? S[i][j] : S[j][i];
+    A[(size_t)blk_row(pr.x, pr.y, i) * np + blk_row(pr.x, pr.y, j)] = v;
+  }
 }
 
-// A32 (n2 x n2, zero padded) <- fl32(A)
+// Block update of A for block pairs P < R: A_PR <- U_P^T A_PR U_R, mirrored to A_RP (so A
+// stays exactly symmetric).  The diagonal pair blocks were written by the subproblem solve.
+__global__ __launch_bounds__(256) void k_block_apply_a(float* __restrict__ A, int np,
+                                                       const int2* __restrict__ pairs,
+                                                       const float* __restrict__ U, int nb2) {
+  __shared__ __align__(16) float Up[PM][PL], Ur[PM][PL], Ab[PM][PL];
+  const int tid = threadIdx.x;
+  // blockIdx.x enumerates P < R
+  int b = blockIdx.x, P = 0;
+  while (b >= nb2 - 1 - P) { b -= nb2 - 1 - P; ++P; }
+  const int R = P + 1 + b;
+  const int2 pp = pairs[P], pr = pairs[R];
+  const float* Ug = U + (size_t)P * PM * PM;
+  const float* Uh = U + (size_t)R * PM * PM;
+  for (int e = tid; e < PM * PM; e += 256) {
+    int i = e / PM, j = e % PM;
+    Up[i][j] = Ug[e];
+    Ur[i][j] = Uh[e];
+    Ab[i][j] = A[(size_t)blk_row(pp.x, pp.y, i) * np + blk_row(pr.x, pr.y, j)];
+  }
+  __syncthreads();
+  const int ti = (tid >> 4) * 4, tj = (tid & 15) * 4;
+  float acc[4][4];
+  // T = U_P^T A_PR
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
+  for (int k = 0; k < PM; ++k) {
+    float4 u = *reinterpret_cast<const float4*>(&Up[k][ti]);
+    float4 x = *reinterpret_cast<const float4*>(&Ab[k][tj]);
+    float uu[4] = {u.x, u.y, u.z, u.w}, xx[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(uu[a], xx[c], acc[a][c]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Ab[ti + a][tj + c] = acc[a][c];
+  __syncthreads();
+  // out = T U_R
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
+  for (int k = 0; k < PM; ++k) {
+    float4 u = *reinterpret_cast<const float4*>(&Ur[k][tj]);
+    float uu[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      float t = Ab[ti + a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(t, uu[c], acc[a][c]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int gi = blk_row(pp.x, pp.y, ti + a), gj = blk_row(pr.x, pr.y, tj + c);
+      A[(size_t)gi * np + gj] = acc[a][c];
+      A[(size_t)gj * np + gi] = acc[a][c];
+    }
+}
+
+// V <- V U_R on the columns of block pair R, for a tile of 64 rows.
+__global__ __launch_bounds__(256) void k_block_apply_v(float* __restrict__ V, int nrows, int np,
+                                                       const int2* __restrict__ pairs,
+                                                       const float* __restrict__ U) {
+  __shared__ __align__(16) float Ur[PM][PL], Vb[PM][PL];
+  const int tid = threadIdx.x;
+  const int R = blockIdx.y, r0 = blockIdx.x * PM;
+  const int2 pr = pairs[R];
+  const float* Uh = U + (size_t)R * PM * PM;
+  for (int e = tid; e < PM * PM; e += 256) {
+    int i = e / PM, j = e % PM;
+    Ur[i][j] = Uh[e];
+    Vb[i][j] = (r0 + i < nrows) ? V[(size_t)(r0 + i) * np + blk_row(pr.x, pr.y, j)] : 0.0f;
+  }
+  __syncthreads();
+  const int ti = (tid >> 4) * 4, tj = (tid & 15) * 4;
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
+  for (int k = 0; k < PM; ++k) {
+    float4 u = *reinterpret_cast<const float4*>(&Ur[k][tj]);
+    float uu[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      float t = Vb[ti + a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(t, uu[c], acc[a][c]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (r0 + ti + a < nrows)
+        V[(size_t)(r0 + ti + a) * np + blk_row(pr.x, pr.y, tj + c)] = acc[a][c];
+}
+
+// A32 (np x np, zero padded) <- fl32(A)
 __global__ void k_to_f32_pad(const double* __restrict__ A, int n, int lda, float* __restrict__ B,
-                             int n2) {
+                             int np) {
   size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)n2 * n2) return;
-  int i = (int)(idx / n2), j = (int)(idx - (size_t)i * n2);
+  if (idx >= (size_t)np * np) return;
+  int i = (int)(idx / np), j = (int)(idx - (size_t)i * np);
   B[idx] = (i < n && j < n) ? (float)A[(size_t)i * lda + j] : 0.0f;
 }
 
@@ -131,30 +283,30 @@ __global__ void k_identity_f32(float* V, int nrows, int ldv) {
   V[idx] = (i == j) ? 1.0f : 0.0f;
 }
 
-// off(A)^2 and ||A||_F^2 of an n2 x n2 FP32 matrix (double accumulation, fixed order).
-__global__ __launch_bounds__(256) void k_off_norm_f32(const float* __restrict__ A, int n2,
+// off(A)^2 and ||A||_F^2 of an np x np FP32 matrix (double accumulation, fixed order).
+__global__ __launch_bounds__(256) void k_off_norm_f32(const float* __restrict__ A, int np,
                                                       double* __restrict__ partial) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= n2) return;
+  if (row >= np) return;
   double so = 0.0, sd = 0.0;
-  for (int l = lane; l < n2; l += 64) {
-    double v = A[(size_t)row * n2 + l];
+  for (int l = lane; l < np; l += 64) {
+    double v = A[(size_t)row * np + l];
     if (l == row) sd += v * v;
     else so += v * v;
   }
-  so = wave_sum_d(so);
-  sd = wave_sum_d(sd);
+  so = wave_sum_fast(so);
+  sd = wave_sum_fast(sd);
   if (lane == 0) { partial[2 * row] = so; partial[2 * row + 1] = sd; }
 }
 
-__global__ __launch_bounds__(256) void k_off_norm_sum(const double* __restrict__ partial, int n2,
+__global__ __launch_bounds__(256) void k_off_norm_sum(const double* __restrict__ partial, int np,
                                                       double* out) {
   __shared__ double w[2][4];
   double so = 0.0, sd = 0.0;
-  for (int k = threadIdx.x; k < n2; k += 256) { so += partial[2 * k]; sd += partial[2 * k + 1]; }
-  so = wave_sum_d(so);
-  sd = wave_sum_d(sd);
+  for (int k = threadIdx.x; k < np; k += 256) { so += partial[2 * k]; sd += partial[2 * k + 1]; }
+  so = wave_sum_fast(so);
+  sd = wave_sum_fast(sd);
   if ((threadIdx.x & 63) == 0) { w[0][threadIdx.x >> 6] = so; w[1][threadIdx.x >> 6] = sd; }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -165,100 +317,95 @@ __global__ __launch_bounds__(256) void k_off_norm_sum(const double* __restrict__
   }
 }
 
-// Q (n x n, FP64, row-major) <- columns of V32 at positions colmap[0..n)
-__global__ void k_gather_q(const float* __restrict__ V, int n, int ldv, const int* __restrict__ colmap,
-                           double* __restrict__ Q, int ldq) {
+// Q (n x n, FP64, row-major) <- the first n columns of V32
+__global__ void k_gather_q(const float* __restrict__ V, int n, int ldv, double* __restrict__ Q,
+                           int ldq) {
   size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * n) return;
   int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
-  Q[(size_t)i * ldq + j] = (double)V[(size_t)i * ldv + colmap[j]];
+  Q[(size_t)i * ldq + j] = (double)V[(size_t)i * ldv + j];
 }
 
+static int padded(int n) { return (n + PM - 1) / PM * PM; }
+
 size_t precond_f32_bytes(int n) {
-  size_t n2 = (size_t)(n + (n & 1));
-  size_t b = 2 * n2 * n2 * 4 + 2 * (size_t)n * n2 * 4;  // A32 x2, V32 x2
-  b += 2 * n2 * 8 + 64;                                  // partial sums + result
-  b += (size_t)n * 4 + 256;                              // column map
-  return (b + 255) & ~(size_t)255;
+  size_t np = (size_t)padded(n), nb = np / PB;
+  size_t b = np * np * 4 + (size_t)n * np * 4;   // A32, V32
+  b += (nb / 2) * PM * PM * 4;                    // U of every block pair of a round
+  b += (nb - 1 > 0 ? nb - 1 : 1) * (nb / 2) * 8;  // pair table of all rounds
+  b += 2 * np * 8 + 256;                          // partial sums + result
+  return (b + 4095) & ~(size_t)4095;
 }
 
 hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq, void* scratch,
-                           int max_sweeps, int* sweeps, hipStream_t s) {
-  const int n2 = n + (n & 1), m = n2 / 2;
+                           int max_sweeps, double tol, double rho, int* sweeps, hipStream_t s) {
+  const int np = padded(n), nb = np / PB, nb2 = nb / 2, rounds = nb - 1;
   char* p = (char*)scratch;
-  float* A0 = (float*)p; p += (size_t)n2 * n2 * 4;
-  float* A1 = (float*)p; p += (size_t)n2 * n2 * 4;
-  float* V0 = (float*)p; p += (size_t)n * n2 * 4;
-  float* V1 = (float*)p; p += (size_t)n * n2 * 4;
-  double* part = (double*)p; p += 2 * (size_t)n2 * 8;
-  double* res = (double*)p; p += 64;
-  int* colmap = (int*)p;
+  float* A32 = (float*)p; p += (size_t)np * np * 4;
+  float* V32 = (float*)p; p += (size_t)n * np * 4;
+  float* U = (float*)p; p += (size_t)nb2 * PM * PM * 4;
+  int2* pairs = (int2*)p; p += (size_t)rounds * nb2 * 8;
+  double* part = (double*)p; p += 2 * (size_t)np * 8;
+  double* res = (double*)p;
   hipError_t e;
+  // circle-method block pairs of every round (block nb - 1 fixed)
+  std::vector<int2> tab((size_t)rounds * nb2);
+  for (int r = 0; r < rounds; ++r)
+    for (int k = 0; k < nb2; ++k) {
+      int x, y;
+      if (k == 0) { x = nb - 1; y = r; }
+      else { x = (r + k) % (nb - 1); y = (r - k + (nb - 1)) % (nb - 1); }
+      tab[(size_t)r * nb2 + k] = int2{x < y ? x : y, x < y ? y : x};
+    }
+  if ((e = hipMemcpyAsync(pairs, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return e;
   {
-    size_t tot = (size_t)n2 * n2;
+    size_t tot = (size_t)np * np;
     hipLaunchKernelGGL(k_to_f32_pad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Asym,
-                       n, ld, A0, n2);
-    size_t totv = (size_t)n * n2;
-    hipLaunchKernelGGL(k_identity_f32, dim3((unsigned)((totv + 255) / 256)), dim3(256), 0, s, V0,
-                       n, n2);
+                       n, ld, A32, np);
+    size_t totv = (size_t)n * np;
+    hipLaunchKernelGGL(k_identity_f32, dim3((unsigned)((totv + 255) / 256)), dim3(256), 0, s, V32,
+                       n, np);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // position -> index bookkeeping on the host (to find the dummy column for odd n)
-  int* pos_idx = new int[n2];
-  int* tmp = new int[n2];
-  for (int x = 0; x < n2; ++x) pos_idx[x] = x;
-  const int nb1 = (m + 15) / 16;
-  const int nbA = nb1 * nb1;
-  const int nbV = ((n + 15) / 16) * nb1;
   double h[2];
-  hipLaunchKernelGGL(k_off_norm_f32, dim3((n2 + 3) / 4), dim3(256), 0, s, A0, n2, part);
-  hipLaunchKernelGGL(k_off_norm_sum, dim3(1), dim3(256), 0, s, part, n2, res);
-  if ((e = hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) goto out;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) goto out;
-  {
-    double off = h[0], nrm = h[1];
-    const double tol = 0x1p-22;
-    int sw = 0;
-    while (sw < max_sweeps && off > tol * nrm) {
-      for (int r = 0; r < n2 - 1; ++r) {
-        hipLaunchKernelGGL(k_rr_round, dim3(nbA + nbV), dim3(256), 0, s, A0, A1, n2, V0, V1, n2, n,
-                           m, nb1, nbA);
-        float* t = A0; A0 = A1; A1 = t;
-        t = V0; V0 = V1; V1 = t;
-        for (int x = 0; x < n2; ++x) tmp[rr_next(x, m)] = pos_idx[x];
-        for (int x = 0; x < n2; ++x) pos_idx[x] = tmp[x];
-      }
-      if ((e = hipGetLastError()) != hipSuccess) goto out;
-      ++sw;
-      hipLaunchKernelGGL(k_off_norm_f32, dim3((n2 + 3) / 4), dim3(256), 0, s, A0, n2, part);
-      hipLaunchKernelGGL(k_off_norm_sum, dim3(1), dim3(256), 0, s, part, n2, res);
-      if ((e = hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) goto out;
-      if ((e = hipStreamSynchronize(s)) != hipSuccess) goto out;
-      double prev = off;
-      off = h[0];
-      nrm = h[1];
-      if (off >= prev) break;
+  auto off_norm = [&]() -> hipError_t {
+    hipLaunchKernelGGL(k_off_norm_f32, dim3((np + 3) / 4), dim3(256), 0, s, A32, np, part);
+    hipLaunchKernelGGL(k_off_norm_sum, dim3(1), dim3(256), 0, s, part, np, res);
+    hipError_t r = hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, s);
+    if (r == hipSuccess) r = hipStreamSynchronize(s);
+    return r;
+  };
+  if ((e = off_norm()) != hipSuccess) return e;
+  double off = h[0], nrm = h[1];
+  // a single block pair is the whole matrix: its subproblem solve converges it
+  const int inner = (nb == 2) ? max_sweeps : 1;
+  int sw = 0;
+  while (sw < max_sweeps && off > tol * nrm) {
+    for (int r = 0; r < rounds; ++r) {
+      const int2* pr = pairs + (size_t)r * nb2;
+      hipLaunchKernelGGL(k_block_solve, dim3(nb2), dim3(SNT), 0, s, A32, np, pr, U, inner,
+                         (float)(tol * tol), (float)(rho * rho));
+      if (nb2 > 1)
+        hipLaunchKernelGGL(k_block_apply_a, dim3(nb2 * (nb2 - 1) / 2), dim3(256), 0, s, A32, np,
+                           pr, U, nb2);
+      hipLaunchKernelGGL(k_block_apply_v, dim3((n + PM - 1) / PM, nb2), dim3(256), 0, s, V32, n,
+                         np, pr, U);
     }
-    *sweeps = sw;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    ++sw;
+    double prev = off;
+    if ((e = off_norm()) != hipSuccess) return e;
+    off = h[0];
+    nrm = h[1];
+    if (nb == 2 || off >= rho * prev) break;
   }
-  {
-    int* cm = new int[n];
-    int j = 0;
-    for (int x = 0; x < n2; ++x)
-      if (pos_idx[x] < n) cm[j++] = x;
-    e = hipMemcpyAsync(colmap, cm, (size_t)n * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    delete[] cm;
-    if (e != hipSuccess) goto out;
-    size_t tot = (size_t)n * n;
-    hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V0, n, n2,
-                       colmap, Q, ldq);
-    e = hipGetLastError();
-  }
-out:
-  delete[] pos_idx;
-  delete[] tmp;
-  return e;
+  *sweeps = sw;
+  size_t tot = (size_t)n * n;
+  hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V32, n, np,
+                     Q, ldq);
+  return hipGetLastError();
 }
 
 }  // namespace je
