@@ -11,7 +11,9 @@ Pipeline (Shao & Nakatsukasa, Sec. 2.1 and Algorithm 1):
    decomposition), re-orthogonalised in FP64 by Householder QR with diag(R) > 0 (the
    experiments of Sec. 4 use Householder QR).  With ``passes=2`` (default) the FP32
    decomposition is refined once: FP32 Jacobi again on fl32(Q^T A Q), Q <- QR(Q V_2).
-   Then A_hat = Q^T (A Q), symmetrised;
+   Then A_hat = Q^T (A Q), symmetrised.  The FP32 Jacobi skips pairs that FP32 cannot
+   separate (a_pq and a_pp - a_qq both at the rounding level of the diagonal) and leaves
+   them to the FP64 phase;
 3. FP64 Jacobi on A_hat with greedy or gap-aware pivots (eq. (1)) until the chosen stop
    rule holds (Theorem 1 certificate by default);
 4. V = Q V_J, optionally polished by one Newton-Schulz step; eigenvalues =
@@ -73,7 +75,8 @@ def lib():
                                  ctypes.c_longlong, ctypes.c_int, dp, ip, dp, ctypes.c_longlong,
                                  ctypes.POINTER(_Stats)]
         L.orc_jacobi_f32.restype = ctypes.c_int
-        L.orc_jacobi_f32.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_double]
+        L.orc_jacobi_f32.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double]
         _lib = L
     return _lib
 
@@ -132,14 +135,22 @@ def jacobi(a: np.ndarray, pivot: int = GAP, stop: int = STOP_CERT, thr: float = 
                         st.final_sel, st.final_cert, st.final_off, int(st.status))
 
 
-def jacobi_f32(a: np.ndarray, max_sweeps: int = 20, tol: float = 2.0 ** -22):
-    """Cyclic FP32 Jacobi: returns (A32_final, V32, sweeps)."""
+F32_TOL1, F32_RHO1 = 2.0 ** -22, 1.0   # first pass: FP32 floor of off(fl32(A)), or no progress
+F32_TOL2, F32_RHO2 = 0.0, 0.5          # refinement passes: until a sweep fails to halve off
+
+
+def jacobi_f32(a: np.ndarray, max_sweeps: int = 20, tol: float = F32_TOL1,
+               rho: float = F32_RHO1):
+    """Cyclic FP32 Jacobi: returns (A32_final, V32, sweeps).  Pairs whose a_pq and
+    a_pp - a_qq are both at FP32 rounding level of the diagonal are skipped; sweeps stop at
+    off <= tol ||A32||_F, when a sweep leaves off >= rho times its previous value, or after
+    ``max_sweeps``."""
     a32 = np.array(a, dtype=np.float32, order="C", copy=True)
     n = a32.shape[0]
     v32 = np.empty((n, n), dtype=np.float32)
     fp = ctypes.POINTER(ctypes.c_float)
     sweeps = lib().orc_jacobi_f32(a32.ctypes.data_as(fp), n, v32.ctypes.data_as(fp),
-                                  max_sweeps, tol)
+                                  max_sweeps, tol, rho)
     return a32, v32, sweeps
 
 
@@ -209,7 +220,7 @@ def eigh(a: np.ndarray, tol: float, pivot: int = GAP, precond: str = "fp32",
         for _ in range(passes - 1):
             a1 = q.T @ (a @ q)
             a1 = 0.5 * (a1 + a1.T)
-            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32)
+            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32, tol=F32_TOL2, rho=F32_RHO2)
             sw += sw2
             q = householder_q(q @ v2.astype(np.float64))
         a_hat = q.T @ (a @ q)

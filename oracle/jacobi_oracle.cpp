@@ -328,7 +328,18 @@ int orc_jacobi(double* A, int n, int pivot, int stop, double thr, long long maxr
 // starts at I).  A sweep visits every pair (p, q), p < q, in row order.  Sweeps stop once
 // off(A32) <= tol * ||A32||_F, once a sweep fails to reduce off(A32), or after max_sweeps.
 // Returns the number of sweeps performed.
-int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol) {
+// Cyclic-by-rows FP32 Jacobi (the low-precision decomposition of Sec. 2.1, whose method the
+// paper leaves open).  A pair is skipped when a_pq and a_pp - a_qq both lie within
+// 2^-22 (|a_pp| + |a_qq|): at that level FP32 cannot separate the two eigenvalues and the
+// rotation angle would be decided by rounding; the FP64 phase resolves such pairs.  Sweeps
+// stop at off <= tol ||A32||_F, when a sweep leaves off >= rho times its previous value,
+// or after max_sweeps.
+static bool f32_noise_pair(float app, float aqq, float apq) {
+  float nz = 0x1p-22f * (std::fabs(app) + std::fabs(aqq));
+  return std::fabs(app - aqq) <= nz && std::fabs(apq) <= nz;
+}
+
+int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol, double rho) {
   std::fill(V32, V32 + (size_t)n * n, 0.0f);
   for (int i = 0; i < n; ++i) V32[(size_t)i * n + i] = 1.0f;
   auto off_and_norm = [&](double* off, double* nrm) {
@@ -352,6 +363,7 @@ int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol) {
       for (int q = p + 1; q < n; ++q) {
         float apq = A32[(size_t)p * n + q];
         if (apq == 0.0f) continue;
+        if (f32_noise_pair(A32[(size_t)p * n + p], A32[(size_t)q * n + q], apq)) continue;
         float t, c, s;
         rotation<float>(A32[(size_t)p * n + p], A32[(size_t)q * n + q], apq, &t, &c, &s);
         for (int k = 0; k < n; ++k) {
@@ -378,7 +390,7 @@ int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol) {
     ++sweeps;
     double prev = off;
     off_and_norm(&off, &nrm);
-    if (off >= prev) break;
+    if (off >= rho * prev) break;
   }
   return sweeps;
 }

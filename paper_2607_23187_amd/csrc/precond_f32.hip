@@ -5,9 +5,9 @@
 // The matrix (padded with zero rows/columns to np = a multiple of 64) is split into
 // 32-row blocks.  A sweep visits every pair of blocks once in round-robin (circle method)
 // order: nb - 1 rounds of nb/2 disjoint block pairs.  For each pair (I, J) of a round one
-// workgroup diagonalises the 64 x 64 subproblem [[A_II, A_IJ], [A_JI, A_JJ]] in LDS with
-// the same scalar Jacobi rotations in FP32 (parallel round-robin inside the block),
-// accumulating its orthogonal factor U_IJ; then every 64 x 64 block of A is replaced by
+// workgroup applies scalar FP32 Jacobi rotations (parallel round-robin inside the block)
+// to the 64 x 64 subproblem [[A_II, A_IJ], [A_JI, A_JJ]] in LDS, accumulating its
+// orthogonal factor U_IJ; then every other 64 x 64 block of A is replaced by
 // U_P^T A_PR U_R and the columns of V by V U_R.  Each round reads and writes A and V once,
 // so a sweep costs nb - 1 passes over memory instead of np - 1.  For n <= 64 the single
 // block pair is the whole matrix and the subproblem solve is the whole decomposition.
@@ -43,6 +43,13 @@ __device__ __forceinline__ int blk_row(int I, int J, int i) {
 // scalar method's: the pivot entry becomes exactly 0 and the diagonal app + t apq,
 // aqq - t apq, so the diagonal blocks keep the entry-wise accuracy of scalar Jacobi.
 //
+// With full != 0 an inner sweep visits all 2016 pairs of the subproblem (63 rounds of the
+// circle method); otherwise only the 1024 pairs that couple the two blocks (32 rounds,
+// round r pairing local index a with 32 + (a + r) mod 32).  The first round of every outer
+// sweep is full: its block pairs cover each block once, so every pair inside a block is
+// rotated there, and the later rounds need only the cross pairs: one outer sweep then
+// rotates each index pair once, like a scalar cyclic sweep.
+//
 // A rotation is skipped when both a_pq and a_pp - a_qq are at the rounding level of the
 // diagonal (|.| <= 2^-22 (|a_pp| + |a_qq|)): FP32 cannot tell such eigenvalues apart, its
 // rotation angle would be set by rounding noise, and the large noise-driven rotations
@@ -56,33 +63,48 @@ __device__ __forceinline__ bool f32_noise_pair(float app, float aqq, float apq) 
   return fabsf(app - aqq) <= nz && fabsf(apq) <= nz;
 }
 
+__device__ __forceinline__ void inner_pair(int full, int r, int k, int& p, int& q) {
+  if (full) {
+    circle64(r, k, p, q);
+  } else {
+    p = k;
+    q = PB + ((k + r) & (PB - 1));
+  }
+}
+
 __global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int np,
                                                      const int2* __restrict__ pairs,
                                                      float* __restrict__ U, int inner_max,
-                                                     float tol2, float rho2) {
+                                                     int full, float tol2, float rho2) {
   __shared__ __align__(16) float S[PM][PL];
-  __shared__ __align__(16) float Um[PM][PL];
+  __shared__ __align__(16) float Ut[PM][PL];  // U transposed: Ut[j][i] = U[i][j]
   __shared__ float cs_c[32], cs_s[32], cs_dp[32], cs_dq[32], cs_z[32];
-  __shared__ int cs_p[32], cs_q[32];
   __shared__ float red[2][SNT / 64];
   const int tid = threadIdx.x;
   const int2 pr = pairs[blockIdx.x];
   for (int e = tid; e < PM * PM; e += SNT) {
     int i = e / PM, j = e % PM;
     S[i][j] = A[(size_t)blk_row(pr.x, pr.y, i) * np + blk_row(pr.x, pr.y, j)];
-    Um[i][j] = (i == j) ? 1.0f : 0.0f;
+    Ut[i][j] = (i == j) ? 1.0f : 0.0f;
   }
   __syncthreads();
-  // row phase: pair kb, columns jb .. jb+3; column phase: pair kc, rows ic .. ic+3
+  // row phase: pair kb, columns jb .. jb+3 (the 16 lanes of a pair share one wave);
+  // column phase: pair kc, rows ic .. ic+3
   const int kb = tid >> 4, jb = (tid & 15) * 4;
   const int kc = tid & 31, ic = (tid >> 5) * 4;
+  const int nr = full ? PM - 1 : PB;
   float prev_off = 3.4e38f;
   for (int sw = 0; sw < inner_max; ++sw) {
-    for (int r = 0; r < 63; ++r) {
-      if (tid < 32) {
+    for (int r = 0; r < nr; ++r) {
+      {
         int p, q;
-        circle64(r, tid, p, q);
-        float app = S[p][p], aqq = S[q][q], apq = S[p][q], c = 1.0f, s = 0.0f;
+        inner_pair(full, r, kb, p, q);
+        // every lane of the pair reads the 2x2 block before any lane of it stores
+        float app = S[p][p], aqq = S[q][q];
+        const float apq = S[p][q];
+        const float4 x = *reinterpret_cast<const float4*>(&S[p][jb]);
+        const float4 y = *reinterpret_cast<const float4*>(&S[q][jb]);
+        float c = 1.0f, s = 0.0f;
         const bool skip = apq == 0.0f || f32_noise_pair(app, aqq, apq);
         if (!skip) {
           float t;
@@ -90,17 +112,6 @@ __global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int 
           app = app + t * apq;
           aqq = aqq - t * apq;
         }
-        cs_c[tid] = c; cs_s[tid] = s; cs_p[tid] = p; cs_q[tid] = q;
-        cs_dp[tid] = app;
-        cs_dq[tid] = aqq;
-        cs_z[tid] = skip ? apq : 0.0f;
-      }
-      __syncthreads();
-      {
-        const int p = cs_p[kb], q = cs_q[kb];
-        const float c = cs_c[kb], s = cs_s[kb];
-        float4 x = *reinterpret_cast<const float4*>(&S[p][jb]);
-        float4 y = *reinterpret_cast<const float4*>(&S[q][jb]);
         float4 xo, yo;
         xo.x = c * x.x + s * y.x; yo.x = c * y.x - s * x.x;
         xo.y = c * x.y + s * y.y; yo.y = c * y.y - s * x.y;
@@ -108,17 +119,22 @@ __global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int 
         xo.w = c * x.w + s * y.w; yo.w = c * y.w - s * x.w;
         *reinterpret_cast<float4*>(&S[p][jb]) = xo;
         *reinterpret_cast<float4*>(&S[q][jb]) = yo;
+        if ((tid & 15) == 0) {
+          cs_c[kb] = c; cs_s[kb] = s;
+          cs_dp[kb] = app; cs_dq[kb] = aqq;
+          cs_z[kb] = skip ? apq : 0.0f;
+        }
       }
       __syncthreads();
       {
-        const int p = cs_p[kc], q = cs_q[kc];
+        int p, q;
+        inner_pair(full, r, kc, p, q);
         const float c = cs_c[kc], s = cs_s[kc];
-        float sx[4], sy[4], ux[4], uy[4];
+        float sx[4], sy[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          sx[k] = S[ic + k][p]; sy[k] = S[ic + k][q];
-          ux[k] = Um[ic + k][p]; uy[k] = Um[ic + k][q];
-        }
+        for (int k = 0; k < 4; ++k) { sx[k] = S[ic + k][p]; sy[k] = S[ic + k][q]; }
+        const float4 up = *reinterpret_cast<const float4*>(&Ut[p][ic]);
+        const float4 uq = *reinterpret_cast<const float4*>(&Ut[q][ic]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int i = ic + k;
@@ -127,9 +143,14 @@ __global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int 
           if (i == q) { op = cs_z[kc]; oq = cs_dq[kc]; }
           S[i][p] = op;
           S[i][q] = oq;
-          Um[i][p] = c * ux[k] + s * uy[k];
-          Um[i][q] = c * uy[k] - s * ux[k];
         }
+        float4 po, qo;
+        po.x = c * up.x + s * uq.x; qo.x = c * uq.x - s * up.x;
+        po.y = c * up.y + s * uq.y; qo.y = c * uq.y - s * up.y;
+        po.z = c * up.z + s * uq.z; qo.z = c * uq.z - s * up.z;
+        po.w = c * up.w + s * uq.w; qo.w = c * uq.w - s * up.w;
+        *reinterpret_cast<float4*>(&Ut[p][ic]) = po;
+        *reinterpret_cast<float4*>(&Ut[q][ic]) = qo;
       }
       __syncthreads();
     }
@@ -154,7 +175,7 @@ __global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int 
   float* Uo = U + (size_t)blockIdx.x * PM * PM;
   for (int e = tid; e < PM * PM; e += SNT) {
     int i = e / PM, j = e % PM;
-    Uo[e] = Um[i][j];
+    Uo[e] = Ut[j][i];
     float v = (i <= j) ? S[i][j] : S[j][i];
     A[(size_t)blk_row(pr.x, pr.y, i) * np + blk_row(pr.x, pr.y, j)] = v;
   }
@@ -386,7 +407,7 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
     for (int r = 0; r < rounds; ++r) {
       const int2* pr = pairs + (size_t)r * nb2;
       hipLaunchKernelGGL(k_block_solve, dim3(nb2), dim3(SNT), 0, s, A32, np, pr, U, inner,
-                         (float)(tol * tol), (float)(rho * rho));
+                         r == 0 ? 1 : 0, (float)(tol * tol), (float)(rho * rho));
       if (nb2 > 1)
         hipLaunchKernelGGL(k_block_apply_a, dim3(nb2 * (nb2 - 1) / 2), dim3(256), 0, s, A32, np,
                            pr, U, nb2);
