@@ -63,6 +63,30 @@ __device__ __forceinline__ bool f32_noise_pair(float app, float aqq, float apq) 
   return fabsf(app - aqq) <= nz && fabsf(apq) <= nz;
 }
 
+// Rotation of the FP32 stage: the same formula as the FP64 phase (t = 2a / (|d| +
+// sqrt(d^2 + 4a^2)), sign of d; c = 1/sqrt(1+t^2); s = t c) evaluated with the hardware
+// square root, reciprocal and reciprocal square root (about 1 ulp each).  The stage's
+// result is re-orthogonalised in FP64, so the angle only needs FP32 working accuracy, and
+// these few instructions replace the correctly rounded sequences that made every inner
+// round issue-bound.
+__device__ __forceinline__ void rot_fast(float app, float aqq, float apq, float& t, float& c,
+                                         float& s) {
+  float d = app - aqq, a = apq;
+  const float m = fmaxf(fabsf(d), fabsf(a));
+  if (m < 0x1p-50f || m > 0x1p50f) {
+    int e;
+    (void)frexpf(m, &e);
+    d = ldexpf(d, -e);
+    a = ldexpf(a, -e);
+  }
+  const float den = fabsf(d) + __builtin_amdgcn_sqrtf(d * d + 4.0f * (a * a));
+  float tt = (2.0f * a) * __builtin_amdgcn_rcpf(den);
+  if (d < 0.0f) tt = -tt;
+  c = __builtin_amdgcn_rsqf(1.0f + tt * tt);
+  s = tt * c;
+  t = tt;
+}
+
 __device__ __forceinline__ void inner_pair(int full, int r, int k, int& p, int& q) {
   if (full) {
     circle64(r, k, p, q);
@@ -72,16 +96,12 @@ __device__ __forceinline__ void inner_pair(int full, int r, int k, int& p, int& 
   }
 }
 
-__global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int np,
-                                                     const int2* __restrict__ pairs,
-                                                     float* __restrict__ U, int inner_max,
-                                                     int full, float tol2, float rho2) {
-  __shared__ __align__(16) float S[PM][PL];
-  __shared__ __align__(16) float Ut[PM][PL];  // U transposed: Ut[j][i] = U[i][j]
+__device__ __forceinline__ void solve_body(float (*S)[PL], float (*Ut)[PL], float* __restrict__ A,
+                                           int np, int2 pr, float* __restrict__ Uo,
+                                           int inner_max, int full, float tol2, float rho2) {
   __shared__ float cs_c[32], cs_s[32], cs_dp[32], cs_dq[32], cs_z[32];
   __shared__ float red[2][SNT / 64];
   const int tid = threadIdx.x;
-  const int2 pr = pairs[blockIdx.x];
   for (int e = tid; e < PM * PM; e += SNT) {
     int i = e / PM, j = e % PM;
     S[i][j] = A[(size_t)blk_row(pr.x, pr.y, i) * np + blk_row(pr.x, pr.y, j)];
@@ -108,7 +128,7 @@ __global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int 
         const bool skip = apq == 0.0f || f32_noise_pair(app, aqq, apq);
         if (!skip) {
           float t;
-          rot_params<float>(app, aqq, apq, t, c, s);
+          rot_fast(app, aqq, apq, t, c, s);
           app = app + t * apq;
           aqq = aqq - t * apq;
         }
@@ -172,7 +192,6 @@ __global__ __launch_bounds__(SNT) void k_block_solve(float* __restrict__ A, int 
       prev_off = off;
     }
   }
-  float* Uo = U + (size_t)blockIdx.x * PM * PM;
   for (int e = tid; e < PM * PM; e += SNT) {
     int i = e / PM, j = e % PM;
     Uo[e] = Ut[j][i];
@@ -249,43 +268,60 @@ __global__ __launch_bounds__(256) void k_block_apply_a(float* __restrict__ A, in
     }
 }
 
-// V <- V U_R on the columns of block pair R, for a tile of 64 rows.
-__global__ __launch_bounds__(256) void k_block_apply_v(float* __restrict__ V, int nrows, int np,
-                                                       const int2* __restrict__ pairs,
-                                                       const float* __restrict__ U) {
-  __shared__ __align__(16) float Ur[PM][PL], Vb[PM][PL];
+// V <- V U_R on the columns of block pair R, for the tile of 64 rows from r0.
+__device__ __forceinline__ void vtile_body(float (*Ur)[PL], float (*Vb)[PL], float* __restrict__ V,
+                                           int nrows, int np, int r0, int2 pr,
+                                           const float* __restrict__ Uh) {
   const int tid = threadIdx.x;
-  const int R = blockIdx.y, r0 = blockIdx.x * PM;
-  const int2 pr = pairs[R];
-  const float* Uh = U + (size_t)R * PM * PM;
-  for (int e = tid; e < PM * PM; e += 256) {
+  for (int e = tid; e < PM * PM; e += SNT) {
     int i = e / PM, j = e % PM;
     Ur[i][j] = Uh[e];
     Vb[i][j] = (r0 + i < nrows) ? V[(size_t)(r0 + i) * np + blk_row(pr.x, pr.y, j)] : 0.0f;
   }
   __syncthreads();
-  const int ti = (tid >> 4) * 4, tj = (tid & 15) * 4;
-  float acc[4][4];
+  const int ti = (tid >> 4) * 2, tj = (tid & 15) * 4;
+  float acc[2][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
+#pragma unroll 4
   for (int k = 0; k < PM; ++k) {
     float4 u = *reinterpret_cast<const float4*>(&Ur[k][tj]);
     float uu[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 2; ++a) {
       float t = Vb[ti + a][k];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(t, uu[c], acc[a][c]);
     }
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
       if (r0 + ti + a < nrows)
         V[(size_t)(r0 + ti + a) * np + blk_row(pr.x, pr.y, tj + c)] = acc[a][c];
+}
+
+// One launch per round: blocks [0, nsolve) solve the round's block pairs (writing U of this
+// round); the remaining blocks apply the previous round's factors to V, which no solve reads,
+// so the V update runs beside the next round's subproblem solves.
+__global__ __launch_bounds__(SNT) void k_block_round(float* __restrict__ A, int np,
+                                                     const int2* __restrict__ pairs,
+                                                     float* __restrict__ U, int nsolve,
+                                                     int inner_max, int full, float tol2,
+                                                     float rho2, float* __restrict__ V, int nrows,
+                                                     const int2* __restrict__ vpairs,
+                                                     const float* __restrict__ vU, int nvt) {
+  __shared__ __align__(16) float lds[2][PM][PL];
+  if ((int)blockIdx.x < nsolve) {
+    solve_body(lds[0], lds[1], A, np, pairs[blockIdx.x], U + (size_t)blockIdx.x * PM * PM,
+               inner_max, full, tol2, rho2);
+  } else {
+    const int b = blockIdx.x - nsolve, R = b / nvt, rt = b - R * nvt;
+    vtile_body(lds[0], lds[1], V, nrows, np, rt * PM, vpairs[R], vU + (size_t)R * PM * PM);
+  }
 }
 
 // A32 (np x np, zero padded) <- fl32(A)
@@ -352,7 +388,7 @@ static int padded(int n) { return (n + PM - 1) / PM * PM; }
 size_t precond_f32_bytes(int n) {
   size_t np = (size_t)padded(n), nb = np / PB;
   size_t b = np * np * 4 + (size_t)n * np * 4;   // A32, V32
-  b += (nb / 2) * PM * PM * 4;                    // U of every block pair of a round
+  b += 2 * (nb / 2) * PM * PM * 4;                // U of every block pair of two rounds
   b += (nb - 1 > 0 ? nb - 1 : 1) * (nb / 2) * 8;  // pair table of all rounds
   b += 2 * np * 8 + 256;                          // partial sums + result
   return (b + 4095) & ~(size_t)4095;
@@ -364,7 +400,7 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
   char* p = (char*)scratch;
   float* A32 = (float*)p; p += (size_t)np * np * 4;
   float* V32 = (float*)p; p += (size_t)n * np * 4;
-  float* U = (float*)p; p += (size_t)nb2 * PM * PM * 4;
+  float* U = (float*)p; p += 2 * (size_t)nb2 * PM * PM * 4;
   int2* pairs = (int2*)p; p += (size_t)rounds * nb2 * 8;
   double* part = (double*)p; p += 2 * (size_t)np * 8;
   double* res = (double*)p;
@@ -402,17 +438,28 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
   double off = h[0], nrm = h[1];
   // a single block pair is the whole matrix: its subproblem solve converges it
   const int inner = (nb == 2) ? max_sweeps : 1;
+  const int nvt = (n + PM - 1) / PM;
+  // U of consecutive rounds alternates between two buffers; the V update of a round runs
+  // in the next round's launch (or in a launch of its own after the last round)
+  long long g = 0;
+  int vround = -1;
+  auto ubuf = [&](long long k) { return U + (size_t)(k & 1) * nb2 * PM * PM; };
+  auto vlaunch_args = [&](int nsolve, const int2* pr, float* Uw, int full) {
+    const int nv = vround >= 0 ? nvt * nb2 : 0;
+    const int2* vp = vround >= 0 ? pairs + (size_t)vround * nb2 : pairs;
+    hipLaunchKernelGGL(k_block_round, dim3(nsolve + nv), dim3(SNT), 0, s, A32, np, pr, Uw,
+                       nsolve, inner, full, (float)(tol * tol), (float)(rho * rho), V32, n, vp,
+                       ubuf(g - 1), nvt);
+  };
   int sw = 0;
   while (sw < max_sweeps && off > tol * nrm) {
-    for (int r = 0; r < rounds; ++r) {
+    for (int r = 0; r < rounds; ++r, ++g) {
       const int2* pr = pairs + (size_t)r * nb2;
-      hipLaunchKernelGGL(k_block_solve, dim3(nb2), dim3(SNT), 0, s, A32, np, pr, U, inner,
-                         r == 0 ? 1 : 0, (float)(tol * tol), (float)(rho * rho));
+      vlaunch_args(nb2, pr, ubuf(g), r == 0 ? 1 : 0);
       if (nb2 > 1)
         hipLaunchKernelGGL(k_block_apply_a, dim3(nb2 * (nb2 - 1) / 2), dim3(256), 0, s, A32, np,
-                           pr, U, nb2);
-      hipLaunchKernelGGL(k_block_apply_v, dim3((n + PM - 1) / PM, nb2), dim3(256), 0, s, V32, n,
-                         np, pr, U);
+                           pr, ubuf(g), nb2);
+      vround = r;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     ++sw;
@@ -421,6 +468,10 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
     off = h[0];
     nrm = h[1];
     if (nb == 2 || off >= rho * prev) break;
+  }
+  if (vround >= 0) {
+    vlaunch_args(0, pairs, nullptr, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   *sweeps = sw;
   size_t tot = (size_t)n * n;
