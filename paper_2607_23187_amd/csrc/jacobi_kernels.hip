@@ -747,39 +747,21 @@ static hipError_t launch_one(const JDesc& d, long long log_base, hipStream_t s) 
   return hipGetLastError();
 }
 
+// HBM-resident matrices are updated in mirror mode by default (rows and columns p, q stored,
+// every load a contiguous row segment); JE_MIRROR=0 selects the timestamp mode (rows only,
+// the newer copy of each entry chosen by per-row write timestamps).  Both give the same
+// arithmetic and the same pivot sequence.
 static int mirror_mode() {
-  static int m = -1;
-  if (m < 0) {
-    const char* e = getenv("JE_MIRROR");
-    m = (e && e[0] == '1') ? 1 : 0;
-  }
-  return m;
-}
-
-static int threads_override() {
-  static int t = -1;
-  if (t < 0) {
-    const char* e = getenv("JE_NT");
-    t = e ? atoi(e) : 0;
-  }
-  return t;
+  const char* e = getenv("JE_MIRROR");
+  return (e && e[0] == '0') ? 0 : 1;
 }
 
 // Threads per workgroup for the HBM-resident kernel: 512 (two waves per SIMD, 256 VGPRs
-// per lane) unless overridden; rows per thread RM = ceil(n / NT).
+// per lane); rows per thread RM = ceil(n / NT).
 template <bool GAP, bool MIR>
 static hipError_t launch_global(const JDesc& d, long long log_base, hipStream_t s) {
   const int n = d.n;
-  const int nt = threads_override();
   if (n <= 256) return launch_one<256, 1, GAP, false, MIR>(d, log_base, s);
-  if (nt == 1024) {
-    if (n <= 1024) return launch_one<1024, 1, GAP, false, MIR>(d, log_base, s);
-    if (n <= 2048) return launch_one<1024, 2, GAP, false, MIR>(d, log_base, s);
-    if (n <= 4096) return launch_one<1024, 4, GAP, false, MIR>(d, log_base, s);
-  }
-  if (nt == 256) {
-    if (n <= 1024) return launch_one<256, 4, GAP, false, MIR>(d, log_base, s);
-  }
   if (n <= 512) return launch_one<512, 1, GAP, false, MIR>(d, log_base, s);
   if (n <= 1024) return launch_one<512, 2, GAP, false, MIR>(d, log_base, s);
   if (n <= 2048) return launch_one<512, 4, GAP, false, MIR>(d, log_base, s);

@@ -109,6 +109,23 @@ def test_pivot_sequence_identical_preconditioned(n, pivot):
     assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a)))
 
 
+@pytest.mark.parametrize("n", [129, 300, 520])
+@pytest.mark.parametrize("pivot", [J.GREEDY, J.GAP])
+def test_pivot_sequence_identical_timestamp_mode(n, pivot, monkeypatch):
+    """The HBM-resident kernel's other storage mode (rows only, per-row write timestamps
+    pick the newer copy of each entry) gives the same pivots and eigenvalues."""
+    say("timestamp-mode parity", n, pivot)
+    monkeypatch.setenv("JE_MIRROR", "0")
+    p = I.clustered(n, seed=3500 + n, size=8, offset=1e-10)
+    ah = oracle_a_hat(p)
+    thr = cert_thr(ah, np.max(np.abs(p.lam)), n)
+    r, ref = _parity_case(ah, pivot, "cert", thr)
+    assert r.status == J.OK
+    assert r.stats["rotations"] == ref.rotations
+    assert np.array_equal(r.pivots.cpu().numpy(), ref.pivots)
+    assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a)))
+
+
 @pytest.mark.parametrize("n", [64, 150])
 def test_off_stop_rule(n):
     """off(A) <= tol ||A||_F: the per-row sums are added in a different order on the two
