@@ -2,17 +2,20 @@
 // two-sided Jacobi in FP32 (the eigenvector matrix is re-orthogonalised in FP64 by the host
 // driver afterwards).
 //
-// The matrix (padded with zero rows/columns to np = a multiple of 64) is split into
-// 32-row blocks.  A sweep visits every pair of blocks once in round-robin (circle method)
-// order: nb - 1 rounds of nb/2 disjoint block pairs.  For each pair (I, J) of a round one
-// workgroup applies scalar FP32 Jacobi rotations (parallel round-robin inside the block)
-// to the 64 x 64 subproblem [[A_II, A_IJ], [A_JI, A_JJ]] in LDS, accumulating its
-// orthogonal factor U_IJ; then every other 64 x 64 block of A is replaced by
-// U_P^T A_PR U_R and the columns of V by V U_R.  Each round reads and writes A and V once,
-// so a sweep costs nb - 1 passes over memory instead of np - 1.  For n <= 64 the single
-// block pair is the whole matrix and the subproblem solve is the whole decomposition.
+// The matrix (padded with zero rows/columns to np = a multiple of 2 PB) is split into
+// blocks of PB rows (PB = 16 or 32).  A sweep visits every pair of blocks once in
+// round-robin (circle method) order: nb - 1 rounds of nb/2 disjoint block pairs.  For each
+// pair (I, J) of a round one workgroup applies scalar FP32 Jacobi rotations (parallel
+// round-robin inside the block) to the PM x PM subproblem [[A_II, A_IJ], [A_JI, A_JJ]]
+// (PM = 2 PB) in LDS, accumulating its orthogonal factor U_IJ; then every other PM x PM
+// block of A is replaced by U_P^T A_PR U_R and the columns of V by V U_R.  Each round reads
+// and writes A and V once, so a sweep costs nb - 1 passes over memory instead of np - 1.
+// For n <= PM the single block pair is the whole matrix and the subproblem solve is the
+// whole decomposition.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "device_common.h"
@@ -20,32 +23,40 @@
 
 namespace je {
 
-constexpr int PB = 32;          // block rows
-constexpr int PM = 64;          // subproblem size (two blocks)
-constexpr int PL = PM + 4;      // LDS row stride (floats), rows stay 16-byte aligned
+// Block geometry: PB rows per block, PM = 2 PB per subproblem, LDS rows padded by 4 floats
+// (16-byte aligned), NT threads per workgroup so that both phases of an inner round give
+// every thread four entries of S.
+template <int PB>
+struct Blk {
+  static constexpr int PM = 2 * PB;
+  static constexpr int PL = PM + 4;
+  static constexpr int NT = PB * PM / 4;
+};
 
-// Index pair k of round r of the circle method on 64 indices (index 63 fixed).
-__device__ __forceinline__ void circle64(int r, int k, int& p, int& q) {
+// Index pair k of round r of the circle method on M indices (index M - 1 fixed).
+template <int M>
+__device__ __forceinline__ void circle(int r, int k, int& p, int& q) {
   int x, y;
-  if (k == 0) { x = 63; y = r; }
-  else { x = (r + k) % 63; y = (r - k + 63) % 63; }
+  if (k == 0) { x = M - 1; y = r; }
+  else { x = (r + k) % (M - 1); y = (r - k + M - 1) % (M - 1); }
   p = min(x, y);
   q = max(x, y);
 }
 
+template <int PB>
 __device__ __forceinline__ int blk_row(int I, int J, int i) {
   return i < PB ? I * PB + i : J * PB + (i - PB);
 }
 
-// One workgroup per block pair: Jacobi on the 64 x 64 subproblem in LDS.  The solved block
+// One workgroup per block pair: Jacobi on the PM x PM subproblem in LDS.  The solved block
 // goes back into A (upper triangle, mirrored, so A stays exactly symmetric) and its
 // orthogonal factor U = product of the rotations into U.  Every rotation ends like the
 // scalar method's: the pivot entry becomes exactly 0 and the diagonal app + t apq,
 // aqq - t apq, so the diagonal blocks keep the entry-wise accuracy of scalar Jacobi.
 //
-// With full != 0 an inner sweep visits all 2016 pairs of the subproblem (63 rounds of the
-// circle method); otherwise only the 1024 pairs that couple the two blocks (32 rounds,
-// round r pairing local index a with 32 + (a + r) mod 32).  The first round of every outer
+// With full != 0 an inner sweep visits all pairs of the subproblem (PM - 1 rounds of the
+// circle method); otherwise only the PB^2 pairs that couple the two blocks (PB rounds,
+// round r pairing local index a with PB + (a + r) mod PB).  The first round of every outer
 // sweep is full: its block pairs cover each block once, so every pair inside a block is
 // rotated there, and the later rounds need only the cross pairs: one outer sweep then
 // rotates each index pair once, like a scalar cyclic sweep.
@@ -55,7 +66,6 @@ __device__ __forceinline__ int blk_row(int I, int J, int i) {
 // rotation angle would be set by rounding noise, and the large noise-driven rotations
 // inside a cluster would keep re-mixing the cluster's couplings to the rest of the matrix,
 // so that they only decay linearly.  Those entries are left for the FP64 phase.
-constexpr int SNT = 512;
 constexpr float kNoise = 0x1p-22f;
 
 __device__ __forceinline__ bool f32_noise_pair(float app, float aqq, float apq) {
@@ -87,97 +97,92 @@ __device__ __forceinline__ void rot_fast(float app, float aqq, float apq, float&
   t = tt;
 }
 
+template <int PB>
 __device__ __forceinline__ void inner_pair(int full, int r, int k, int& p, int& q) {
   if (full) {
-    circle64(r, k, p, q);
+    circle<2 * PB>(r, k, p, q);
   } else {
     p = k;
     q = PB + ((k + r) & (PB - 1));
   }
 }
 
-__device__ __forceinline__ void solve_body(float (*S)[PL], float (*Ut)[PL], float* __restrict__ A,
+// Both phases of an inner round read rows only.  With J the product of the round's disjoint
+// rotations, the row phase forms M = J^T S and stores it transposed, W = M^T; the second
+// phase forms J^T W = (S J ... )^T, i.e. the rotated matrix J^T S J read by rows (it is
+// symmetric up to rounding; its upper triangle is the one used).  A lane keeps the same
+// pair and columns in both phases, so its c, s stay in registers.
+template <int PB>
+__device__ __forceinline__ void solve_body(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
+                                           float (*Ut)[Blk<PB>::PL], float* __restrict__ A,
                                            int np, int2 pr, float* __restrict__ Uo,
                                            int inner_max, int full, float tol2, float rho2) {
-  __shared__ float cs_c[32], cs_s[32], cs_dp[32], cs_dq[32], cs_z[32];
-  __shared__ float red[2][SNT / 64];
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, LB = PM / 4;
+  __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
-  for (int e = tid; e < PM * PM; e += SNT) {
+  for (int e = tid; e < PM * PM; e += NT) {
     int i = e / PM, j = e % PM;
-    S[i][j] = A[(size_t)blk_row(pr.x, pr.y, i) * np + blk_row(pr.x, pr.y, j)];
+    S[i][j] = A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
     Ut[i][j] = (i == j) ? 1.0f : 0.0f;
   }
   __syncthreads();
-  // row phase: pair kb, columns jb .. jb+3 (the 16 lanes of a pair share one wave);
-  // column phase: pair kc, rows ic .. ic+3
-  const int kb = tid >> 4, jb = (tid & 15) * 4;
-  const int kc = tid & 31, ic = (tid >> 5) * 4;
+  // pair kb, columns jb .. jb+3 (the LB lanes of a pair share one wave)
+  const int kb = tid / LB, jb = (tid % LB) * 4;
   const int nr = full ? PM - 1 : PB;
   float prev_off = 3.4e38f;
   for (int sw = 0; sw < inner_max; ++sw) {
     for (int r = 0; r < nr; ++r) {
-      {
-        int p, q;
-        inner_pair(full, r, kb, p, q);
-        // every lane of the pair reads the 2x2 block before any lane of it stores
-        float app = S[p][p], aqq = S[q][q];
-        const float apq = S[p][q];
-        const float4 x = *reinterpret_cast<const float4*>(&S[p][jb]);
-        const float4 y = *reinterpret_cast<const float4*>(&S[q][jb]);
-        float c = 1.0f, s = 0.0f;
-        const bool skip = apq == 0.0f || f32_noise_pair(app, aqq, apq);
-        if (!skip) {
-          float t;
-          rot_fast(app, aqq, apq, t, c, s);
-          app = app + t * apq;
-          aqq = aqq - t * apq;
-        }
-        float4 xo, yo;
-        xo.x = c * x.x + s * y.x; yo.x = c * y.x - s * x.x;
-        xo.y = c * x.y + s * y.y; yo.y = c * y.y - s * x.y;
-        xo.z = c * x.z + s * y.z; yo.z = c * y.z - s * x.z;
-        xo.w = c * x.w + s * y.w; yo.w = c * y.w - s * x.w;
-        *reinterpret_cast<float4*>(&S[p][jb]) = xo;
-        *reinterpret_cast<float4*>(&S[q][jb]) = yo;
-        if ((tid & 15) == 0) {
-          cs_c[kb] = c; cs_s[kb] = s;
-          cs_dp[kb] = app; cs_dq[kb] = aqq;
-          cs_z[kb] = skip ? apq : 0.0f;
-        }
+      int p, q;
+      inner_pair<PB>(full, r, kb, p, q);
+      // every lane of the pair reads the 2x2 block before any lane of it stores
+      float app = S[p][p], aqq = S[q][q];
+      const float apq = S[p][q];
+      const float4 x = *reinterpret_cast<const float4*>(&S[p][jb]);
+      const float4 y = *reinterpret_cast<const float4*>(&S[q][jb]);
+      float c = 1.0f, s = 0.0f;
+      const bool skip = apq == 0.0f || f32_noise_pair(app, aqq, apq);
+      if (!skip) {
+        float t;
+        rot_fast(app, aqq, apq, t, c, s);
+        app = app + t * apq;
+        aqq = aqq - t * apq;
       }
+      const float z = skip ? apq : 0.0f;
+      W[jb + 0][p] = c * x.x + s * y.x; W[jb + 0][q] = c * y.x - s * x.x;
+      W[jb + 1][p] = c * x.y + s * y.y; W[jb + 1][q] = c * y.y - s * x.y;
+      W[jb + 2][p] = c * x.z + s * y.z; W[jb + 2][q] = c * y.z - s * x.z;
+      W[jb + 3][p] = c * x.w + s * y.w; W[jb + 3][q] = c * y.w - s * x.w;
       __syncthreads();
       {
-        int p, q;
-        inner_pair(full, r, kc, p, q);
-        const float c = cs_c[kc], s = cs_s[kc];
-        float sx[4], sy[4];
+        const float4 wx = *reinterpret_cast<const float4*>(&W[p][jb]);
+        const float4 wy = *reinterpret_cast<const float4*>(&W[q][jb]);
+        float xo[4] = {c * wx.x + s * wy.x, c * wx.y + s * wy.y, c * wx.z + s * wy.z,
+                       c * wx.w + s * wy.w};
+        float yo[4] = {c * wy.x - s * wx.x, c * wy.y - s * wx.y, c * wy.z - s * wx.z,
+                       c * wy.w - s * wx.w};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { sx[k] = S[ic + k][p]; sy[k] = S[ic + k][q]; }
-        const float4 up = *reinterpret_cast<const float4*>(&Ut[p][ic]);
-        const float4 uq = *reinterpret_cast<const float4*>(&Ut[q][ic]);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = ic + k;
-          float op = c * sx[k] + s * sy[k], oq = c * sy[k] - s * sx[k];
-          if (i == p) { op = cs_dp[kc]; oq = cs_z[kc]; }
-          if (i == q) { op = cs_z[kc]; oq = cs_dq[kc]; }
-          S[i][p] = op;
-          S[i][q] = oq;
+        for (int v = 0; v < 4; ++v) {
+          if (jb + v == p) { xo[v] = app; yo[v] = z; }
+          if (jb + v == q) { xo[v] = z; yo[v] = aqq; }
         }
+        *reinterpret_cast<float4*>(&S[p][jb]) = make_float4(xo[0], xo[1], xo[2], xo[3]);
+        *reinterpret_cast<float4*>(&S[q][jb]) = make_float4(yo[0], yo[1], yo[2], yo[3]);
+        const float4 up = *reinterpret_cast<const float4*>(&Ut[p][jb]);
+        const float4 uq = *reinterpret_cast<const float4*>(&Ut[q][jb]);
         float4 po, qo;
         po.x = c * up.x + s * uq.x; qo.x = c * uq.x - s * up.x;
         po.y = c * up.y + s * uq.y; qo.y = c * uq.y - s * up.y;
         po.z = c * up.z + s * uq.z; qo.z = c * uq.z - s * up.z;
         po.w = c * up.w + s * uq.w; qo.w = c * uq.w - s * up.w;
-        *reinterpret_cast<float4*>(&Ut[p][ic]) = po;
-        *reinterpret_cast<float4*>(&Ut[q][ic]) = qo;
+        *reinterpret_cast<float4*>(&Ut[p][jb]) = po;
+        *reinterpret_cast<float4*>(&Ut[q][jb]) = qo;
       }
       __syncthreads();
     }
     if (sw + 1 < inner_max) {
       // off(S) and ||S||_F decide whether another inner sweep pays
       float so = 0.0f, sd = 0.0f;
-      for (int e = tid; e < PM * PM; e += SNT) {
+      for (int e = tid; e < PM * PM; e += NT) {
         int i = e / PM, j = e % PM;
         float v = S[i][j] * S[i][j];
         if (i == j) sd += v; else so += v;
@@ -186,25 +191,50 @@ __device__ __forceinline__ void solve_body(float (*S)[PL], float (*Ut)[PL], floa
       if ((tid & 63) == 0) { red[0][tid >> 6] = so; red[1][tid >> 6] = sd; }
       __syncthreads();
       float off = 0.0f, dg = 0.0f;
-      for (int w = 0; w < SNT / 64; ++w) { off += red[0][w]; dg += red[1][w]; }
+      for (int w = 0; w < NT / 64; ++w) { off += red[0][w]; dg += red[1][w]; }
       __syncthreads();
       if (off <= tol2 * (off + dg) || off >= rho2 * prev_off) break;
       prev_off = off;
     }
   }
-  for (int e = tid; e < PM * PM; e += SNT) {
+  for (int e = tid; e < PM * PM; e += NT) {
     int i = e / PM, j = e % PM;
     Uo[e] = Ut[j][i];
     float v = (i <= j) ? S[i][j] : S[j][i];
-    A[(size_t)blk_row(pr.x, pr.y, i) * np + blk_row(pr.x, pr.y, j)] = v;
+    A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
+  }
+}
+
+// out (PM x PM, R x 4 entries per thread) = X^T Y if TA, else X Y; X, Y in LDS.
+template <int PB, bool TA, int R>
+__device__ __forceinline__ void tile_gemm(float (*X)[Blk<PB>::PL], float (*Y)[Blk<PB>::PL],
+                                          int ti, int tj, float (&acc)[R][4]) {
+  constexpr int PM = Blk<PB>::PM;
+#pragma unroll
+  for (int a = 0; a < R; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
+#pragma unroll 4
+  for (int k = 0; k < PM; ++k) {
+    const float4 y = *reinterpret_cast<const float4*>(&Y[k][tj]);
+    const float yy[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      const float xv = TA ? X[k][ti + a] : X[ti + a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xv, yy[c], acc[a][c]);
+    }
   }
 }
 
 // Block update of A for block pairs P < R: A_PR <- U_P^T A_PR U_R, mirrored to A_RP (so A
 // stays exactly symmetric).  The diagonal pair blocks were written by the subproblem solve.
-__global__ __launch_bounds__(256) void k_block_apply_a(float* __restrict__ A, int np,
-                                                       const int2* __restrict__ pairs,
-                                                       const float* __restrict__ U, int nb2) {
+template <int PB>
+__global__ __launch_bounds__(Blk<PB>::NT) void k_block_apply_a(float* __restrict__ A, int np,
+                                                               const int2* __restrict__ pairs,
+                                                               const float* __restrict__ U,
+                                                               int nb2) {
+  constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL, NT = Blk<PB>::NT;
   __shared__ __align__(16) float Up[PM][PL], Ur[PM][PL], Ab[PM][PL];
   const int tid = threadIdx.x;
   // blockIdx.x enumerates P < R
@@ -214,113 +244,74 @@ __global__ __launch_bounds__(256) void k_block_apply_a(float* __restrict__ A, in
   const int2 pp = pairs[P], pr = pairs[R];
   const float* Ug = U + (size_t)P * PM * PM;
   const float* Uh = U + (size_t)R * PM * PM;
-  for (int e = tid; e < PM * PM; e += 256) {
+  for (int e = tid; e < PM * PM; e += NT) {
     int i = e / PM, j = e % PM;
     Up[i][j] = Ug[e];
     Ur[i][j] = Uh[e];
-    Ab[i][j] = A[(size_t)blk_row(pp.x, pp.y, i) * np + blk_row(pr.x, pr.y, j)];
+    Ab[i][j] = A[(size_t)blk_row<PB>(pp.x, pp.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
   }
   __syncthreads();
-  const int ti = (tid >> 4) * 4, tj = (tid & 15) * 4;
-  float acc[4][4];
-  // T = U_P^T A_PR
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
-  for (int k = 0; k < PM; ++k) {
-    float4 u = *reinterpret_cast<const float4*>(&Up[k][ti]);
-    float4 x = *reinterpret_cast<const float4*>(&Ab[k][tj]);
-    float uu[4] = {u.x, u.y, u.z, u.w}, xx[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(uu[a], xx[c], acc[a][c]);
-  }
+  const int ti = (tid / (PM / 4)) * 2, tj = (tid % (PM / 4)) * 4;
+  float acc[2][4];
+  tile_gemm<PB, true, 2>(Up, Ab, ti, tj, acc);  // T = U_P^T A_PR
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) Ab[ti + a][tj + c] = acc[a][c];
   __syncthreads();
-  // out = T U_R
+  tile_gemm<PB, false, 2>(Ab, Ur, ti, tj, acc);  // T U_R
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
-  for (int k = 0; k < PM; ++k) {
-    float4 u = *reinterpret_cast<const float4*>(&Ur[k][tj]);
-    float uu[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      float t = Ab[ti + a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(t, uu[c], acc[a][c]);
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      int gi = blk_row(pp.x, pp.y, ti + a), gj = blk_row(pr.x, pr.y, tj + c);
+      int gi = blk_row<PB>(pp.x, pp.y, ti + a), gj = blk_row<PB>(pr.x, pr.y, tj + c);
       A[(size_t)gi * np + gj] = acc[a][c];
       A[(size_t)gj * np + gi] = acc[a][c];
     }
 }
 
-// V <- V U_R on the columns of block pair R, for the tile of 64 rows from r0.
-__device__ __forceinline__ void vtile_body(float (*Ur)[PL], float (*Vb)[PL], float* __restrict__ V,
-                                           int nrows, int np, int r0, int2 pr,
-                                           const float* __restrict__ Uh) {
+// V <- V U_R on the columns of block pair R, for the tile of PM rows from r0 (RT threads,
+// VR x 4 entries each).
+template <int PB>
+__device__ __forceinline__ void vtile_body(float (*Ur)[Blk<PB>::PL], float (*Vb)[Blk<PB>::PL],
+                                           float* __restrict__ V, int nrows, int np, int r0,
+                                           int2 pr, const float* __restrict__ Uh) {
+  constexpr int PM = Blk<PB>::PM, RT = Blk<PB>::NT, VR = PM * PM / (4 * RT);
   const int tid = threadIdx.x;
-  for (int e = tid; e < PM * PM; e += SNT) {
+  for (int e = tid; e < PM * PM; e += RT) {
     int i = e / PM, j = e % PM;
     Ur[i][j] = Uh[e];
-    Vb[i][j] = (r0 + i < nrows) ? V[(size_t)(r0 + i) * np + blk_row(pr.x, pr.y, j)] : 0.0f;
+    Vb[i][j] = (r0 + i < nrows) ? V[(size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j)] : 0.0f;
   }
   __syncthreads();
-  const int ti = (tid >> 4) * 2, tj = (tid & 15) * 4;
-  float acc[2][4];
+  const int ti = (tid / (PM / 4)) * VR, tj = (tid % (PM / 4)) * 4;
+  float acc[VR][4];
+  tile_gemm<PB, false, VR>(Vb, Ur, ti, tj, acc);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
-#pragma unroll 4
-  for (int k = 0; k < PM; ++k) {
-    float4 u = *reinterpret_cast<const float4*>(&Ur[k][tj]);
-    float uu[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      float t = Vb[ti + a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(t, uu[c], acc[a][c]);
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < VR; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
       if (r0 + ti + a < nrows)
-        V[(size_t)(r0 + ti + a) * np + blk_row(pr.x, pr.y, tj + c)] = acc[a][c];
+        V[(size_t)(r0 + ti + a) * np + blk_row<PB>(pr.x, pr.y, tj + c)] = acc[a][c];
 }
 
 // One launch per round: blocks [0, nsolve) solve the round's block pairs (writing U of this
 // round); the remaining blocks apply the previous round's factors to V, which no solve reads,
 // so the V update runs beside the next round's subproblem solves.
-__global__ __launch_bounds__(SNT) void k_block_round(float* __restrict__ A, int np,
-                                                     const int2* __restrict__ pairs,
-                                                     float* __restrict__ U, int nsolve,
-                                                     int inner_max, int full, float tol2,
-                                                     float rho2, float* __restrict__ V, int nrows,
-                                                     const int2* __restrict__ vpairs,
-                                                     const float* __restrict__ vU, int nvt) {
-  __shared__ __align__(16) float lds[2][PM][PL];
+template <int PB>
+__global__ __launch_bounds__(Blk<PB>::NT) void k_block_round(
+    float* __restrict__ A, int np, const int2* __restrict__ pairs, float* __restrict__ U,
+    int nsolve, int inner_max, int full, float tol2, float rho2, float* __restrict__ V,
+    int nrows, const int2* __restrict__ vpairs, const float* __restrict__ vU, int nvt) {
+  constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL;
+  __shared__ __align__(16) float lds[3][PM][PL];
   if ((int)blockIdx.x < nsolve) {
-    solve_body(lds[0], lds[1], A, np, pairs[blockIdx.x], U + (size_t)blockIdx.x * PM * PM,
-               inner_max, full, tol2, rho2);
+    solve_body<PB>(lds[0], lds[1], lds[2], A, np, pairs[blockIdx.x],
+                   U + (size_t)blockIdx.x * PM * PM, inner_max, full, tol2, rho2);
   } else {
     const int b = blockIdx.x - nsolve, R = b / nvt, rt = b - R * nvt;
-    vtile_body(lds[0], lds[1], V, nrows, np, rt * PM, vpairs[R], vU + (size_t)R * PM * PM);
+    vtile_body<PB>(lds[0], lds[1], V, nrows, np, rt * PM, vpairs[R], vU + (size_t)R * PM * PM);
   }
 }
 
@@ -383,10 +374,21 @@ __global__ void k_gather_q(const float* __restrict__ V, int n, int ldv, double* 
   Q[(size_t)i * ldq + j] = (double)V[(size_t)i * ldv + j];
 }
 
-static int padded(int n) { return (n + PM - 1) / PM * PM; }
+// Block rows of the FP32 stage.  32 when one 64 x 64 subproblem is the whole matrix
+// (n <= 64) and above n = 2048, where the per-round passes over A and V dominate and fewer
+// rounds pay; 16 in between, where the subproblem solves dominate and a 32 x 32 inner round
+// is cheaper (measured at n = 1024: 32.8 vs 36.4 ms; at n = 4096: 423 vs 297 ms).
+// JE_F32_BLOCK=16 or 32 overrides the choice.
+static int block_rows(int n) {
+  const char* e = std::getenv("JE_F32_BLOCK");
+  if (e && (std::atoi(e) == 16 || std::atoi(e) == 32)) return std::atoi(e);
+  return (n <= 64 || n > 2048) ? 32 : 16;
+}
 
-size_t precond_f32_bytes(int n) {
-  size_t np = (size_t)padded(n), nb = np / PB;
+template <int PB>
+static size_t blocked_bytes(int n) {
+  constexpr int PM = Blk<PB>::PM;
+  size_t np = (size_t)((n + PM - 1) / PM * PM), nb = np / PB;
   size_t b = np * np * 4 + (size_t)n * np * 4;   // A32, V32
   b += 2 * (nb / 2) * PM * PM * 4;                // U of every block pair of two rounds
   b += (nb - 1 > 0 ? nb - 1 : 1) * (nb / 2) * 8;  // pair table of all rounds
@@ -394,9 +396,16 @@ size_t precond_f32_bytes(int n) {
   return (b + 4095) & ~(size_t)4095;
 }
 
-hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq, void* scratch,
-                           int max_sweeps, double tol, double rho, int* sweeps, hipStream_t s) {
-  const int np = padded(n), nb = np / PB, nb2 = nb / 2, rounds = nb - 1;
+size_t precond_f32_bytes(int n) {
+  return std::max(blocked_bytes<16>(n), blocked_bytes<32>(n));
+}
+
+template <int PB>
+static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int ldq,
+                              void* scratch, int max_sweeps, double tol, double rho, int* sweeps,
+                              hipStream_t s) {
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
+  const int np = (n + PM - 1) / PM * PM, nb = np / PB, nb2 = nb / 2, rounds = nb - 1;
   char* p = (char*)scratch;
   float* A32 = (float*)p; p += (size_t)np * np * 4;
   float* V32 = (float*)p; p += (size_t)n * np * 4;
@@ -417,6 +426,8 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
   if ((e = hipMemcpyAsync(pairs, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s)) !=
       hipSuccess)
     return e;
+  // the table is host memory read by an asynchronous copy: it must outlive the copy
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   {
     size_t tot = (size_t)np * np;
     hipLaunchKernelGGL(k_to_f32_pad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Asym,
@@ -444,10 +455,10 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
   long long g = 0;
   int vround = -1;
   auto ubuf = [&](long long k) { return U + (size_t)(k & 1) * nb2 * PM * PM; };
-  auto vlaunch_args = [&](int nsolve, const int2* pr, float* Uw, int full) {
+  auto round_launch = [&](int nsolve, const int2* pr, float* Uw, int full) {
     const int nv = vround >= 0 ? nvt * nb2 : 0;
     const int2* vp = vround >= 0 ? pairs + (size_t)vround * nb2 : pairs;
-    hipLaunchKernelGGL(k_block_round, dim3(nsolve + nv), dim3(SNT), 0, s, A32, np, pr, Uw,
+    hipLaunchKernelGGL(k_block_round<PB>, dim3(nsolve + nv), dim3(NT), 0, s, A32, np, pr, Uw,
                        nsolve, inner, full, (float)(tol * tol), (float)(rho * rho), V32, n, vp,
                        ubuf(g - 1), nvt);
   };
@@ -455,10 +466,10 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
   while (sw < max_sweeps && off > tol * nrm) {
     for (int r = 0; r < rounds; ++r, ++g) {
       const int2* pr = pairs + (size_t)r * nb2;
-      vlaunch_args(nb2, pr, ubuf(g), r == 0 ? 1 : 0);
+      round_launch(nb2, pr, ubuf(g), r == 0 ? 1 : 0);
       if (nb2 > 1)
-        hipLaunchKernelGGL(k_block_apply_a, dim3(nb2 * (nb2 - 1) / 2), dim3(256), 0, s, A32, np,
-                           pr, ubuf(g), nb2);
+        hipLaunchKernelGGL(k_block_apply_a<PB>, dim3(nb2 * (nb2 - 1) / 2), dim3(NT), 0, s, A32,
+                           np, pr, ubuf(g), nb2);
       vround = r;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -470,7 +481,7 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
     if (nb == 2 || off >= rho * prev) break;
   }
   if (vround >= 0) {
-    vlaunch_args(0, pairs, nullptr, 0);
+    round_launch(0, pairs, nullptr, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   *sweeps = sw;
@@ -478,6 +489,13 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
   hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V32, n, np,
                      Q, ldq);
   return hipGetLastError();
+}
+
+hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq, void* scratch,
+                           int max_sweeps, double tol, double rho, int* sweeps, hipStream_t s) {
+  if (block_rows(n) == 16)
+    return run_blocked<16>(Asym, n, ld, Q, ldq, scratch, max_sweeps, tol, rho, sweeps, s);
+  return run_blocked<32>(Asym, n, ld, Q, ldq, scratch, max_sweeps, tol, rho, sweeps, s);
 }
 
 }  // namespace je
