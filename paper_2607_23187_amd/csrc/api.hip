@@ -345,6 +345,313 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   return S.status;
 }
 
+// ------------------------------------------------------------------ batches
+// All problems of a batch (n >= 2) go through the same sequence of launches; every launch
+// covers the whole batch (grids sized for the largest n, blocks past a matrix's n exit).
+// The FP32 stage runs each matrix at its own pace; the FP64 Jacobi phase is one persistent
+// launch per workgroup shape (LDS-resident n <= 128, HBM-resident above), each workgroup
+// taking the next matrix, largest first, from a device counter.  Logs are drained for all
+// matrices between launches; unfinished matrices are relaunched.
+constexpr long long kBatchLogCap = 1ll << 16;
+
+struct BatchLayout {
+  size_t bytes = 0;
+  std::vector<size_t> off;  // per member: offset of its workspace
+};
+
+size_t bws_bytes(int n, int precond, long long cap) {
+  size_t ld = ld_of(n);
+  size_t mat = al((size_t)n * ld * 8);
+  size_t b = 7 * mat + 8 * al((size_t)n * 8) + al(64) + 7 * al((size_t)n * 4) +
+             al(sizeof(JCtl)) + al((size_t)cap * sizeof(RotEntry));
+  if (precond) b += al(precond_f32_bytes_b(n));
+  return b;
+}
+
+void bws_carve(char* p, BMat& b, int n, int precond, long long cap) {
+  const size_t ld = ld_of(n);
+  const size_t mat = al((size_t)n * ld * 8);
+  auto take = [&](size_t bytes) { char* r = p; p += al(bytes); return (void*)r; };
+  b.ld = (int)ld;
+  b.Asym = (double*)take(mat); b.A = (double*)take(mat); b.Vw = (double*)take(mat);
+  b.X = (double*)take(mat); b.Xb = (double*)take(mat); b.T = (double*)take(mat);
+  b.R = (double*)take(mat);
+  b.diag = (double*)take((size_t)n * 8); b.rowsq = (double*)take((size_t)n * 8);
+  JDesc& d = b.jd;
+  d.bs = (double*)take((size_t)n * 8); d.bv = (double*)take((size_t)n * 8);
+  d.cb = (double*)take((size_t)n * 8); d.off2 = (double*)take((size_t)n * 8);
+  d.bu = (double*)take((size_t)n * 8); d.cu = (double*)take((size_t)n * 8);
+  b.scal = (double*)take(64);
+  d.ba = (int*)take((size_t)n * 4); d.bst = (int*)take((size_t)n * 4);
+  d.ca = (int*)take((size_t)n * 4); d.cst = (int*)take((size_t)n * 4);
+  d.ts = (int*)take((size_t)n * 4);
+  b.rank = (int*)take((size_t)n * 4); b.flag = (int*)take((size_t)n * 4);
+  d.ctl = (JCtl*)take(sizeof(JCtl));
+  d.log = (RotEntry*)take((size_t)cap * sizeof(RotEntry));
+  d.log_cap = cap;
+  if (precond) {
+    constexpr int PM = 32;
+    const int np = (n + PM - 1) / PM * PM;
+    char* f = (char*)take(precond_f32_bytes_b(n));
+    b.np = np;
+    b.nb = np / 16;
+    b.A32 = (float*)f;
+    b.V32 = b.A32 + (size_t)np * np;
+    b.U = b.V32 + (size_t)n * np;
+  }
+}
+
+#define BF(f) BM_FIELD(f)
+
+int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
+                  const int* lda, double* const* W, double* const* V, const int* ldv, double tol,
+                  int pivot, int precond, const je_opts& o, int* info, je_stats* stats,
+                  hipStream_t s) {
+  int cnt = (int)mem.size();
+  if (cnt == 0) return JE_OK;
+  int nmax = 0;
+  for (int b : mem) nmax = std::max(nmax, n[b]);
+  std::vector<size_t> woff(cnt);
+  size_t tot = 0;
+  for (int i = 0; i < cnt; ++i) {
+    woff[i] = tot;
+    tot += bws_bytes(n[mem[i]], precond, kBatchLogCap);
+  }
+  const size_t meta = al((size_t)cnt * sizeof(BMat)) + 8 * al((size_t)cnt * 4 + 4) + al(64) +
+                      al((size_t)cnt * sizeof(BInfo));
+  int err = JE_OK;
+  char* base = (char*)pool_get(tot + meta, &err);
+  if (!base) return err;
+  char* mp = base + tot;
+  BMat* dm = (BMat*)mp; mp += al((size_t)cnt * sizeof(BMat));
+  int* d_idx_lds = (int*)mp; mp += al((size_t)cnt * 4 + 4);
+  int* d_idx_hbm = (int*)mp; mp += al((size_t)cnt * 4 + 4);
+  int* d_pre_solve = (int*)mp; mp += al((size_t)cnt * 4 + 4);
+  int* d_pre_vt = (int*)mp; mp += al((size_t)cnt * 4 + 4);
+  int* d_pre_pa = (int*)mp; mp += al((size_t)cnt * 4 + 4);
+  mp += 2 * al((size_t)cnt * 4 + 4);
+  int* d_cnt = (int*)mp;  // [0], [1] queue counters, [2] pending
+  mp += al(64);
+  BInfo* d_info = (BInfo*)mp;
+  std::vector<BInfo> hi(cnt);
+  auto collect = [&]() -> int {
+    HIPCHK(launch_collect_b(dm, cnt, d_info, s));
+    HIPCHK(hipMemcpyAsync(hi.data(), d_info, (size_t)cnt * sizeof(BInfo), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+    return JE_OK;
+  };
+
+  std::vector<BMat> hm(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    const int b = mem[i];
+    BMat& x = hm[i];
+    std::memset(&x, 0, sizeof(x));
+    x.Au = Ain[b]; x.n = n[b]; x.lda = lda[b];
+    x.Wout = W[b]; x.Vout = V ? V[b] : nullptr; x.ldv = ldv ? ldv[b] : n[b];
+    bws_carve(base + woff[i], x, n[b], precond, kBatchLogCap);
+  }
+  auto upload = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(dm, hm.data(), (size_t)cnt * sizeof(BMat), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return JE_OK;
+  };
+  if (int r = upload()) return r;
+  auto download = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(hm.data(), dm, (size_t)cnt * sizeof(BMat), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return JE_OK;
+  };
+  je_stats S{};
+  Timer tp(s);
+  // ---- 1. symmetric copies, finiteness, ||A||_F
+  HIPCHK(launch_reset_b(dm, cnt, s));
+  HIPCHK(launch_symcopy_b(dm, cnt, nmax, s));
+  HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(Asym), 0, s));
+  if (int r = collect()) return r;
+  // members with a non-finite entry leave the batch here (status JE_ERR_NONFINITE, outputs
+  // untouched, as for a single problem)
+  int worst = JE_OK;
+  {
+    std::vector<int> keep;
+    for (int i = 0; i < cnt; ++i) {
+      if (hi[i].nonfinite) {
+        info[mem[i]] = JE_ERR_NONFINITE;
+        worst = JE_ERR_NONFINITE;
+        if (stats) { std::memset(&stats[mem[i]], 0, sizeof(je_stats)); stats[mem[i]].status = JE_ERR_NONFINITE; }
+      } else {
+        keep.push_back(i);
+      }
+    }
+    if ((int)keep.size() < cnt) {
+      std::vector<BMat> h2;
+      std::vector<int> m2;
+      std::vector<BInfo> i2;
+      for (int i : keep) { h2.push_back(hm[i]); m2.push_back(mem[i]); i2.push_back(hi[i]); }
+      hm.swap(h2); mem.swap(m2); hi.swap(i2);
+      cnt = (int)keep.size();
+      if (cnt == 0) return worst;
+      if (int r = upload()) return r;
+    }
+  }
+  std::vector<double> nrm(cnt);
+  for (int i = 0; i < cnt; ++i) nrm[i] = hi[i].normF;
+  // largest first: the order of the FP64 work queue
+  std::vector<int> ord(cnt);
+  for (int i = 0; i < cnt; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hm[a].n > hm[b].n; });
+  const long long maxrot_opt = o.max_rotations;
+  for (int i = 0; i < cnt; ++i) {
+    BMat& x = hm[i];
+    const int nn = x.n;
+    JDesc& d = x.jd;
+    double thr;
+    if (o.abs_thr > 0.0) thr = o.abs_thr;
+    else if (o.stop == JE_STOP_CERT) thr = tol * nrm[i] / (2.0 * nn * (double)(nn - 1));
+    else thr = tol * nrm[i];
+    d.A = precond ? x.A : x.Asym;
+    d.n = nn; d.ld = x.ld; d.diag = x.diag;
+    d.thr = thr;
+    d.maxrot = maxrot_opt > 0 ? maxrot_opt : default_maxrot(nn);
+    d.pivot = pivot; d.stop = o.stop;
+    d.prof = nullptr;
+    x.log_base = 0;
+    x.f_pass_sweeps = 0;
+  }
+  if (int r = upload()) return r;
+  // non-finite inputs: reported, their workspaces still processed (results discarded)
+  // ---- 2. preconditioner
+  float ms_gemm = 0.f;
+  size_t offX = BF(X), offXb = BF(Xb);
+  auto orthonormalize_b = [&]() -> int {
+    for (int itn = 0; itn < 6; ++itn) {
+      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s));
+      HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s));
+      HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(R), 1, s));
+      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, offX, BF(R), 1.0, offX, offXb, s));
+      std::swap(offX, offXb);
+      if (int r = collect()) return r;
+      bool all = true;
+      for (int i = 0; i < cnt; ++i) all = all && hi[i].rnorm <= 4.0 * hm[i].n * 0x1p-53;
+      if (all) break;
+    }
+    return JE_OK;
+  };
+  if (precond) {
+    // FP32 stage tables: per-matrix block counts of the three round kernels
+    std::vector<int> ps(cnt + 1), pv(cnt + 1), pa(cnt + 1);
+    int max_rounds = 1;
+    ps[0] = pv[0] = pa[0] = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const int nb2 = hm[i].nb / 2, nvt = (hm[i].n + 31) / 32;
+      ps[i + 1] = ps[i] + nb2;
+      pv[i + 1] = pv[i] + nvt * nb2;
+      pa[i + 1] = pa[i] + nb2 * (nb2 - 1) / 2;
+      max_rounds = std::max(max_rounds, hm[i].nb - 1);
+    }
+    HIPCHK(hipMemcpyAsync(d_pre_solve, ps.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_pre_vt, pv.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_pre_pa, pa.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    auto f32pass = [&](size_t src, size_t dst, double t, double r) -> int {
+      HIPCHK(run_precond_f32_b(dm, cnt, nmax, d_pre_solve, d_pre_vt, d_pre_pa, ps[cnt], pv[cnt],
+                               pa[cnt], max_rounds, src, dst, o.fp32_max_sweeps, t, r,
+                               d_cnt + 2, s));
+      return JE_OK;
+    };
+    if (int r = f32pass(BF(Asym), offX, kF32Tol1, kF32Rho1)) return r;
+    if (int r = orthonormalize_b()) return r;
+    for (int pass = 1; pass < o.fp32_passes; ++pass) {
+      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
+      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
+      HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
+      if (int r = f32pass(BF(A), BF(T), kF32Tol2, kF32Rho2)) return r;
+      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, offX, BF(T), 0.0, 0, offXb, s));
+      std::swap(offX, offXb);
+      if (int r = orthonormalize_b()) return r;
+    }
+    S.ms_precond = tp.stop();
+    Timer tg(s);
+    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
+    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
+    HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
+    HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(Vw), offX, s));
+    HIPCHK(launch_get_diag_b(dm, cnt, nmax, BF(A), s));
+    ms_gemm = tg.stop();
+  } else {
+    HIPCHK(launch_set_identity_b(dm, cnt, nmax, BF(Vw), s));
+    S.ms_precond = tp.stop();
+  }
+  // ---- 3. FP64 pivoted Jacobi: persistent launches until every matrix is done
+  Timer tj(s);
+  HIPCHK(launch_reset_b(dm, cnt, s));
+  const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
+  HIPCHK(launch_init_rows_b(dm, cnt, nmax, pivot, use_cert, s));
+  std::vector<JCtl> hc(cnt);
+  std::vector<char> done(cnt, 0);
+  float ms_kernel = 0.f;
+  for (int launch = 0;; ++launch) {
+    std::vector<int> il, ih;
+    int nl = 0, nh = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int i = ord[k];
+      if (done[i]) continue;
+      if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
+      else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
+    }
+    if (il.empty() && ih.empty()) break;
+    if (!il.empty())
+      HIPCHK(hipMemcpyAsync(d_idx_lds, il.data(), il.size() * 4, hipMemcpyHostToDevice, s));
+    if (!ih.empty())
+      HIPCHK(hipMemcpyAsync(d_idx_hbm, ih.data(), ih.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(d_cnt, 0, 8, s));
+    HIPCHK(hipStreamSynchronize(s));
+    Timer tk(s);
+    if (!il.empty())
+      HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, 64, d_cnt, (int)std::min<size_t>(il.size(), 2048), s));
+    if (!ih.empty())
+      HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, 512, d_cnt + 1, (int)std::min<size_t>(ih.size(), 512), s));
+    ms_kernel += tk.stop();
+    HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
+    if (int r = collect()) return r;
+    for (int i = 0; i < cnt; ++i) { hc[i] = hi[i].ctl; done[i] = hc[i].done ? 1 : 0; }
+  }
+  S.ms_jacobi = tj.stop();
+  S.ms_jacobi_kernel = ms_kernel;
+  // ---- 4. polish, sort, output
+  Timer tf(s);
+  if (V && o.polish_v) {
+    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, BF(Vw), BF(Vw), 0.0, 0, BF(R), s));
+    HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s));
+    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, BF(Vw), BF(R), 1.0, BF(Vw), BF(X), s));
+    HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(Vw), BF(X), s));
+  }
+  HIPCHK(launch_sort_output_b(dm, cnt, nmax, s));
+  if (int r = download()) return r;
+  S.ms_finalize = tf.stop();
+  S.ms_gemm = ms_gemm;
+  for (int i = 0; i < cnt; ++i) {
+    const int b = mem[i];
+    int st = hc[i].status == ST_MAXROT ? JE_WARN_MAXROT
+             : (hc[i].status == ST_STALL ? JE_WARN_STALL : JE_OK);
+    info[b] = st;
+    worst = std::max(worst, st);
+    if (stats) {
+      je_stats& x = stats[b];
+      x = S;
+      x.rotations = hc[i].rotations;
+      x.rescans = hc[i].rescans;
+      x.final_max_score = hc[i].final_cert;
+      x.final_off = hc[i].final_off;
+      x.normF = nrm[i];
+      x.thr = hm[i].jd.thr;
+      x.sweeps32 = hm[i].f_pass_sweeps;
+      x.status = st;
+    }
+  }
+  return worst;
+}
+
 int check_args(const double* A, int n, int lda, const double* W, const double* V, int ldv,
                double tol, int pivot, int precond, const je_opts& o) {
   if (!A && n > 0) return -1;
@@ -424,16 +731,27 @@ int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const i
   if (opts) o = *opts;
   else je_opts_default(&o);
   o.pivot_log = nullptr;
-  int worst = JE_OK;
+  // argument checks first: a bad problem rejects the whole call before any work
   for (int b = 0; b < batch; ++b) {
+    int a = check_args(A[b], n[b], lda[b], W[b], V ? V[b] : nullptr, ldv ? ldv[b] : n[b], tol,
+                       pivot, precond, o);
+    if (a) { info[b] = a; return a; }
+    if (n[b] > JE_MAX_N) { info[b] = JE_ERR_TOO_LARGE; return JE_ERR_TOO_LARGE; }
+  }
+  int worst = JE_OK;
+  std::vector<int> mem;
+  for (int b = 0; b < batch; ++b) {
+    if (n[b] >= 2) { mem.push_back(b); info[b] = JE_ERR_DEVICE; continue; }
     je_stats* sb = stats ? &stats[b] : nullptr;
     int r = jacobi_eigh_ex(A[b], n[b], lda[b], W[b], V ? V[b] : nullptr, ldv ? ldv[b] : n[b], tol,
                            pivot, precond, &o, sb, stream);
     info[b] = r;
-    if (r < 0) return r;
-    worst = std::max(worst, r);  // errors (>= 3) rank above warnings (1, 2)
+    worst = std::max(worst, r);
   }
-  return worst;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int r = solve_batched(mem, A, n, lda, W, V, ldv, tol, pivot, precond, o, info, stats,
+                        (hipStream_t)stream);
+  return std::max(worst, r);  // errors (>= 3) rank above warnings (1, 2)
 }
 
 size_t jacobi_workspace_size(int n, int precond) {

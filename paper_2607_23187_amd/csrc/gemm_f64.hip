@@ -17,10 +17,10 @@ constexpr int GB = 64;   // tile of C
 constexpr int GK = 16;   // K step
 
 template <int TRANSA>
-__global__ __launch_bounds__(256) void k_dgemm(int n, double alpha, const double* __restrict__ A,
-                                               int lda, const double* __restrict__ B, int ldb,
-                                               double beta, const double* Cin, int ldcin,
-                                               double* C, int ldc) {
+__device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __restrict__ A,
+                                           int lda, const double* __restrict__ B, int ldb,
+                                           double beta, const double* Cin, int ldcin, double* C,
+                                           int ldc) {
   __shared__ double sA[GK][GB + 2];  // sA[k][i] = op(A)[i0 + i][k0 + k]
   __shared__ double sB[GK][GB + 2];  // sB[k][j] = B[k0 + k][j0 + j]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -85,6 +85,55 @@ __global__ __launch_bounds__(256) void k_dgemm(int n, double alpha, const double
       }
 }
 
+template <int TRANSA>
+__global__ __launch_bounds__(256) void k_dgemm(int n, double alpha, const double* __restrict__ A,
+                                               int lda, const double* __restrict__ B, int ldb,
+                                               double beta, const double* Cin, int ldcin,
+                                               double* C, int ldc) {
+  dgemm_tile<TRANSA>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc);
+}
+
+__device__ __forceinline__ double* bm_ptr(BMat& b, size_t off) {
+  return *reinterpret_cast<double**>(reinterpret_cast<char*>(&b) + off);
+}
+
+// One product per matrix of a batch, operands chosen by BMat field offsets (leading
+// dimension b.ld for all of them); tiles past the matrix's n exit.
+template <int TRANSA>
+__global__ __launch_bounds__(256) void k_dgemm_b(BMat* __restrict__ mats, double alpha,
+                                                 size_t offA, size_t offB, double beta,
+                                                 size_t offCin, size_t offC) {
+  BMat& b = mats[blockIdx.z];
+  const int n = b.n;
+  if ((int)blockIdx.y * GB >= n || (int)blockIdx.x * GB >= n) return;
+  dgemm_tile<TRANSA>(n, alpha, bm_ptr(b, offA), b.ld, bm_ptr(b, offB), b.ld, beta,
+                     beta != 0.0 ? bm_ptr(b, offCin) : nullptr, b.ld, bm_ptr(b, offC), b.ld);
+}
+
+hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
+                          size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s) {
+  int nb = (nmax + GB - 1) / GB;
+  dim3 g(nb, nb, count), bl(256);
+  if (transA)
+    hipLaunchKernelGGL(k_dgemm_b<1>, g, bl, 0, s, m, alpha, offA, offB, beta, offCin, offC);
+  else
+    hipLaunchKernelGGL(k_dgemm_b<0>, g, bl, 0, s, m, alpha, offA, offB, beta, offCin, offC);
+  return hipGetLastError();
+}
+
+__global__ void k_add_identity_b(BMat* __restrict__ mats, size_t off, double scale) {
+  BMat& b = mats[blockIdx.y];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < b.n) bm_ptr(b, off)[(size_t)i * b.ld + i] += scale;
+}
+
+hipError_t launch_add_identity_b(BMat* m, int count, int nmax, size_t off, double scale,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_add_identity_b, dim3((nmax + 255) / 256, count), dim3(256), 0, s, m, off,
+                     scale);
+  return hipGetLastError();
+}
+
 hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int lda, const double* B,
                         int ldb, double beta, const double* Cin, int ldcin, double* C, int ldc,
                         hipStream_t s) {
@@ -108,8 +157,7 @@ hipError_t launch_add_identity(double* C, int n, int ldc, double scale, hipStrea
 }
 
 // A <- (A + A^T) / 2, both halves from the same sum so that A is exactly symmetric.
-__global__ __launch_bounds__(256) void k_symmetrize(double* A, int n, int ld) {
-  const int bi = blockIdx.y, bj = blockIdx.x;
+__device__ __forceinline__ void symmetrize_tile(double* A, int n, int ld, int bi, int bj) {
   if (bi > bj) return;
   __shared__ double t1[32][33], t2[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -127,6 +175,22 @@ __global__ __launch_bounds__(256) void k_symmetrize(double* A, int n, int ld) {
     int i2 = j0 + r, j2 = i0 + tx;
     if (i2 < n && j2 < n) A[(size_t)i2 * ld + j2] = 0.5 * (t1[tx][r] + t2[r][tx]);
   }
+}
+
+__global__ __launch_bounds__(256) void k_symmetrize(double* A, int n, int ld) {
+  symmetrize_tile(A, n, ld, blockIdx.y, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_symmetrize_b(BMat* __restrict__ mats, size_t off) {
+  BMat& b = mats[blockIdx.z];
+  if ((int)blockIdx.y * 32 >= b.n || (int)blockIdx.x * 32 >= b.n) return;
+  symmetrize_tile(bm_ptr(b, off), b.n, b.ld, blockIdx.y, blockIdx.x);
+}
+
+hipError_t launch_symmetrize_b(BMat* m, int count, int nmax, size_t off, hipStream_t s) {
+  int nb = (nmax + 31) / 32;
+  hipLaunchKernelGGL(k_symmetrize_b, dim3(nb, nb, count), dim3(256), 0, s, m, off);
+  return hipGetLastError();
 }
 
 hipError_t launch_symmetrize(double* A, int n, int ld, hipStream_t s) {

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -28,10 +30,10 @@ namespace je {
 // diag[k] = a_kk, nonfinite flag.
 constexpr int kTile = 32;
 
-__global__ __launch_bounds__(256) void k_symcopy(const double* __restrict__ Au, int n, int lda,
-                                                 double* __restrict__ A, int ld,
-                                                 double* __restrict__ diag, int* nonfinite) {
-  const int bi = blockIdx.y, bj = blockIdx.x;
+__device__ __forceinline__ void symcopy_tile(const double* __restrict__ Au, int n, int lda,
+                                             double* __restrict__ A, int ld,
+                                             double* __restrict__ diag, int* nonfinite, int bi,
+                                             int bj) {
   if (bi > bj) return;
   __shared__ double t[kTile][kTile + 1];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -63,6 +65,56 @@ __global__ __launch_bounds__(256) void k_symcopy(const double* __restrict__ Au, 
   }
 }
 
+__global__ __launch_bounds__(256) void k_symcopy(const double* __restrict__ Au, int n, int lda,
+                                                 double* __restrict__ A, int ld,
+                                                 double* __restrict__ diag, int* nonfinite) {
+  symcopy_tile(Au, n, lda, A, ld, diag, nonfinite, blockIdx.y, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_symcopy_b(BMat* __restrict__ mats) {
+  BMat& b = mats[blockIdx.z];
+  if ((int)blockIdx.y * kTile >= b.n || (int)blockIdx.x * kTile >= b.n) return;
+  symcopy_tile(b.Au, b.n, b.lda, b.Asym, b.ld, b.diag, b.flag, blockIdx.y, blockIdx.x);
+}
+
+__global__ void k_reset_b(BMat* __restrict__ mats, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  mats[i].flag[0] = 0;
+  JCtl* c = mats[i].jd.ctl;
+  c->rotations = 0; c->rescans = 0; c->status = 0; c->done = 0;
+  c->final_sel = 0.0; c->final_cert = 0.0; c->final_off = 0.0;
+}
+
+__global__ void k_collect_b(const BMat* __restrict__ mats, int count, BInfo* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const BMat& b = mats[i];
+  BInfo x;
+  x.normF = b.scal[0];
+  x.rnorm = b.scal[1];
+  x.nonfinite = b.flag[0];
+  x.pad = 0;
+  x.ctl = *b.jd.ctl;
+  out[i] = x;
+}
+
+hipError_t launch_reset_b(BMat* m, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect_b(const BMat* m, int count, BInfo* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_collect_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_symcopy_b(BMat* m, int count, int nmax, hipStream_t s) {
+  int nb = (nmax + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_symcopy_b, dim3(nb, nb, count), dim3(256), 0, s, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_symcopy(const double* Au, int n, int lda, double* A, int ld, double* diag,
                           double* rowsq, int* nonfinite, hipStream_t s) {
   (void)rowsq;
@@ -75,6 +127,21 @@ hipError_t launch_symcopy(const double* Au, int n, int lda, double* A, int ld, d
 __global__ void k_get_diag(const double* __restrict__ A, int n, int ld, double* __restrict__ diag) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) diag[k] = A[(size_t)k * ld + k];
+}
+
+__device__ __forceinline__ double* bm_mat(BMat& b, size_t off) {
+  return *reinterpret_cast<double**>(reinterpret_cast<char*>(&b) + off);
+}
+
+__global__ void k_get_diag_b(BMat* __restrict__ mats, size_t off) {
+  BMat& b = mats[blockIdx.y];
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < b.n) b.diag[k] = bm_mat(b, off)[(size_t)k * b.ld + k];
+}
+
+hipError_t launch_get_diag_b(BMat* m, int count, int nmax, size_t off, hipStream_t s) {
+  hipLaunchKernelGGL(k_get_diag_b, dim3((nmax + 255) / 256, count), dim3(256), 0, s, m, off);
+  return hipGetLastError();
 }
 
 hipError_t launch_get_diag(const double* A, int n, int ld, double* diag, hipStream_t s) {
@@ -109,6 +176,39 @@ __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ par
   if (threadIdx.x == 0) out[0] = sqrt(((w[0] + w[1]) + w[2]) + w[3]);
 }
 
+__global__ __launch_bounds__(256) void k_rowsq_b(BMat* __restrict__ mats, size_t off) {
+  BMat& b = mats[blockIdx.y];
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= b.n) return;
+  const double* A = bm_mat(b, off);
+  double s = 0.0;
+  for (int l = lane; l < b.n; l += 64) {
+    double v = A[(size_t)row * b.ld + l];
+    s += v * v;
+  }
+  s = wave_sum_d(s);
+  if (lane == 0) b.rowsq[row] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_rows_b(BMat* __restrict__ mats, int slot) {
+  BMat& b = mats[blockIdx.x];
+  __shared__ double w[4];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < b.n; k += 256) s += b.rowsq[k];
+  s = wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) b.scal[slot] = sqrt(((w[0] + w[1]) + w[2]) + w[3]);
+}
+
+hipError_t launch_fro2_b(BMat* m, int count, int nmax, size_t off, int out_slot,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_rowsq_b, dim3((nmax + 3) / 4, count), dim3(256), 0, s, m, off);
+  hipLaunchKernelGGL(k_sum_rows_b, dim3(count), dim3(256), 0, s, m, out_slot);
+  return hipGetLastError();
+}
+
 hipError_t launch_fro2(const double* A, int n, int ld, double* partial, double* out,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_rowsq, dim3((n + 3) / 4), dim3(256), 0, s, A, n, ld, partial);
@@ -140,7 +240,7 @@ __device__ __forceinline__ double wave_second(double s1, double s2, int wlane) {
 // score over the other columns; the same for L_kl (greedy + certificate only);
 // off2[k] = sum_{l != k} a_kl^2.
 template <bool GAP>
-__global__ __launch_bounds__(256) void k_init_rows(JDesc d, int use_cert) {
+__device__ __forceinline__ void init_rows_body(const JDesc& d, int use_cert) {
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= d.n) return;
@@ -177,6 +277,25 @@ __global__ __launch_bounds__(256) void k_init_rows(JDesc d, int use_cert) {
     d.off2[k] = o2;
     d.ts[k] = 0;
   }
+}
+
+template <bool GAP>
+__global__ __launch_bounds__(256) void k_init_rows(JDesc d, int use_cert) {
+  init_rows_body<GAP>(d, use_cert);
+}
+
+template <bool GAP>
+__global__ __launch_bounds__(256) void k_init_rows_b(BMat* __restrict__ mats, int use_cert) {
+  const JDesc d = mats[blockIdx.y].jd;
+  init_rows_body<GAP>(d, use_cert);
+}
+
+hipError_t launch_init_rows_b(BMat* m, int count, int nmax, int pivot, int use_cert,
+                              hipStream_t s) {
+  dim3 g((nmax + 3) / 4, count), b(256);
+  if (pivot == 1) hipLaunchKernelGGL(k_init_rows_b<true>, g, b, 0, s, m, use_cert);
+  else hipLaunchKernelGGL(k_init_rows_b<false>, g, b, 0, s, m, use_cert);
+  return hipGetLastError();
 }
 
 hipError_t launch_init_rows(const JDesc& d, hipStream_t s) {
@@ -384,7 +503,7 @@ __device__ __forceinline__ void cand_top2(Cand& x, double v, int col, double a) 
 // current and every load is a contiguous row segment); otherwise rows only, with the
 // per-row write timestamps choosing the current copy of each entry.
 template <int NT, int RM, bool GAP, bool LDSA, bool MIR>
-__global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
+__device__ __forceinline__ void jacobi_body(const JDesc d, long long log_base) {
   constexpr int NW = NT / kWave;
   extern __shared__ double smem[];
   __shared__ Slots<NW> S;
@@ -709,6 +828,30 @@ __global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
   }
 }
 
+template <int NT, int RM, bool GAP, bool LDSA, bool MIR>
+__global__ __launch_bounds__(NT) void k_jacobi(JDesc d, long long log_base) {
+  jacobi_body<NT, RM, GAP, LDSA, MIR>(d, log_base);
+}
+
+// Persistent form for a batch: each workgroup takes the next matrix from a device counter
+// (the host orders idx largest first) and runs the same pivoted Jacobi on it, until the
+// list is exhausted.  Workgroups never wait for each other.
+template <int NT, int RM, bool GAP, bool LDSA, bool MIR>
+__global__ __launch_bounds__(NT) void k_jacobi_queue(BMat* __restrict__ mats,
+                                                     const int* __restrict__ idx, int count,
+                                                     int* counter) {
+  __shared__ int s_next;
+  for (;;) {
+    __syncthreads();  // the previous matrix is finished with LDS
+    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_next;
+    if (t >= count) return;
+    const BMat& b = mats[idx[t]];
+    jacobi_body<NT, RM, GAP, LDSA, MIR>(b.jd, b.log_base);
+  }
+}
+
 // LDS budget of the kernel's dynamic part (diagonal, timestamps, and A if LDS-resident).
 static size_t lds_bytes(int n, bool ldsa) {
   size_t b = (size_t)n * 8 + (size_t)((n + 1) / 2) * 8;
@@ -780,6 +923,49 @@ static hipError_t launch_jacobi_t(const JDesc& d, long long log_base, bool lds, 
   return launch_global<GAP, false>(d, log_base, s);
 }
 
+template <int NT, int RM, bool GAP, bool LDSA>
+static hipError_t launch_queue_one(BMat* m, const int* idx, int count, int nmax, int* counter,
+                                   int grid, hipStream_t s) {
+  size_t sh = lds_bytes(nmax, LDSA);
+  auto fn = k_jacobi_queue<NT, RM, GAP, LDSA, true>;
+  if (sh > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), sh, s, m, idx, count, counter);
+  return hipGetLastError();
+}
+
+// Workgroup shapes of the batched Jacobi: LDS-resident matrices (n <= 128) with one or two
+// waves, HBM-resident ones with 256 or 512 threads; rows per thread = ceil(nmax / threads).
+template <bool GAP>
+static hipError_t launch_queue_t(BMat* m, const int* idx, int count, int nmax, bool lds,
+                                 int threads, int* counter, int grid, hipStream_t s) {
+  if (lds) {
+    if (threads == 128 && nmax <= 128)
+      return launch_queue_one<128, 1, GAP, true>(m, idx, count, nmax, counter, grid, s);
+    if (nmax <= 64) return launch_queue_one<64, 1, GAP, true>(m, idx, count, nmax, counter, grid, s);
+    return launch_queue_one<64, 2, GAP, true>(m, idx, count, nmax, counter, grid, s);
+  }
+  if (threads == 256) {
+    if (nmax <= 256) return launch_queue_one<256, 1, GAP, false>(m, idx, count, nmax, counter, grid, s);
+    if (nmax <= 512) return launch_queue_one<256, 2, GAP, false>(m, idx, count, nmax, counter, grid, s);
+  }
+  if (nmax <= 512) return launch_queue_one<512, 1, GAP, false>(m, idx, count, nmax, counter, grid, s);
+  if (nmax <= 1024) return launch_queue_one<512, 2, GAP, false>(m, idx, count, nmax, counter, grid, s);
+  if (nmax <= 2048) return launch_queue_one<512, 4, GAP, false>(m, idx, count, nmax, counter, grid, s);
+  return launch_queue_one<512, 8, GAP, false>(m, idx, count, nmax, counter, grid, s);
+}
+
+hipError_t launch_jacobi_queue(BMat* m, const int* idx, int count, int nmax, int pivot,
+                               bool lds_mode, int threads, int* counter, int grid,
+                               hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (pivot == 1) return launch_queue_t<true>(m, idx, count, nmax, lds_mode, threads, counter, grid, s);
+  return launch_queue_t<false>(m, idx, count, nmax, lds_mode, threads, counter, grid, s);
+}
+
 hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, hipStream_t s) {
   if (d.pivot == 1) return launch_jacobi_t<true>(d, log_base, lds_mode, s);
   return launch_jacobi_t<false>(d, log_base, lds_mode, s);
@@ -817,6 +1003,61 @@ __global__ __launch_bounds__(64) void k_apply_log(double* __restrict__ V, int n,
   }
 }
 
+// Rows of V per workgroup of the log drain: as many as fit 64 KB of LDS, at most 64.
+__host__ __device__ __forceinline__ int apply_rows(int n) {
+  int R = (int)(65536 / ((size_t)n * 8));
+  return R > 64 ? 64 : (R < 1 ? 1 : R);
+}
+
+__global__ __launch_bounds__(64) void k_apply_log_b(BMat* __restrict__ mats) {
+  extern __shared__ double tile[];
+  BMat& b = mats[blockIdx.y];
+  const int n = b.n, R = apply_rows(n);
+  const int r0 = blockIdx.x * R;
+  if (r0 >= n) return;
+  const long long m = b.jd.ctl->rotations - b.log_base;
+  if (m <= 0) return;
+  double* V = b.Vw;
+  const int ldv = b.ld;
+  const RotEntry* log = b.jd.log;
+  const int lane = threadIdx.x;
+  const int rows = min(R, n - r0);
+  for (int idx = lane; idx < rows * n; idx += 64) {
+    int r = idx / n, j = idx - r * n;
+    tile[j * R + r] = V[(size_t)(r0 + r) * ldv + j];
+  }
+  __syncthreads();
+  if (lane < rows) {
+    for (long long e = 0; e < m; ++e) {
+      const RotEntry g = log[e];
+      double* xp = tile + g.p * R + lane;
+      double* xq = tile + g.q * R + lane;
+      const double x = *xp, y = *xq;
+      *xp = g.c * x + g.s * y;
+      *xq = g.c * y - g.s * x;
+    }
+  }
+  __syncthreads();
+  for (int idx = lane; idx < rows * n; idx += 64) {
+    int r = idx / n, j = idx - r * n;
+    V[(size_t)(r0 + r) * ldv + j] = tile[j * R + r];
+  }
+}
+
+// After the drain: the log of every matrix is empty again.
+__global__ void k_log_drained_b(BMat* __restrict__ mats, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) mats[i].log_base = mats[i].jd.ctl->rotations;
+}
+
+hipError_t launch_apply_log_b(BMat* m, int count, int nmax, hipStream_t s) {
+  // blocks per matrix: ceil(n / R(n)) grows with n, so the largest matrix sets the grid
+  const int gx = (nmax + apply_rows(nmax) - 1) / apply_rows(nmax);
+  hipLaunchKernelGGL(k_apply_log_b, dim3(gx, count), dim3(64), 65536, s, m);
+  hipLaunchKernelGGL(k_log_drained_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_apply_log(double* V, int n, int ldv, const RotEntry* log, long long m,
                             hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
@@ -838,6 +1079,37 @@ __global__ void k_set_identity(double* V, int n, int ldv) {
   if (idx >= (size_t)n * n) return;
   int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
   V[(size_t)i * ldv + j] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void k_set_identity_b(BMat* __restrict__ mats, size_t off) {
+  BMat& b = mats[blockIdx.y];
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)b.n * b.n) return;
+  int i = (int)(idx / b.n), j = (int)(idx - (size_t)i * b.n);
+  bm_mat(b, off)[(size_t)i * b.ld + j] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void k_copy_mat_b(BMat* __restrict__ mats, size_t dst, size_t src) {
+  BMat& b = mats[blockIdx.y];
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)b.n * b.n) return;
+  int i = (int)(idx / b.n), j = (int)(idx - (size_t)i * b.n);
+  bm_mat(b, dst)[(size_t)i * b.ld + j] = bm_mat(b, src)[(size_t)i * b.ld + j];
+}
+
+hipError_t launch_set_identity_b(BMat* m, int count, int nmax, size_t off, hipStream_t s) {
+  size_t tot = (size_t)nmax * nmax;
+  hipLaunchKernelGGL(k_set_identity_b, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0,
+                     s, m, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_mat_b(BMat* m, int count, int nmax, size_t dst, size_t src,
+                             hipStream_t s) {
+  size_t tot = (size_t)nmax * nmax;
+  hipLaunchKernelGGL(k_copy_mat_b, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0, s,
+                     m, dst, src);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_identity(double* V, int n, int ldv, hipStream_t s) {
@@ -882,6 +1154,56 @@ __global__ __launch_bounds__(256) void k_permute_out(const double* __restrict__ 
     int k = k0 + r, i = i0 + tx;
     if (i < n && k < n) Vout[(size_t)rank[k] * ldvo + i] = t[tx][r];
   }
+}
+
+__global__ __launch_bounds__(256) void k_rank_b(BMat* __restrict__ mats) {
+  extern __shared__ double sd[];
+  BMat& b = mats[blockIdx.y];
+  const int n = b.n;
+  if ((int)blockIdx.x * 256 >= n) return;
+  for (int l = threadIdx.x; l < n; l += 256) sd[l] = b.diag[l];
+  __syncthreads();
+  int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  double v = sd[k];
+  int r = 0;
+  for (int l = 0; l < n; ++l) {
+    double u = sd[l];
+    r += (u < v) || (u == v && l < k);
+  }
+  b.rank[k] = r;
+  b.Wout[r] = v;
+}
+
+__global__ __launch_bounds__(256) void k_permute_out_b(BMat* __restrict__ mats) {
+  BMat& b = mats[blockIdx.z];
+  const int n = b.n;
+  if (!b.Vout || (int)blockIdx.y * kTile >= n || (int)blockIdx.x * kTile >= n) return;
+  __shared__ double t[kTile][kTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
+  for (int r = ty; r < kTile; r += 8) {
+    int i = i0 + r, k = k0 + tx;
+    t[r][tx] = (i < n && k < n) ? b.Vw[(size_t)i * b.ld + k] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < kTile; r += 8) {
+    int k = k0 + r, i = i0 + tx;
+    if (i < n && k < n) b.Vout[(size_t)b.rank[k] * b.ldv + i] = t[tx][r];
+  }
+}
+
+hipError_t launch_sort_output_b(BMat* m, int count, int nmax, hipStream_t s) {
+  size_t sh = (size_t)nmax * 8;
+  if (sh > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rank_b,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_rank_b, dim3((nmax + 255) / 256, count), dim3(256), sh, s, m);
+  int nb = (nmax + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_permute_out_b, dim3(nb, nb, count), dim3(256), 0, s, m);
+  return hipGetLastError();
 }
 
 hipError_t launch_sort_output(const double* diag, int n, const double* Vw, int ldw, double* W,

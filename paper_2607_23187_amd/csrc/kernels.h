@@ -87,4 +87,70 @@ hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq
                            void* scratch, int max_sweeps, double tol, double rho, int* sweeps,
                            hipStream_t s);
 
+// ------------------------------------------------------------------ batches
+// One matrix of a batch (device memory).  The batched kernels take an array of these and
+// put the matrix index in their last grid dimension; blocks past a matrix's size exit, so
+// one launch covers matrices of uneven n.  Workspace matrices are row-major n x ld.
+struct BMat {
+  const double* Au; int n, lda;      // input (column-major, upper triangle read)
+  double* Wout; double* Vout; int ldv;
+  int ld;
+  double *Asym, *A, *Vw, *X, *Xb, *T, *R;
+  double *diag, *rowsq, *scal;       // scal[0] = ||A||_F, scal[1] = ||I - X^T X||_F
+  int *rank, *flag;                  // flag[0]: non-finite input
+  // FP32 stage (np = n padded to 32, nb = np / 16 blocks, nb - 1 rounds per sweep)
+  float *A32, *V32, *U;
+  double* part;
+  int np, nb;
+  int f_round, f_sweeps, f_done, f_pass_sweeps;
+  double f_off, f_nrm;
+  // FP64 Jacobi phase
+  JDesc jd;
+  long long log_base;
+  int j_done;
+};
+
+// Per-matrix results gathered into one array, so the host reads a batch with one copy.
+struct BInfo {
+  double normF, rnorm;
+  int nonfinite, pad;
+  JCtl ctl;
+};
+
+// field of a BMat that holds an n x ld FP64 matrix, as an offset for the generic kernels
+#define BM_FIELD(f) offsetof(::je::BMat, f)
+
+hipError_t launch_symcopy_b(BMat* m, int count, int nmax, hipStream_t s);
+// flag[0] = 0 and the Jacobi control block zeroed, for every matrix
+hipError_t launch_reset_b(BMat* m, int count, hipStream_t s);
+hipError_t launch_collect_b(const BMat* m, int count, BInfo* out, hipStream_t s);
+hipError_t launch_fro2_b(BMat* m, int count, int nmax, size_t off, int out_slot,
+                         hipStream_t s);
+hipError_t launch_get_diag_b(BMat* m, int count, int nmax, size_t off, hipStream_t s);
+hipError_t launch_set_identity_b(BMat* m, int count, int nmax, size_t off, hipStream_t s);
+hipError_t launch_copy_mat_b(BMat* m, int count, int nmax, size_t dst, size_t src, hipStream_t s);
+hipError_t launch_init_rows_b(BMat* m, int count, int nmax, int pivot, int use_cert,
+                              hipStream_t s);
+// Persistent Jacobi over the matrices idx[0..count) (one workgroup per matrix at a time,
+// taken from a device counter in the given order); lds_mode as for launch_jacobi.
+hipError_t launch_jacobi_queue(BMat* m, const int* idx, int count, int nmax, int pivot,
+                               bool lds_mode, int threads, int* counter, int grid,
+                               hipStream_t s);
+hipError_t launch_apply_log_b(BMat* m, int count, int nmax, hipStream_t s);
+hipError_t launch_sort_output_b(BMat* m, int count, int nmax, hipStream_t s);
+hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
+                          size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s);
+hipError_t launch_add_identity_b(BMat* m, int count, int nmax, size_t off, double scale,
+                                 hipStream_t s);
+hipError_t launch_symmetrize_b(BMat* m, int count, int nmax, size_t off, hipStream_t s);
+// FP32 stage of a batch: fl32 of the matrix at `off` (padded), V32 = I, sweeps with the
+// given stop rule until every matrix is done or max_sweeps; then the first n columns of
+// V32 (FP64) into the matrix at `qoff`.  `flags` is a device int the driver polls.
+size_t precond_f32_bytes_b(int n);
+hipError_t run_precond_f32_b(BMat* m, int count, int nmax, const int* prefix_solve,
+                             const int* prefix_vt, const int* prefix_pa, int tot_solve,
+                             int tot_vt, int tot_pa, int max_rounds, size_t off, size_t qoff,
+                             int max_sweeps, double tol, double rho, int* pending,
+                             hipStream_t s);
+
 }  // namespace je

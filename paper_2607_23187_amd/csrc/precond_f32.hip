@@ -491,6 +491,243 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ batches
+// Every matrix of a batch runs the same blocked FP32 Jacobi (blocks of 16 rows) at its own
+// pace: a step performs the next round of every matrix not yet done (subproblem solves,
+// then the A and V block updates), and a control kernel closes a sweep when a matrix's
+// round counter wraps (off-norm, stop rule).  Blocks of a launch are spread over the
+// matrices by prefix sums of their per-matrix block counts.
+constexpr int BPB = 16;
+
+__device__ __forceinline__ int find_mat(const int* __restrict__ prefix, int count, int blk) {
+  int lo = 0, hi = count - 1;  // largest m with prefix[m] <= blk
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int2 block_pair(int nb, int r, int k) {
+  int x, y;
+  if (k == 0) { x = nb - 1; y = r; }
+  else { x = (r + k) % (nb - 1); y = (r - k + (nb - 1)) % (nb - 1); }
+  return int2{min(x, y), max(x, y)};
+}
+
+__device__ __forceinline__ float* ubuf_b(const BMat& b, int par) {
+  constexpr int PM = Blk<BPB>::PM;
+  return b.U + (size_t)par * (b.nb / 2) * PM * PM;
+}
+
+__global__ __launch_bounds__(Blk<BPB>::NT) void k_round_solve_b(
+    BMat* __restrict__ mats, const int* __restrict__ prefix, int count, int max_inner,
+    float tol2, float rho2) {
+  constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL;
+  __shared__ __align__(16) float lds[3][PM][PL];
+  const int m = find_mat(prefix, count, blockIdx.x);
+  BMat& b = mats[m];
+  const int k = blockIdx.x - prefix[m];
+  if (b.f_done || k >= b.nb / 2) return;
+  const int r = b.f_round;
+  const int2 pr = block_pair(b.nb, r, k);
+  const int par = (b.f_sweeps * (b.nb - 1) + r) & 1;
+  solve_body<BPB>(lds[0], lds[1], lds[2], b.A32, b.np, pr, ubuf_b(b, par) + (size_t)k * PM * PM,
+                  b.nb == 2 ? max_inner : 1, r == 0 ? 1 : 0, tol2, rho2);
+}
+
+__global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
+    BMat* __restrict__ mats, const int* __restrict__ prefix, int count) {
+  constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL, NT = Blk<BPB>::NT;
+  __shared__ __align__(16) float Up[PM][PL], Ur[PM][PL], Ab[PM][PL];
+  const int m = find_mat(prefix, count, blockIdx.x);
+  BMat& bm = mats[m];
+  const int nb2 = bm.nb / 2;
+  int bl = blockIdx.x - prefix[m];
+  if (bm.f_done || bl >= nb2 * (nb2 - 1) / 2) return;
+  int P = 0;
+  while (bl >= nb2 - 1 - P) { bl -= nb2 - 1 - P; ++P; }
+  const int R = P + 1 + bl;
+  const int r = bm.f_round;
+  const int2 pp = block_pair(bm.nb, r, P), pr = block_pair(bm.nb, r, R);
+  const int par = (bm.f_sweeps * (bm.nb - 1) + r) & 1;
+  const float* Ug = ubuf_b(bm, par) + (size_t)P * PM * PM;
+  const float* Uh = ubuf_b(bm, par) + (size_t)R * PM * PM;
+  float* A = bm.A32;
+  const int np = bm.np, tid = threadIdx.x;
+  for (int e = tid; e < PM * PM; e += NT) {
+    int i = e / PM, j = e % PM;
+    Up[i][j] = Ug[e];
+    Ur[i][j] = Uh[e];
+    Ab[i][j] = A[(size_t)blk_row<BPB>(pp.x, pp.y, i) * np + blk_row<BPB>(pr.x, pr.y, j)];
+  }
+  __syncthreads();
+  const int ti = (tid / (PM / 4)) * 2, tj = (tid % (PM / 4)) * 4;
+  float acc[2][4];
+  tile_gemm<BPB, true, 2>(Up, Ab, ti, tj, acc);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Ab[ti + a][tj + c] = acc[a][c];
+  __syncthreads();
+  tile_gemm<BPB, false, 2>(Ab, Ur, ti, tj, acc);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int gi = blk_row<BPB>(pp.x, pp.y, ti + a), gj = blk_row<BPB>(pr.x, pr.y, tj + c);
+      A[(size_t)gi * np + gj] = acc[a][c];
+      A[(size_t)gj * np + gi] = acc[a][c];
+    }
+}
+
+__global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_v_b(
+    BMat* __restrict__ mats, const int* __restrict__ prefix, int count) {
+  constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL;
+  __shared__ __align__(16) float lds[2][PM][PL];
+  const int m = find_mat(prefix, count, blockIdx.x);
+  BMat& b = mats[m];
+  const int nvt = (b.n + PM - 1) / PM, nb2 = b.nb / 2;
+  const int bl = blockIdx.x - prefix[m];
+  if (b.f_done || bl >= nvt * nb2) return;
+  const int R = bl / nvt, rt = bl - R * nvt;
+  const int r = b.f_round;
+  const int par = (b.f_sweeps * (b.nb - 1) + r) & 1;
+  vtile_body<BPB>(lds[0], lds[1], b.V32, b.n, b.np, rt * PM, block_pair(b.nb, r, R),
+                  ubuf_b(b, par) + (size_t)R * PM * PM);
+}
+
+// off(A32) and ||A32||_F of one matrix by one workgroup (FP64 sums, fixed order).
+__device__ __forceinline__ void off_norm_wg(const float* __restrict__ A, int np, double& off,
+                                            double& nrm) {
+  __shared__ double w[2][4];
+  double so = 0.0, sd = 0.0;
+  for (size_t e = threadIdx.x; e < (size_t)np * np; e += 256) {
+    int i = (int)(e / np), j = (int)(e - (size_t)i * np);
+    double v = A[e];
+    if (i == j) sd += v * v; else so += v * v;
+  }
+  so = wave_sum_fast(so);
+  sd = wave_sum_fast(sd);
+  if ((threadIdx.x & 63) == 0) { w[0][threadIdx.x >> 6] = so; w[1][threadIdx.x >> 6] = sd; }
+  __syncthreads();
+  const double o = ((w[0][0] + w[0][1]) + w[0][2]) + w[0][3];
+  const double d = ((w[1][0] + w[1][1]) + w[1][2]) + w[1][3];
+  off = sqrt(o);
+  nrm = sqrt(o + d);
+}
+
+// Start of a pass: A32 <- fl32(matrix at off) padded, V32 <- I, off-norm, done flags.
+__global__ __launch_bounds__(256) void k_f32_start_b(BMat* __restrict__ mats, size_t off,
+                                                     double tol) {
+  BMat& b = mats[blockIdx.x];
+  const double* S = *reinterpret_cast<double* const*>(reinterpret_cast<const char*>(&b) + off);
+  const int n = b.n, np = b.np;
+  for (size_t e = threadIdx.x; e < (size_t)np * np; e += 256) {
+    int i = (int)(e / np), j = (int)(e - (size_t)i * np);
+    b.A32[e] = (i < n && j < n) ? (float)S[(size_t)i * b.ld + j] : 0.0f;
+  }
+  for (size_t e = threadIdx.x; e < (size_t)n * np; e += 256) {
+    int i = (int)(e / np), j = (int)(e - (size_t)i * np);
+    b.V32[e] = (i == j) ? 1.0f : 0.0f;
+  }
+  __syncthreads();
+  double o, nr;
+  off_norm_wg(b.A32, np, o, nr);
+  if (threadIdx.x == 0) {
+    b.f_round = 0;
+    b.f_sweeps = 0;
+    b.f_off = o;
+    b.f_nrm = nr;
+    b.f_done = (o <= tol * nr) ? 1 : 0;
+  }
+}
+
+// End of a step: advance the round; at the end of a sweep apply the stop rule.
+__global__ __launch_bounds__(256) void k_f32_control_b(BMat* __restrict__ mats, int max_sweeps,
+                                                       double tol, double rho) {
+  BMat& b = mats[blockIdx.x];
+  if (b.f_done) return;
+  const int rounds = b.nb - 1;
+  if (b.f_round + 1 < rounds) {
+    __syncthreads();
+    if (threadIdx.x == 0) b.f_round = b.f_round + 1;
+    return;
+  }
+  double o, nr;
+  off_norm_wg(b.A32, b.np, o, nr);
+  if (threadIdx.x == 0) {
+    const double prev = b.f_off;
+    b.f_sweeps = b.f_sweeps + 1;
+    b.f_pass_sweeps = b.f_pass_sweeps + 1;
+    b.f_round = 0;
+    b.f_off = o;
+    b.f_nrm = nr;
+    if (b.nb == 2 || o <= tol * nr || o >= rho * prev || b.f_sweeps >= max_sweeps) b.f_done = 1;
+  }
+}
+
+__global__ void k_f32_pending_b(const BMat* __restrict__ mats, int count, int* pending) {
+  __shared__ int c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x)
+    if (!mats[i].f_done) atomicAdd(&c, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *pending = c;
+}
+
+__global__ void k_f32_gather_b(BMat* __restrict__ mats, size_t qoff) {
+  BMat& b = mats[blockIdx.y];
+  double* Q = *reinterpret_cast<double**>(reinterpret_cast<char*>(&b) + qoff);
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)b.n * b.n) return;
+  int i = (int)(idx / b.n), j = (int)(idx - (size_t)i * b.n);
+  Q[(size_t)i * b.ld + j] = (double)b.V32[(size_t)i * b.np + j];
+}
+
+size_t precond_f32_bytes_b(int n) {
+  constexpr int PM = Blk<BPB>::PM;
+  size_t np = (size_t)((n + PM - 1) / PM * PM), nb = np / BPB;
+  size_t b = np * np * 4 + (size_t)n * np * 4 + 2 * (nb / 2) * PM * PM * 4;
+  return (b + 255) & ~(size_t)255;
+}
+
+hipError_t run_precond_f32_b(BMat* m, int count, int nmax, const int* prefix_solve,
+                             const int* prefix_vt, const int* prefix_pa, int tot_solve,
+                             int tot_vt, int tot_pa, int max_rounds, size_t off, size_t qoff,
+                             int max_sweeps, double tol, double rho, int* pending,
+                             hipStream_t s) {
+  constexpr int NT = Blk<BPB>::NT;
+  hipLaunchKernelGGL(k_f32_start_b, dim3(count), dim3(256), 0, s, m, off, tol);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // at most max_sweeps sweeps of max_rounds rounds; the pending count is polled once per
+  // sweep of the largest matrix
+  const long long max_steps = (long long)max_sweeps * max_rounds;
+  for (long long step = 0; step < max_steps; ++step) {
+    hipLaunchKernelGGL(k_round_solve_b, dim3(tot_solve), dim3(NT), 0, s, m, prefix_solve, count,
+                       max_sweeps, (float)(tol * tol), (float)(rho * rho));
+    if (tot_pa > 0)
+      hipLaunchKernelGGL(k_round_apply_a_b, dim3(tot_pa), dim3(NT), 0, s, m, prefix_pa, count);
+    hipLaunchKernelGGL(k_round_apply_v_b, dim3(tot_vt), dim3(NT), 0, s, m, prefix_vt, count);
+    hipLaunchKernelGGL(k_f32_control_b, dim3(count), dim3(256), 0, s, m, max_sweeps, tol, rho);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((step + 1) % max_rounds == 0) {
+      int h = 0;
+      hipLaunchKernelGGL(k_f32_pending_b, dim3(1), dim3(256), 0, s, m, count, pending);
+      if ((e = hipMemcpyAsync(&h, pending, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (h == 0) break;
+    }
+  }
+  size_t tot = (size_t)nmax * nmax;
+  hipLaunchKernelGGL(k_f32_gather_b, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0, s,
+                     m, qoff);
+  return hipGetLastError();
+}
+
 hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq, void* scratch,
                            int max_sweeps, double tol, double rho, int* sweeps, hipStream_t s) {
   if (block_rows(n) == 16)

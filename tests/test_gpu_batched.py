@@ -1,0 +1,119 @@
+"""Batched solves (one launch sequence for many matrices of uneven size) through the C ABI.
+
+* precond='none': each matrix's eigenvalues and rotation count are bit-identical to the
+  single-problem path (whose pivot sequences equal the oracle's; the per-rotation
+  arithmetic does not depend on the workgroup shape) and to the oracle itself.
+* precond='fp32': every matrix meets the FP64 accuracy bar against its known spectrum
+  (10 n u ||A||_2) with ||V^T V - I||_F <= 10 n u, and its status is OK.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_23187_amd import inputs as I
+from paper_2607_23187_amd import jacobi as J
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+SIZES = [2, 3, 17, 40, 64, 65, 100, 128, 129, 200, 300, 520]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def problems(sizes, seed):
+    out = []
+    for i, n in enumerate(sizes):
+        if n >= 8:
+            p = I.clustered(n, seed=seed + i, size=4, offset=1e-9)
+            out.append((p.a, p.lam))
+        else:
+            a = I.random_symmetric(n, seed=seed + i)
+            out.append((a, np.linalg.eigvalsh(a)))
+    return out
+
+
+def tol_for(a, lam):
+    n = a.shape[0]
+    return 10 * n * U * np.max(np.abs(lam)) / np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("pivot", ["greedy", "gap"])
+def test_batched_plain_equals_single_and_oracle(pivot):
+    probs = problems(SIZES, 7100)
+    # one tolerance for the whole batch: the tightest of the members
+    tol = min(tol_for(a, lam) for a, lam in probs)
+    mats = [torch.from_numpy(a).cuda() for a, _ in probs]
+    say("batched plain", pivot, [a.shape[0] for a, _ in probs])
+    status, res = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="none")
+    assert status == J.OK
+    for (a, lam), m, r in zip(probs, mats, res):
+        n = a.shape[0]
+        assert r.status == J.OK
+        one = J.eigh(m, tol=tol, pivot=pivot, precond="none")
+        assert r.stats["rotations"] == one.stats["rotations"], n
+        assert torch.equal(r.w, one.w), n
+        normF = np.linalg.norm(a)
+        thr = O.threshold(O.STOP_CERT, tol, n, normF)
+        ref = O.jacobi(a, pivot=O.GAP if pivot == "gap" else O.GREEDY, stop=O.STOP_CERT,
+                       thr=thr, scan=1, want_vj=False)
+        assert r.stats["rotations"] == ref.rotations, n
+        assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a))), n
+        v = r.v.cpu().numpy()
+        assert np.linalg.norm(v.T @ v - np.eye(n)) <= 10 * n * U
+
+
+@pytest.mark.parametrize("pivot", ["greedy", "gap"])
+def test_batched_preconditioned_accuracy(pivot):
+    sizes = [2, 5, 31, 32, 33, 64, 97, 128, 160, 256, 333, 512]
+    probs = problems(sizes, 7300)
+    tol = min(tol_for(a, lam) for a, lam in probs)
+    mats = [torch.from_numpy(a).cuda() for a, _ in probs]
+    say("batched fp32", pivot, sizes)
+    status, res = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="fp32")
+    assert status == J.OK
+    for (a, lam), r in zip(probs, res):
+        n = a.shape[0]
+        assert r.status == J.OK, n
+        w = r.w.cpu().numpy()
+        lam2 = np.max(np.abs(lam))
+        assert np.max(np.abs(w - np.sort(lam))) <= 10 * n * U * lam2, n
+        v = r.v.cpu().numpy()
+        assert np.linalg.norm(v.T @ v - np.eye(n)) <= 10 * n * U, n
+        # eigenpairs: the certificate bounds every remaining L_ij by thr, hence every
+        # remaining |a_ij| by sqrt(thr (|delta| + |a_ij|)) <= sqrt(4 thr ||A||_2); the
+        # residual of the pairs is at most the Frobenius norm of those entries
+        normF = np.linalg.norm(a)
+        thr = tol * normF / (2.0 * n * (n - 1))
+        resid = np.linalg.norm(a @ v - v * w[None, :])
+        assert resid <= n * np.sqrt(4 * thr * lam2) + 100 * n * U * normF, n
+
+
+def test_batched_repeatable_and_order_independent():
+    """The same matrix gives the same bits alone, in a batch, and at another batch position."""
+    probs = problems([150, 40, 300, 64], 7500)
+    tol = min(tol_for(a, lam) for a, lam in probs)
+    mats = [torch.from_numpy(a).cuda() for a, _ in probs]
+    _, r1 = J.eigh_batched(mats, tol=tol, pivot="gap", precond="fp32")
+    _, r2 = J.eigh_batched(mats[::-1], tol=tol, pivot="gap", precond="fp32")
+    _, r3 = J.eigh_batched([mats[2]], tol=tol, pivot="gap", precond="fp32")
+    for i in range(4):
+        assert torch.equal(r1[i].w, r2[3 - i].w)
+        assert torch.equal(r1[i].v, r2[3 - i].v)
+    assert torch.equal(r1[2].w, r3[0].w)
+
+
+def test_batched_nonfinite_member():
+    probs = problems([40, 60], 7700)
+    a_bad = probs[1][0].copy()
+    a_bad[3, 5] = a_bad[5, 3] = np.nan
+    mats = [torch.from_numpy(probs[0][0]).cuda(), torch.from_numpy(a_bad).cuda()]
+    status, res = J.eigh_batched(mats, tol=1e-12, pivot="gap", precond="fp32")
+    assert res[0].status == J.OK
+    assert res[1].status == J.ERR_NONFINITE
+    assert status == J.ERR_NONFINITE
