@@ -390,14 +390,18 @@ void bws_carve(char* p, BMat& b, int n, int precond, long long cap) {
   d.log = (RotEntry*)take((size_t)cap * sizeof(RotEntry));
   d.log_cap = cap;
   if (precond) {
-    constexpr int PM = 32;
+    const int PB = precond_f32_block_b(), PM = 2 * PB;
     const int np = (n + PM - 1) / PM * PM;
     char* f = (char*)take(precond_f32_bytes_b(n));
     b.np = np;
-    b.nb = np / 16;
+    b.nb = np / PB;
     b.A32 = (float*)f;
     b.V32 = b.A32 + (size_t)np * np;
     b.U = b.V32 + (size_t)n * np;
+    const size_t nb2 = (size_t)b.nb / 2;
+    const size_t fb = ((size_t)np * np * 4 + (size_t)n * np * 4 + 2 * nb2 * PM * PM * 4 + 255) &
+                      ~(size_t)255;
+    b.part = (double*)(f + fb);
   }
 }
 
@@ -426,10 +430,7 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   BMat* dm = (BMat*)mp; mp += al((size_t)cnt * sizeof(BMat));
   int* d_idx_lds = (int*)mp; mp += al((size_t)cnt * 4 + 4);
   int* d_idx_hbm = (int*)mp; mp += al((size_t)cnt * 4 + 4);
-  int* d_pre_solve = (int*)mp; mp += al((size_t)cnt * 4 + 4);
-  int* d_pre_vt = (int*)mp; mp += al((size_t)cnt * 4 + 4);
-  int* d_pre_pa = (int*)mp; mp += al((size_t)cnt * 4 + 4);
-  mp += 2 * al((size_t)cnt * 4 + 4);
+  int* d_work = (int*)mp; mp += 5 * al((size_t)cnt * 4 + 4);  // FP32 stage launch lists
   int* d_cnt = (int*)mp;  // [0], [1] queue counters, [2] pending
   mp += al(64);
   BInfo* d_info = (BInfo*)mp;
@@ -538,25 +539,11 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
     return JE_OK;
   };
   if (precond) {
-    // FP32 stage tables: per-matrix block counts of the three round kernels
-    std::vector<int> ps(cnt + 1), pv(cnt + 1), pa(cnt + 1);
-    int max_rounds = 1;
-    ps[0] = pv[0] = pa[0] = 0;
-    for (int i = 0; i < cnt; ++i) {
-      const int nb2 = hm[i].nb / 2, nvt = (hm[i].n + 31) / 32;
-      ps[i + 1] = ps[i] + nb2;
-      pv[i + 1] = pv[i] + nvt * nb2;
-      pa[i + 1] = pa[i] + nb2 * (nb2 - 1) / 2;
-      max_rounds = std::max(max_rounds, hm[i].nb - 1);
-    }
-    HIPCHK(hipMemcpyAsync(d_pre_solve, ps.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_pre_vt, pv.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_pre_pa, pa.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> nv(cnt);
+    for (int i = 0; i < cnt; ++i) nv[i] = hm[i].n;
     auto f32pass = [&](size_t src, size_t dst, double t, double r) -> int {
-      HIPCHK(run_precond_f32_b(dm, cnt, nmax, d_pre_solve, d_pre_vt, d_pre_pa, ps[cnt], pv[cnt],
-                               pa[cnt], max_rounds, src, dst, o.fp32_max_sweeps, t, r,
-                               d_cnt + 2, s));
+      HIPCHK(run_precond_f32_b(dm, nv.data(), cnt, nmax, d_work, src, dst, o.fp32_max_sweeps, t,
+                               r, s));
       return JE_OK;
     };
     if (int r = f32pass(BF(Asym), offX, kF32Tol1, kF32Rho1)) return r;

@@ -98,7 +98,7 @@ struct BMat {
   double *Asym, *A, *Vw, *X, *Xb, *T, *R;
   double *diag, *rowsq, *scal;       // scal[0] = ||A||_F, scal[1] = ||I - X^T X||_F
   int *rank, *flag;                  // flag[0]: non-finite input
-  // FP32 stage (np = n padded to 32, nb = np / 16 blocks, nb - 1 rounds per sweep)
+  // FP32 stage (np = n padded to 2 PB, nb = np / PB blocks, nb - 1 rounds per sweep)
   float *A32, *V32, *U;
   double* part;
   int np, nb;
@@ -144,13 +144,13 @@ hipError_t launch_add_identity_b(BMat* m, int count, int nmax, size_t off, doubl
                                  hipStream_t s);
 hipError_t launch_symmetrize_b(BMat* m, int count, int nmax, size_t off, hipStream_t s);
 // FP32 stage of a batch: fl32 of the matrix at `off` (padded), V32 = I, sweeps with the
-// given stop rule until every matrix is done or max_sweeps; then the first n columns of
-// V32 (FP64) into the matrix at `qoff`.  `flags` is a device int the driver polls.
+// given stop rule until every matrix is done (each at its own pace, at most max_sweeps);
+// then the first n columns of V32 (FP64) into the matrix at `qoff`.  nvec: host array of
+// the sizes; dwork: device ints, 5 per matrix.
 size_t precond_f32_bytes_b(int n);
-hipError_t run_precond_f32_b(BMat* m, int count, int nmax, const int* prefix_solve,
-                             const int* prefix_vt, const int* prefix_pa, int tot_solve,
-                             int tot_vt, int tot_pa, int max_rounds, size_t off, size_t qoff,
-                             int max_sweeps, double tol, double rho, int* pending,
+int precond_f32_block_b();  // block rows PB of the batched FP32 stage
+hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int* dwork,
+                             size_t off, size_t qoff, int max_sweeps, double tol, double rho,
                              hipStream_t s);
 
 }  // namespace je

@@ -497,7 +497,9 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
 // then the A and V block updates), and a control kernel closes a sweep when a matrix's
 // round counter wraps (off-norm, stop rule).  Blocks of a launch are spread over the
 // matrices by prefix sums of their per-matrix block counts.
-constexpr int BPB = 16;
+constexpr int BPB = 32;
+
+int precond_f32_block_b() { return BPB; }
 
 __device__ __forceinline__ int find_mat(const int* __restrict__ prefix, int count, int blk) {
   int lo = 0, hi = count - 1;  // largest m with prefix[m] <= blk
@@ -520,30 +522,64 @@ __device__ __forceinline__ float* ubuf_b(const BMat& b, int par) {
   return b.U + (size_t)par * (b.nb / 2) * PM * PM;
 }
 
+// Sums of squares of a PM x PM LDS tile by one workgroup of NT threads (FP64, fixed
+// order): the off-diagonal part (weighted) and the diagonal part (diag != 0 only).
+template <int PB>
+__device__ __forceinline__ void tile_sq(float (*T)[Blk<PB>::PL], bool diag, double w,
+                                        double* __restrict__ out) {
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
+  __shared__ double red[2][NT / 64];
+  double so = 0.0, sd = 0.0;
+  for (int e = threadIdx.x; e < PM * PM; e += NT) {
+    const int i = e / PM, j = e % PM;
+    const double v = T[i][j];
+    if (diag && i == j) sd += v * v; else so += v * v;
+  }
+  so = wave_sum_fast(so);
+  sd = wave_sum_fast(sd);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = so; red[1][threadIdx.x >> 6] = sd; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = 0.0, d = 0.0;
+    for (int k = 0; k < NT / 64; ++k) { o += red[0][k]; d += red[1][k]; }
+    out[0] = w * o;
+    out[1] = d;
+  }
+}
+
 __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_solve_b(
-    BMat* __restrict__ mats, const int* __restrict__ prefix, int count, int max_inner,
-    float tol2, float rho2) {
+    BMat* __restrict__ mats, const int* __restrict__ act, const int* __restrict__ prefix,
+    int count, int max_inner, float tol2, float rho2) {
   constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL;
   __shared__ __align__(16) float lds[3][PM][PL];
-  const int m = find_mat(prefix, count, blockIdx.x);
-  BMat& b = mats[m];
-  const int k = blockIdx.x - prefix[m];
+  const int j = find_mat(prefix, count, blockIdx.x);
+  BMat& b = mats[act[j]];
+  const int k = blockIdx.x - prefix[j];
   if (b.f_done || k >= b.nb / 2) return;
   const int r = b.f_round;
   const int2 pr = block_pair(b.nb, r, k);
   const int par = (b.f_sweeps * (b.nb - 1) + r) & 1;
   solve_body<BPB>(lds[0], lds[1], lds[2], b.A32, b.np, pr, ubuf_b(b, par) + (size_t)k * PM * PM,
                   b.nb == 2 ? max_inner : 1, r == 0 ? 1 : 0, tol2, rho2);
+  // the solved block as written back: its upper triangle, mirrored
+  for (int e = threadIdx.x; e < PM * PM; e += Blk<BPB>::NT) {
+    const int i = e / PM, j = e % PM;
+    if (i > j) lds[1][i][j] = lds[0][j][i];
+    else lds[1][i][j] = lds[0][i][j];
+  }
+  __syncthreads();
+  tile_sq<BPB>(lds[1], true, 1.0, b.part + 2 * k);
 }
 
 __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
-    BMat* __restrict__ mats, const int* __restrict__ prefix, int count) {
+    BMat* __restrict__ mats, const int* __restrict__ act, const int* __restrict__ prefix,
+    int count) {
   constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL, NT = Blk<BPB>::NT;
   __shared__ __align__(16) float Up[PM][PL], Ur[PM][PL], Ab[PM][PL];
-  const int m = find_mat(prefix, count, blockIdx.x);
-  BMat& bm = mats[m];
+  const int j = find_mat(prefix, count, blockIdx.x);
+  BMat& bm = mats[act[j]];
   const int nb2 = bm.nb / 2;
-  int bl = blockIdx.x - prefix[m];
+  int bl = blockIdx.x - prefix[j];
   if (bm.f_done || bl >= nb2 * (nb2 - 1) / 2) return;
   int P = 0;
   while (bl >= nb2 - 1 - P) { bl -= nb2 - 1 - P; ++P; }
@@ -580,16 +616,24 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
       A[(size_t)gi * np + gj] = acc[a][c];
       A[(size_t)gj * np + gi] = acc[a][c];
     }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Up[ti + a][tj + c] = acc[a][c];
+  __syncthreads();
+  tile_sq<BPB>(Up, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
 }
 
 __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_v_b(
-    BMat* __restrict__ mats, const int* __restrict__ prefix, int count) {
+    BMat* __restrict__ mats, const int* __restrict__ act, const int* __restrict__ prefix,
+    int count) {
   constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL;
   __shared__ __align__(16) float lds[2][PM][PL];
-  const int m = find_mat(prefix, count, blockIdx.x);
-  BMat& b = mats[m];
+  const int j = find_mat(prefix, count, blockIdx.x);
+  BMat& b = mats[act[j]];
   const int nvt = (b.n + PM - 1) / PM, nb2 = b.nb / 2;
-  const int bl = blockIdx.x - prefix[m];
+  const int bl = blockIdx.x - prefix[j];
   if (b.f_done || bl >= nvt * nb2) return;
   const int R = bl / nvt, rt = bl - R * nvt;
   const int r = b.f_round;
@@ -645,37 +689,35 @@ __global__ __launch_bounds__(256) void k_f32_start_b(BMat* __restrict__ mats, si
 }
 
 // End of a step: advance the round; at the end of a sweep apply the stop rule.
-__global__ __launch_bounds__(256) void k_f32_control_b(BMat* __restrict__ mats, int max_sweeps,
-                                                       double tol, double rho) {
-  BMat& b = mats[blockIdx.x];
+__global__ void k_f32_control_b(BMat* __restrict__ mats, const int* __restrict__ act, int count,
+                                int max_sweeps, double tol, double rho) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  BMat& b = mats[act[t]];
   if (b.f_done) return;
-  const int rounds = b.nb - 1;
-  if (b.f_round + 1 < rounds) {
-    __syncthreads();
-    if (threadIdx.x == 0) b.f_round = b.f_round + 1;
+  if (b.f_round + 1 < b.nb - 1) {
+    b.f_round = b.f_round + 1;
     return;
   }
-  double o, nr;
-  off_norm_wg(b.A32, b.np, o, nr);
-  if (threadIdx.x == 0) {
-    const double prev = b.f_off;
-    b.f_sweeps = b.f_sweeps + 1;
-    b.f_pass_sweeps = b.f_pass_sweeps + 1;
-    b.f_round = 0;
-    b.f_off = o;
-    b.f_nrm = nr;
-    if (b.nb == 2 || o <= tol * nr || o >= rho * prev || b.f_sweeps >= max_sweeps) b.f_done = 1;
-  }
+  // off(A32)^2 and ||A32||_F^2 after the sweep's last round: every block of A was written
+  // by that round (diagonal pair blocks by the solves, the others by the A update), each
+  // with its sums of squares in a fixed slot, added here in slot order
+  const int nb2 = b.nb / 2, np2 = nb2 + nb2 * (nb2 - 1) / 2;
+  double so = 0.0, sd = 0.0;
+  for (int k = 0; k < np2; ++k) { so += b.part[2 * k]; sd += b.part[2 * k + 1]; }
+  const double o = sqrt(so), nr = sqrt(so + sd);
+  const double prev = b.f_off;
+  b.f_sweeps = b.f_sweeps + 1;
+  b.f_pass_sweeps = b.f_pass_sweeps + 1;
+  b.f_round = 0;
+  b.f_off = o;
+  b.f_nrm = nr;
+  if (b.nb == 2 || o <= tol * nr || o >= rho * prev || b.f_sweeps >= max_sweeps) b.f_done = 1;
 }
 
-__global__ void k_f32_pending_b(const BMat* __restrict__ mats, int count, int* pending) {
-  __shared__ int c;
-  if (threadIdx.x == 0) c = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < count; i += blockDim.x)
-    if (!mats[i].f_done) atomicAdd(&c, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) *pending = c;
+__global__ void k_f32_done_b(const BMat* __restrict__ mats, int count, int* __restrict__ done) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) done[i] = mats[i].f_done;
 }
 
 __global__ void k_f32_gather_b(BMat* __restrict__ mats, size_t qoff) {
@@ -689,37 +731,73 @@ __global__ void k_f32_gather_b(BMat* __restrict__ mats, size_t qoff) {
 
 size_t precond_f32_bytes_b(int n) {
   constexpr int PM = Blk<BPB>::PM;
-  size_t np = (size_t)((n + PM - 1) / PM * PM), nb = np / BPB;
-  size_t b = np * np * 4 + (size_t)n * np * 4 + 2 * (nb / 2) * PM * PM * 4;
+  size_t np = (size_t)((n + PM - 1) / PM * PM), nb = np / BPB, nb2 = nb / 2;
+  size_t b = np * np * 4 + (size_t)n * np * 4 + 2 * nb2 * PM * PM * 4;
+  b = (b + 255) & ~(size_t)255;
+  b += (nb2 + nb2 * (nb2 - 1) / 2) * 16;  // per-block sums of squares of a round
   return (b + 255) & ~(size_t)255;
 }
 
-hipError_t run_precond_f32_b(BMat* m, int count, int nmax, const int* prefix_solve,
-                             const int* prefix_vt, const int* prefix_pa, int tot_solve,
-                             int tot_vt, int tot_pa, int max_rounds, size_t off, size_t qoff,
-                             int max_sweeps, double tol, double rho, int* pending,
+hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int* dwork,
+                             size_t off, size_t qoff, int max_sweeps, double tol, double rho,
                              hipStream_t s) {
-  constexpr int NT = Blk<BPB>::NT;
+  constexpr int NT = Blk<BPB>::NT, PM = Blk<BPB>::PM;
   hipLaunchKernelGGL(k_f32_start_b, dim3(count), dim3(256), 0, s, m, off, tol);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // at most max_sweeps sweeps of max_rounds rounds; the pending count is polled once per
-  // sweep of the largest matrix
+  // device work area: done flags, active list, three prefix arrays
+  int* d_done = dwork;
+  int* d_act = dwork + count;
+  int* d_ps = dwork + 2 * count;
+  int* d_pa = dwork + 3 * count;
+  int* d_pv = dwork + 4 * count;
+  std::vector<int> done(count, 0), act, ps, pa, pv;
+  int tps = 0, tpa = 0, tpv = 0, na = 0, max_rounds = 1;
+  // launch lists of the matrices not yet done (rebuilt at every poll)
+  auto rebuild = [&]() -> hipError_t {
+    act.clear(); ps.clear(); pa.clear(); pv.clear();
+    tps = tpa = tpv = 0;
+    max_rounds = 1;
+    for (int i = 0; i < count; ++i) {
+      if (done[i]) continue;
+      const int np = (nvec[i] + PM - 1) / PM * PM, nb = np / BPB, nb2 = nb / 2;
+      const int nvt = (nvec[i] + PM - 1) / PM;
+      act.push_back(i); ps.push_back(tps); pa.push_back(tpa); pv.push_back(tpv);
+      tps += nb2; tpa += nb2 * (nb2 - 1) / 2; tpv += nvt * nb2;
+      max_rounds = std::max(max_rounds, nb - 1);
+    }
+    na = (int)act.size();
+    if (na == 0) return hipSuccess;
+    hipError_t r;
+    if ((r = hipMemcpyAsync(d_act, act.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+    if ((r = hipMemcpyAsync(d_ps, ps.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+    if ((r = hipMemcpyAsync(d_pa, pa.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+    if ((r = hipMemcpyAsync(d_pv, pv.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+    return hipStreamSynchronize(s);  // the host vectors are reused by the next rebuild
+  };
+  auto poll = [&]() -> hipError_t {
+    hipLaunchKernelGGL(k_f32_done_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count, d_done);
+    hipError_t r = hipMemcpyAsync(done.data(), d_done, count * 4, hipMemcpyDeviceToHost, s);
+    if (r == hipSuccess) r = hipStreamSynchronize(s);
+    return r;
+  };
+  if ((e = poll()) != hipSuccess) return e;
+  if ((e = rebuild()) != hipSuccess) return e;
+  // every matrix ends within max_sweeps sweeps of at most max_rounds rounds
   const long long max_steps = (long long)max_sweeps * max_rounds;
-  for (long long step = 0; step < max_steps; ++step) {
-    hipLaunchKernelGGL(k_round_solve_b, dim3(tot_solve), dim3(NT), 0, s, m, prefix_solve, count,
+  const int poll_every = 8;
+  for (long long step = 0; step < max_steps && na > 0; ++step) {
+    hipLaunchKernelGGL(k_round_solve_b, dim3(tps), dim3(NT), 0, s, m, d_act, d_ps, na,
                        max_sweeps, (float)(tol * tol), (float)(rho * rho));
-    if (tot_pa > 0)
-      hipLaunchKernelGGL(k_round_apply_a_b, dim3(tot_pa), dim3(NT), 0, s, m, prefix_pa, count);
-    hipLaunchKernelGGL(k_round_apply_v_b, dim3(tot_vt), dim3(NT), 0, s, m, prefix_vt, count);
-    hipLaunchKernelGGL(k_f32_control_b, dim3(count), dim3(256), 0, s, m, max_sweeps, tol, rho);
+    if (tpa > 0)
+      hipLaunchKernelGGL(k_round_apply_a_b, dim3(tpa), dim3(NT), 0, s, m, d_act, d_pa, na);
+    hipLaunchKernelGGL(k_round_apply_v_b, dim3(tpv), dim3(NT), 0, s, m, d_act, d_pv, na);
+    hipLaunchKernelGGL(k_f32_control_b, dim3((na + 63) / 64), dim3(64), 0, s, m, d_act, na,
+                       max_sweeps, tol, rho);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((step + 1) % max_rounds == 0) {
-      int h = 0;
-      hipLaunchKernelGGL(k_f32_pending_b, dim3(1), dim3(256), 0, s, m, count, pending);
-      if ((e = hipMemcpyAsync(&h, pending, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-      if (h == 0) break;
+    if ((step + 1) % poll_every == 0) {
+      if ((e = poll()) != hipSuccess) return e;
+      if ((e = rebuild()) != hipSuccess) return e;
     }
   }
   size_t tot = (size_t)nmax * nmax;
