@@ -14,8 +14,11 @@ namespace je {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int GB = 64;   // tile of C
-constexpr int GK = 16;   // K step
+constexpr int GK = 32;   // K step
 
+// One 64 x 64 tile of C.  K advances in steps of GK; the operands of the next step are
+// loaded into registers while the matrix cores work on the current one (with a single
+// workgroup per CU at n = 1024 nothing else would hide the global-load latency).
 template <int TRANSA>
 __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __restrict__ A,
                                            int lda, const double* __restrict__ B, int ldb,
@@ -23,6 +26,7 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
                                            int ldc) {
   __shared__ double sA[GK][GB + 2];  // sA[k][i] = op(A)[i0 + i][k0 + k]
   __shared__ double sB[GK][GB + 2];  // sB[k][j] = B[k0 + k][j0 + j]
+  constexpr int PER = GB * GK / 256;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = blockIdx.y * GB, j0 = blockIdx.x * GB;
   const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
@@ -32,25 +36,38 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
+  double ra[PER], rb[PER];
+  // element e of a K step: A part (i, k) with the contiguous index fastest, B part (k, j)
+  auto a_idx = [&](int e, int& i, int& k) {
+    if (TRANSA) { i = e % GB; k = e / GB; }   // A[k][i]: contiguous in i
+    else { k = e % GK; i = e / GK; }          // A[i][k]: contiguous in k
+  };
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * 256;
+      int i, k;
+      a_idx(e, i, k);
+      const int gi = i0 + i, gk = k0 + k;
+      ra[t] = (gi < n && gk < n) ? (TRANSA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk])
+                                 : 0.0;
+      const int j = e % GB, kb = e / GB;
+      const int gkb = k0 + kb, gj = j0 + j;
+      rb[t] = (gkb < n && gj < n) ? B[(size_t)gkb * ldb + gj] : 0.0;
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < n; k0 += GK) {
 #pragma unroll
-    for (int e = tid; e < GB * GK; e += 256) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * 256;
       int i, k;
-      if (TRANSA) { i = e % GB; k = e / GB; }   // A[k][i]: contiguous in i
-      else { k = e % GK; i = e / GK; }          // A[i][k]: contiguous in k
-      int gi = i0 + i, gk = k0 + k;
-      double v = 0.0;
-      if (gi < n && gk < n) v = TRANSA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
-      sA[k][i] = v;
-    }
-#pragma unroll
-    for (int e = tid; e < GB * GK; e += 256) {
-      int j = e % GB, k = e / GB;
-      int gk = k0 + k, gj = j0 + j;
-      sB[k][j] = (gk < n && gj < n) ? B[(size_t)gk * ldb + gj] : 0.0;
+      a_idx(e, i, k);
+      sA[k][i] = ra[t];
+      sB[e / GB][e % GB] = rb[t];
     }
     __syncthreads();
+    if (k0 + GK < n) fetch(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       double av[2], bv[2];
