@@ -149,6 +149,49 @@ const char* jacobi_strerror(int status);
 /* Free the workspace pool of every device. */
 void jacobi_release(void);
 
+/* ---------------------------------------------------------------- serving
+ * A request server for streams of independent problems of different sizes (the served
+ * workload of the batched method; each problem is solved exactly as by jacobi_eigh_ex with
+ * the server's tol, pivot, precond and opts, and gives the same bits as a solve of its own).
+ * `workers` host threads (1..16), each with its own HIP stream on the device current at
+ * creation and its own device buffer of `hbm_budget` bytes, take queued requests in
+ * arrival order: a free worker takes every queued request whose workspaces fit its buffer
+ * together (always at least one; a larger request grows the buffer) and solves them as one
+ * batch.  Batches of different workers run concurrently on the device.
+ *
+ * Ownership: A, W and V of a request are the caller's device memory and must stay valid
+ * (A unmodified) until the request's completion record has been polled.  The server owns
+ * its threads, streams and buffers; jacobi_server_destroy waits for queued requests. */
+typedef struct je_server je_server;
+
+typedef struct {
+  long long tag;        /* the caller's tag from jacobi_server_submit                    */
+  int status;           /* as jacobi_eigh_ex                                              */
+  int n;
+  int batch;            /* requests solved in the same batch                             */
+  int pad;
+  long long rotations;
+  double t_submit;      /* seconds on the server's clock (jacobi_server_clock)           */
+  double t_start;       /* the batch's start                                              */
+  double t_done;        /* the batch's end: results are in W, V                           */
+} je_done;
+
+/* NULL on an invalid argument or device error. */
+je_server* jacobi_server_create(int workers, size_t hbm_budget, double tol, int pivot,
+                                int precond, const je_opts* opts);
+/* Queues one problem (arguments as jacobi_eigh_ex, numbered from 2).  Returns 0, a
+ * negative argument index, JE_ERR_TOO_LARGE, or a device error seen by a worker. */
+int jacobi_server_submit(je_server* srv, const double* A, int n, int lda, double* W, double* V,
+                         int ldv, long long tag);
+/* Moves up to `max` completion records to `out` (host array) and returns their number;
+ * with wait != 0 it first blocks until a record exists or nothing is queued or running. */
+int jacobi_server_poll(je_server* srv, je_done* out, int max, int wait);
+/* Requests queued or being solved. */
+long long jacobi_server_pending(je_server* srv);
+/* Seconds since the server's creation (the clock of je_done). */
+double jacobi_server_clock(je_server* srv);
+void jacobi_server_destroy(je_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/jacobi.h"
@@ -407,10 +411,23 @@ void bws_carve(char* p, BMat& b, int n, int precond, long long cap) {
 
 #define BF(f) BM_FIELD(f)
 
+// Device bytes a batch of these sizes needs (workspaces + per-batch tables).
+size_t batch_bytes(const std::vector<int>& sizes, int precond) {
+  size_t tot = 0;
+  for (int nn : sizes) tot += bws_bytes(nn, precond, kBatchLogCap);
+  const size_t cnt = sizes.size();
+  return tot + al(cnt * sizeof(BMat)) + 8 * al(cnt * 4 + 4) + al(64) + al(cnt * sizeof(BInfo));
+}
+
+// Device memory for one batched solve: the library's pool, or a server worker's buffer.
+using WsGet = void* (*)(size_t bytes, int* err, void* ctx);
+
+void* pool_ws(size_t bytes, int* err, void*) { return pool_get(bytes, err); }
+
 int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
                   const int* lda, double* const* W, double* const* V, const int* ldv, double tol,
                   int pivot, int precond, const je_opts& o, int* info, je_stats* stats,
-                  hipStream_t s) {
+                  hipStream_t s, WsGet ws_get = pool_ws, void* ws_ctx = nullptr) {
   int cnt = (int)mem.size();
   if (cnt == 0) return JE_OK;
   int nmax = 0;
@@ -424,7 +441,7 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   const size_t meta = al((size_t)cnt * sizeof(BMat)) + 8 * al((size_t)cnt * 4 + 4) + al(64) +
                       al((size_t)cnt * sizeof(BInfo));
   int err = JE_OK;
-  char* base = (char*)pool_get(tot + meta, &err);
+  char* base = (char*)ws_get(tot + meta, &err, ws_ctx);
   if (!base) return err;
   char* mp = base + tot;
   BMat* dm = (BMat*)mp; mp += al((size_t)cnt * sizeof(BMat));
@@ -639,6 +656,127 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   return worst;
 }
 
+// ------------------------------------------------------------------ serving
+// Requests wait in a FIFO queue.  Each worker (a host thread with its own stream and
+// device buffer) takes, when it is free, every queued request that fits its buffer, in
+// arrival order (admission by workspace footprint; a request larger than the buffer is
+// taken alone and the buffer grows), and solves them as one batch.  Requests that arrive
+// while the workers are busy join the next batch a worker forms; the workers' batches run
+// concurrently on the device.
+struct SrvReq {
+  const double* A;
+  int n, lda;
+  double* W;
+  double* V;
+  int ldv;
+  long long tag;
+  double t_submit;
+};
+
+struct Server {
+  int device = 0;
+  double tol = 0.0;
+  int pivot = 1, precond = 1;
+  je_opts o{};
+  size_t budget = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<SrvReq> queue;
+  std::deque<je_done> done;
+  long long in_flight = 0;
+  bool stop = false;
+  int error = 0;
+  std::vector<std::thread> workers;
+  std::chrono::steady_clock::time_point t0;
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+struct WorkerBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+void* worker_ws(size_t bytes, int* err, void* ctx) {
+  WorkerBuf* b = (WorkerBuf*)ctx;
+  if (b->bytes < bytes) {
+    if (b->ptr) { (void)hipFree(b->ptr); b->ptr = nullptr; b->bytes = 0; }
+    if (hipMalloc(&b->ptr, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *err = JE_ERR_NOMEM;
+      return nullptr;
+    }
+    b->bytes = bytes;
+  }
+  return b->ptr;
+}
+
+void server_worker(Server* S) {
+  (void)hipSetDevice(S->device);
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->error = JE_ERR_DEVICE;
+    return;
+  }
+  WorkerBuf buf;
+  int err = JE_OK;
+  (void)worker_ws(S->budget, &err, &buf);
+  for (;;) {
+    std::vector<SrvReq> take;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+      if (S->queue.empty()) break;  // stop requested and nothing left
+      std::vector<int> sizes;
+      while (!S->queue.empty()) {
+        sizes.push_back(S->queue.front().n);
+        if (!take.empty() && batch_bytes(sizes, S->precond) > S->budget) break;
+        take.push_back(S->queue.front());
+        S->queue.pop_front();
+      }
+      S->in_flight += (long long)take.size();
+    }
+    const int cnt = (int)take.size();
+    std::vector<const double*> A(cnt);
+    std::vector<double*> W(cnt), V(cnt);
+    std::vector<int> n(cnt), lda(cnt), ldv(cnt), info(cnt, JE_ERR_DEVICE), mem(cnt);
+    std::vector<je_stats> stats(cnt);
+    bool anyv = false;
+    for (int i = 0; i < cnt; ++i) {
+      A[i] = take[i].A; W[i] = take[i].W; V[i] = take[i].V; n[i] = take[i].n;
+      lda[i] = take[i].lda; ldv[i] = take[i].ldv; mem[i] = i;
+      anyv = anyv || V[i] != nullptr;
+    }
+    const double t_start = S->now();
+    (void)solve_batched(mem, A.data(), n.data(), lda.data(), W.data(), anyv ? V.data() : nullptr,
+                        ldv.data(), S->tol, S->pivot, S->precond, S->o, info.data(),
+                        stats.data(), st, worker_ws, &buf);
+    (void)hipStreamSynchronize(st);
+    const double t_end = S->now();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (int i = 0; i < cnt; ++i) {
+        je_done d{};
+        d.tag = take[i].tag;
+        d.status = info[i];
+        d.n = take[i].n;
+        d.batch = cnt;
+        d.rotations = stats[i].rotations;
+        d.t_submit = take[i].t_submit;
+        d.t_start = t_start;
+        d.t_done = t_end;
+        S->done.push_back(d);
+      }
+      S->in_flight -= cnt;
+    }
+    S->cv_done.notify_all();
+  }
+  if (buf.ptr) (void)hipFree(buf.ptr);
+  (void)hipStreamDestroy(st);
+}
+
 int check_args(const double* A, int n, int lda, const double* W, const double* V, int ldv,
                double tol, int pivot, int precond, const je_opts& o) {
   if (!A && n > 0) return -1;
@@ -758,6 +896,93 @@ const char* jacobi_strerror(int status) {
     case JE_ERR_TOO_LARGE: return "n exceeds JE_MAX_N";
     default: return "unknown status";
   }
+}
+
+je_server* jacobi_server_create(int workers, size_t hbm_budget, double tol, int pivot,
+                                int precond, const je_opts* opts) {
+  je_opts o;
+  if (opts) o = *opts;
+  else je_opts_default(&o);
+  o.pivot_log = nullptr;
+  if (workers < 1 || workers > 16) return nullptr;
+  if (!(tol > 0.0) && !(o.abs_thr > 0.0)) return nullptr;
+  if (pivot != JE_PIVOT_GREEDY && pivot != JE_PIVOT_GAP) return nullptr;
+  if (precond != JE_PRECOND_NONE && precond != JE_PRECOND_FP32) return nullptr;
+  Server* S = new Server();
+  if (hipGetDevice(&S->device) != hipSuccess) { delete S; return nullptr; }
+  S->tol = tol; S->pivot = pivot; S->precond = precond; S->o = o;
+  S->budget = std::max<size_t>(hbm_budget, (size_t)1 << 20);
+  S->t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < workers; ++i) S->workers.emplace_back(server_worker, S);
+  return reinterpret_cast<je_server*>(S);
+}
+
+int jacobi_server_submit(je_server* srv, const double* A, int n, int lda, double* W, double* V,
+                         int ldv, long long tag) {
+  Server* S = reinterpret_cast<Server*>(srv);
+  if (!S) return -1;
+  int a = check_args(A, n, lda, W, V, ldv, S->tol, S->pivot, S->precond, S->o);
+  if (a) return a - 1;  // argument k of the single call is argument k + 1 here
+  if (n > JE_MAX_N) return JE_ERR_TOO_LARGE;
+  if (n < 2) {
+    // trivial problems complete at once, through the single-problem call
+    int r = jacobi_eigh_ex(A, n, lda, W, V, ldv, S->tol, S->pivot, S->precond, &S->o, nullptr,
+                           nullptr);
+    std::lock_guard<std::mutex> lk(S->mu);
+    je_done d{};
+    d.tag = tag; d.status = r; d.n = n; d.batch = 1;
+    d.t_submit = d.t_start = d.t_done = S->now();
+    S->done.push_back(d);
+    S->cv_done.notify_all();
+    return JE_OK;
+  }
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->error) return S->error;
+    S->queue.push_back(SrvReq{A, n, lda, W, V, ldv, tag, S->now()});
+  }
+  S->cv_work.notify_one();
+  return JE_OK;
+}
+
+int jacobi_server_poll(je_server* srv, je_done* out, int max, int wait) {
+  Server* S = reinterpret_cast<Server*>(srv);
+  if (!S || (!out && max > 0) || max < 0) return -1;
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (wait)
+    S->cv_done.wait(lk, [&] {
+      return !S->done.empty() || (S->queue.empty() && S->in_flight == 0) || S->error;
+    });
+  int k = 0;
+  while (k < max && !S->done.empty()) {
+    out[k++] = S->done.front();
+    S->done.pop_front();
+  }
+  return k;
+}
+
+long long jacobi_server_pending(je_server* srv) {
+  Server* S = reinterpret_cast<Server*>(srv);
+  if (!S) return -1;
+  std::lock_guard<std::mutex> lk(S->mu);
+  return (long long)S->queue.size() + S->in_flight;
+}
+
+double jacobi_server_clock(je_server* srv) {
+  Server* S = reinterpret_cast<Server*>(srv);
+  return S ? S->now() : -1.0;
+}
+
+void jacobi_server_destroy(je_server* srv) {
+  Server* S = reinterpret_cast<Server*>(srv);
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  for (auto& t : S->workers) t.join();
+  delete S;
 }
 
 void jacobi_release(void) {

@@ -50,7 +50,17 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["je_opts_default", "jacobi_eigh", "jacobi_eigh_ex", "jacobi_eigh_batched",
-           "jacobi_workspace_size", "jacobi_strerror", "jacobi_release"]
+           "jacobi_workspace_size", "jacobi_strerror", "jacobi_release",
+           "jacobi_server_create", "jacobi_server_submit", "jacobi_server_poll",
+           "jacobi_server_pending", "jacobi_server_clock", "jacobi_server_destroy"]
+
+
+class Done(ctypes.Structure):
+    """Mirror of je_done (completion record of a served request)."""
+    _fields_ = [("tag", ctypes.c_longlong), ("status", ctypes.c_int), ("n", ctypes.c_int),
+                ("batch", ctypes.c_int), ("pad", ctypes.c_int), ("rotations", ctypes.c_longlong),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 _lib = None
 
@@ -82,6 +92,18 @@ def load(path: str = LIB_PATH):
     L.jacobi_strerror.restype = ctypes.c_char_p
     L.jacobi_release.argtypes = []
     L.jacobi_release.restype = None
+    L.jacobi_server_create.argtypes = [ip, ctypes.c_size_t, dp, ip, ip, ctypes.POINTER(Opts)]
+    L.jacobi_server_create.restype = vp
+    L.jacobi_server_submit.argtypes = [vp, vp, ip, ip, vp, vp, ip, ctypes.c_longlong]
+    L.jacobi_server_submit.restype = ctypes.c_int
+    L.jacobi_server_poll.argtypes = [vp, ctypes.POINTER(Done), ip, ip]
+    L.jacobi_server_poll.restype = ctypes.c_int
+    L.jacobi_server_pending.argtypes = [vp]
+    L.jacobi_server_pending.restype = ctypes.c_longlong
+    L.jacobi_server_clock.argtypes = [vp]
+    L.jacobi_server_clock.restype = ctypes.c_double
+    L.jacobi_server_destroy.argtypes = [vp]
+    L.jacobi_server_destroy.restype = None
     _lib = L
     return L
 
@@ -189,6 +211,69 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
         out.append(Result(ws[i], vs[i].t() if vs is not None else None, int(info[i]),
                           stats[i].as_dict(), None))
     return status, out
+
+
+class Server:
+    """Request server of the library (jacobi_server_*): submit(A, tag) queues a problem,
+    poll() returns completion records.  Keeps each request's tensors alive until its record
+    has been polled; the solve itself runs in the library's worker threads."""
+
+    def __init__(self, workers: int = 2, hbm_budget: int = 1 << 30, tol: float = 1e-14,
+                 pivot="gap", precond="fp32", stop="cert", want_v: bool = True):
+        L = load()
+        o = default_opts()
+        o.stop = _STOPS[stop]
+        self._want_v = want_v
+        self._h = L.jacobi_server_create(int(workers), int(hbm_budget), float(tol),
+                                         _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o))
+        if not self._h:
+            raise RuntimeError("jacobi_server_create failed")
+        self._live = {}
+
+    def submit(self, a: torch.Tensor, tag: int):
+        _check_device_tensor(a)
+        a = a.contiguous()
+        n = a.shape[0]
+        w = torch.empty(n, dtype=torch.float64, device=a.device)
+        v = torch.empty_like(a) if self._want_v else None
+        torch.cuda.synchronize()  # A is written by the caller's stream; workers use their own
+        r = load().jacobi_server_submit(self._h, ctypes.c_void_p(a.data_ptr()), n, max(1, n),
+                                        ctypes.c_void_p(w.data_ptr()),
+                                        ctypes.c_void_p(v.data_ptr()) if v is not None else None,
+                                        max(1, n), int(tag))
+        if r != 0:
+            raise RuntimeError(f"jacobi_server_submit: status {r}")
+        self._live[int(tag)] = (a, w, v)
+
+    def poll(self, wait: bool = False, max_records: int = 1024):
+        buf = (Done * max_records)()
+        k = load().jacobi_server_poll(self._h, buf, max_records, 1 if wait else 0)
+        out = []
+        for i in range(k):
+            d = buf[i]
+            a, w, v = self._live.pop(int(d.tag))
+            out.append({"tag": int(d.tag), "status": int(d.status), "n": int(d.n),
+                        "batch": int(d.batch), "rotations": int(d.rotations),
+                        "t_submit": d.t_submit, "t_start": d.t_start, "t_done": d.t_done,
+                        "w": w, "v": v.t() if v is not None else None})
+        return out
+
+    def pending(self) -> int:
+        return int(load().jacobi_server_pending(self._h))
+
+    def clock(self) -> float:
+        return float(load().jacobi_server_clock(self._h))
+
+    def close(self):
+        if self._h:
+            load().jacobi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def workspace_size(n: int, precond="fp32") -> int:

@@ -69,3 +69,14 @@ def test_argument_errors_follow_lapack_info_convention():
     IA = ctypes.c_int * 1
     assert L.jacobi_eigh_batched(-1, None, None, None, None, None, None, 1e-12, 1, 1, None,
                                  None, None, None) == -1
+
+
+def test_server_rejects_bad_arguments():
+    """Argument checks of jacobi_server_create run before any device call."""
+    L = J.load()
+    o = J.default_opts()
+    assert not L.jacobi_server_create(0, 1 << 20, 1e-12, 1, 1, ctypes.byref(o))
+    assert not L.jacobi_server_create(2, 1 << 20, 1e-12, 7, 1, ctypes.byref(o))
+    assert not L.jacobi_server_create(2, 1 << 20, -1.0, 1, 1, ctypes.byref(o))
+    assert L.jacobi_server_poll(None, None, 0, 0) == -1
+    assert L.jacobi_server_pending(None) == -1
