@@ -154,10 +154,11 @@ void jacobi_release(void);
  * workload of the batched method; each problem is solved exactly as by jacobi_eigh_ex with
  * the server's tol, pivot, precond and opts, and gives the same bits as a solve of its own).
  * `workers` host threads (1..16), each with its own HIP stream on the device current at
- * creation and its own device buffer of `hbm_budget` bytes, take queued requests in
- * arrival order: a free worker takes every queued request whose workspaces fit its buffer
- * together (always at least one; a larger request grows the buffer) and solves them as one
- * batch.  Batches of different workers run concurrently on the device.
+ * creation and its own device buffer of `hbm_budget` bytes, take queued requests: a free
+ * worker opens a batch with the oldest request and adds, in arrival order, the queued
+ * requests of the same size class (n <= 128, <= 512, <= 1024, larger) while their
+ * workspaces fit its buffer (always at least one; a larger request grows the buffer), and
+ * solves them as one batch.  Batches of different workers run concurrently on the device.
  *
  * Ownership: A, W and V of a request are the caller's device memory and must stay valid
  * (A unmodified) until the request's completion record has been polled.  The server owns

@@ -712,6 +712,8 @@ void* worker_ws(size_t bytes, int* err, void* ctx) {
   return b->ptr;
 }
 
+int size_class(int n) { return n <= 128 ? 0 : (n <= 512 ? 1 : (n <= 1024 ? 2 : 3)); }
+
 void server_worker(Server* S) {
   (void)hipSetDevice(S->device);
   hipStream_t st = nullptr;
@@ -729,12 +731,17 @@ void server_worker(Server* S) {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
       if (S->queue.empty()) break;  // stop requested and nothing left
+      // the oldest request opens the batch; queued requests of its size class join in
+      // arrival order while the batch fits the buffer (a batch lasts as long as its largest
+      // member, so small problems do not wait behind large ones)
       std::vector<int> sizes;
-      while (!S->queue.empty()) {
-        sizes.push_back(S->queue.front().n);
+      const int cls = size_class(S->queue.front().n);
+      for (auto it = S->queue.begin(); it != S->queue.end();) {
+        if (size_class(it->n) != cls) { ++it; continue; }
+        sizes.push_back(it->n);
         if (!take.empty() && batch_bytes(sizes, S->precond) > S->budget) break;
-        take.push_back(S->queue.front());
-        S->queue.pop_front();
+        take.push_back(*it);
+        it = S->queue.erase(it);
       }
       S->in_flight += (long long)take.size();
     }
