@@ -95,6 +95,10 @@ typedef struct je_opts {
   int* pivot_log;            /* device int32[2*pivot_log_cap]: (p, q) of every        */
                              /* rotation of the FP64 phase, 0-based, p < q; NULL = off */
   long long pivot_log_cap;
+  int split_gemm;            /* 1: form Q^T A Q from three-slice BF16 products on the  */
+                             /* matrix cores with FP32 accumulation (FP32-level      */
+                             /* accuracy of A_hat: a precision variant, not FP64-     */
+                             /* accurate eigenvalues); 0: FP64 MFMA products     (0)  */
 } je_opts;
 
 /* Statistics of one solve (host struct, filled before return). */
@@ -113,6 +117,8 @@ typedef struct je_stats {
   float ms_finalize;         /* eigenvectors, polish, sort                          */
   float ms_jacobi_kernel;    /* the persistent Jacobi kernel launches alone (HIP    */
                              /* events on `stream` around each launch)             */
+  double a_hat_off;          /* off(A_hat) = sqrt(sum_{i != j} a_ij^2) of the matrix   */
+                             /* the FP64 phase starts from (0 if not measured)       */
 } je_stats;
 
 void je_opts_default(je_opts* opts);

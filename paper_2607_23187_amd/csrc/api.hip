@@ -262,12 +262,20 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
     S.ms_precond = tp.stop();
     Timer tg(s);
     // A_hat = X^T (A X): T = A X, A_hat = X^T T, then exact symmetry
-    HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
-    HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
+    if (o.split_gemm) {
+      HIPCHK(launch_gemm_split(n, 0, w.Asym, ld, X, ld, w.T, ld, s));
+      HIPCHK(launch_gemm_split(n, 1, X, ld, w.T, ld, w.A, ld, s));
+    } else {
+      HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
+      HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
+    }
     HIPCHK(launch_symmetrize(w.A, n, ld, s));
     HIPCHK(hipMemcpyAsync(Vw, X, (size_t)n * ld * 8, hipMemcpyDeviceToDevice, s));
     Ajac = w.A;
     S.ms_gemm = tg.stop();
+    HIPCHK(launch_offnorm(w.A, n, ld, w.rowsq, w.scal + 2, s));
+    HIPCHK(hipMemcpyAsync(&S.a_hat_off, w.scal + 2, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
   } else {
     HIPCHK(launch_set_identity(Vw, n, ld, s));
     S.ms_precond = tp.stop();
@@ -798,6 +806,7 @@ int check_args(const double* A, int n, int lda, const double* W, const double* V
   if (precond != JE_PRECOND_NONE && precond != JE_PRECOND_FP32) return -9;
   if (o.stop < JE_STOP_CERT || o.stop > JE_STOP_SCORE) return -10;
   if (o.fp32_max_sweeps < 0 || o.fp32_passes < 1 || o.fp32_passes > 2) return -10;
+  if (o.split_gemm != 0 && o.split_gemm != 1) return -10;
   return 0;
 }
 
@@ -816,6 +825,7 @@ void je_opts_default(je_opts* o) {
   o->abs_thr = 0.0;
   o->pivot_log = nullptr;
   o->pivot_log_cap = 0;
+  o->split_gemm = 0;
 }
 
 int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,

@@ -163,6 +163,136 @@ hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int ld
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ split-precision product
+// C = op(A) * B on the BF16 matrix cores (v_mfma_f32_16x16x16_bf16).  Every FP64 operand
+// is split into three BF16 slices, v ~ s0 + s1 + s2 (each the BF16 rounding of the FP64
+// residual left by the previous ones: about 24 significant bits), and the six slice
+// products s_a * s_b with a + b <= 2 are accumulated in FP32, smallest first.  FP32
+// accumulators are added into FP64 every kSplitFlush K steps, so FP32 rounding
+// accumulates over 128 terms rather than n (compensated accumulation).  The result carries
+// FP32-level error (~2^-24 |A| |B|): the precision variant of the Q^T A Q contraction.
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int SK = 16;          // K step (one bf16 MFMA)
+constexpr int kSplitFlush = 8;  // K steps per FP32 accumulation chunk
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ double bf16_value(unsigned short h) {
+  return (double)__uint_as_float((unsigned)h << 16);
+}
+
+__device__ __forceinline__ void split3(double v, unsigned short& s0, unsigned short& s1,
+                                       unsigned short& s2) {
+  s0 = bf16_bits((float)v);
+  const double r1 = v - bf16_value(s0);
+  s1 = bf16_bits((float)r1);
+  const double r2 = r1 - bf16_value(s1);
+  s2 = bf16_bits((float)r2);
+}
+
+template <int TRANSA>
+__global__ __launch_bounds__(256) void k_gemm_split(int n, const double* __restrict__ A, int lda,
+                                                    const double* __restrict__ B, int ldb,
+                                                    double* __restrict__ C, int ldc) {
+  // sA[s][i][k]: slice s of op(A)[i0 + i][k0 + k]; sB[s][j][k]: slice s of B[k0 + k][j0 + j]
+  __shared__ __align__(8) unsigned short sA[3][GB][SK + 4];
+  __shared__ __align__(8) unsigned short sB[3][GB][SK + 4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i0 = blockIdx.y * GB, j0 = blockIdx.x * GB;
+  const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
+  const int lr = lane & 15, lq = lane >> 4;
+  f4 acc[2][2];
+  double acc64[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+    }
+  int chunk = 0;
+  for (int k0 = 0; k0 < n; k0 += SK) {
+#pragma unroll
+    for (int t = 0; t < GB * SK / 256; ++t) {
+      const int e = tid + t * 256;
+      int i, k;
+      if (TRANSA) { i = e % GB; k = e / GB; }   // A[k][i]: contiguous in i
+      else { k = e % SK; i = e / SK; }          // A[i][k]: contiguous in k
+      const int gi = i0 + i, gk = k0 + k;
+      double v = 0.0;
+      if (gi < n && gk < n) v = TRANSA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
+      split3(v, sA[0][i][k], sA[1][i][k], sA[2][i][k]);
+      const int j = e % GB, kb = e / GB;
+      const int gkb = k0 + kb, gj = j0 + j;
+      const double u = (gkb < n && gj < n) ? B[(size_t)gkb * ldb + gj] : 0.0;
+      split3(u, sB[0][j][kb], sB[1][j][kb], sB[2][j][kb]);
+    }
+    __syncthreads();
+    bf4 af[3][2], bfr[3][2];
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[sl][t] = *reinterpret_cast<const bf4*>(&sA[sl][wi + t * 16 + lr][4 * lq]);
+        bfr[sl][t] = *reinterpret_cast<const bf4*>(&sB[sl][wj + t * 16 + lr][4 * lq]);
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        f4 c = acc[a][b];
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[2][a], bfr[0][b], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[1][a], bfr[1][b], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[0][a], bfr[2][b], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[1][a], bfr[0][b], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[0][a], bfr[1][b], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[0][a], bfr[0][b], c, 0, 0, 0);
+        acc[a][b] = c;
+      }
+    __syncthreads();
+    if (++chunk == kSplitFlush) {
+      chunk = 0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[a][b][r] += (double)acc[a][b][r];
+          acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+  // D[i][j] of a 16 x 16 tile sits in lane j + 16 * (i / 4), register i % 4
+  // (A[i][k] in lane i + 16 (k / 4), element k % 4; B[k][j] in lane j + 16 (k / 4)).
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wi + a * 16 + 4 * lq + r;
+        const int j = j0 + wj + b * 16 + lr;
+        if (i < n && j < n) C[(size_t)i * ldc + j] = acc64[a][b][r] + (double)acc[a][b][r];
+      }
+}
+
+hipError_t launch_gemm_split(int n, int transA, const double* A, int lda, const double* B,
+                             int ldb, double* C, int ldc, hipStream_t s) {
+  int nb = (n + GB - 1) / GB;
+  dim3 g(nb, nb), b(256);
+  if (transA) hipLaunchKernelGGL(k_gemm_split<1>, g, b, 0, s, n, A, lda, B, ldb, C, ldc);
+  else hipLaunchKernelGGL(k_gemm_split<0>, g, b, 0, s, n, A, lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
 __global__ void k_add_identity(double* C, int n, int ldc, double scale) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) C[(size_t)i * ldc + i] += scale;

@@ -216,6 +216,28 @@ hipError_t launch_fro2(const double* A, int n, int ld, double* partial, double* 
   return hipGetLastError();
 }
 
+// off(A): per-row sums of the off-diagonal squares, then the fixed-order row sum.
+__global__ __launch_bounds__(256) void k_rowsq_off(const double* __restrict__ A, int n, int ld,
+                                                   double* __restrict__ partial) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int l = lane; l < n; l += 64) {
+    double v = (l == row) ? 0.0 : A[(size_t)row * ld + l];
+    s += v * v;
+  }
+  s = wave_sum_d(s);
+  if (lane == 0) partial[row] = s;
+}
+
+hipError_t launch_offnorm(const double* A, int n, int ld, double* partial, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_rowsq_off, dim3((n + 3) / 4), dim3(256), 0, s, A, n, ld, partial);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partial, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_normf(const double* rowsq, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, rowsq, n, out);
   return hipGetLastError();

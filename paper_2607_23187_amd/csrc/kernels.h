@@ -75,9 +75,16 @@ hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int ld
                         const double* B, int ldb, double beta, const double* Cin, int ldcin,
                         double* C, int ldc, hipStream_t s);
 hipError_t launch_add_identity(double* C, int n, int ldc, double scale, hipStream_t s);
+// C = op(A) * B from three-slice BF16 splits on the matrix cores, FP32 accumulation flushed
+// into FP64 every 128 terms: FP32-level accuracy (the precision variant of Q^T A Q).
+hipError_t launch_gemm_split(int n, int transA, const double* A, int lda, const double* B,
+                             int ldb, double* C, int ldc, hipStream_t s);
 hipError_t launch_symmetrize(double* A, int n, int ld, hipStream_t s);
 hipError_t launch_fro2(const double* A, int n, int ld, double* partial, double* out,
                        hipStream_t s);
+// out[0] = off(A) = sqrt(sum_{i != j} a_ij^2)
+hipError_t launch_offnorm(const double* A, int n, int ld, double* partial, double* out,
+                          hipStream_t s);
 
 // FP32 preconditioner.
 size_t precond_f32_bytes(int n);

@@ -33,7 +33,7 @@ class Opts(ctypes.Structure):
                 ("fp32_max_sweeps", ctypes.c_int), ("fp32_passes", ctypes.c_int),
                 ("max_rotations", ctypes.c_longlong),
                 ("abs_thr", ctypes.c_double), ("pivot_log", ctypes.c_void_p),
-                ("pivot_log_cap", ctypes.c_longlong)]
+                ("pivot_log_cap", ctypes.c_longlong), ("split_gemm", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -43,7 +43,7 @@ class Stats(ctypes.Structure):
                 ("sweeps32", ctypes.c_int), ("status", ctypes.c_int),
                 ("ms_precond", ctypes.c_float), ("ms_gemm", ctypes.c_float),
                 ("ms_jacobi", ctypes.c_float), ("ms_finalize", ctypes.c_float),
-                ("ms_jacobi_kernel", ctypes.c_float)]
+                ("ms_jacobi_kernel", ctypes.c_float), ("a_hat_off", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -139,7 +139,7 @@ def _check_device_tensor(a: torch.Tensor):
 def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop="cert",
          want_v: bool = True, abs_thr: float = 0.0, max_rotations: int = 0,
          polish_v: bool = True, fp32_max_sweeps: int = 20, fp32_passes: int = 2,
-         pivot_log_cap: int = 0,
+         pivot_log_cap: int = 0, split_gemm: bool = False,
          stream: torch.cuda.Stream | None = None, check: bool = True) -> Result:
     """Eigen-decomposition of the symmetric float64 CUDA tensor ``a``.
 
@@ -157,6 +157,7 @@ def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop=
     o.polish_v = 1 if polish_v else 0
     o.fp32_max_sweeps = int(fp32_max_sweeps)
     o.fp32_passes = int(fp32_passes)
+    o.split_gemm = 1 if split_gemm else 0
     o.max_rotations = int(max_rotations)
     o.abs_thr = float(abs_thr)
     plog = None

@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_defaults_and_strings():
     o = J.default_opts()
-    assert (o.stop, o.polish_v, o.fp32_max_sweeps, o.fp32_passes, o.max_rotations, o.abs_thr) == (
-        0, 1, 20, 2, 0, 0.0)
+    assert (o.stop, o.polish_v, o.fp32_max_sweeps, o.fp32_passes, o.max_rotations, o.abs_thr,
+            o.split_gemm) == (0, 1, 20, 2, 0, 0.0, 0)
     assert J.strerror(0) == "ok"
     assert "NaN" in J.strerror(J.ERR_NONFINITE)
     assert J.strerror(-3) == "invalid argument"
