@@ -222,3 +222,23 @@ def test_repeatable_bitwise():
     r2 = J.eigh(gpu(p.a), tol=tol)
     assert torch.equal(r1.w, r2.w) and torch.equal(r1.v, r2.v)
     assert r1.stats["rotations"] == r2.stats["rotations"]
+
+
+@pytest.mark.parametrize("n", [300, 1024])
+def test_fp32_sweep_graph_replay_equals_direct(n, monkeypatch):
+    """The FP32 sweeps replayed from captured graphs (with the stop test's own kernels and
+    host synchronisations between replays) give the same bits as direct launches."""
+    say("graph replay", n)
+    p = I.config_c2(n=n)
+    a = gpu(p.a)
+    tol = 10 * n * U * np.max(np.abs(p.lam)) / np.linalg.norm(p.a)
+    monkeypatch.setenv("JE_F32_GRAPH", "0")
+    r0 = J.eigh(a, tol=tol, pivot="gap", precond="fp32")
+    monkeypatch.setenv("JE_F32_GRAPH", "1")
+    r1 = J.eigh(a, tol=tol, pivot="gap", precond="fp32")
+    r2 = J.eigh(a, tol=tol, pivot="gap", precond="fp32")
+    assert r0.stats["sweeps32"] >= 4  # at least two replays of each parity's graph
+    for r in (r1, r2):
+        assert r.stats["rotations"] == r0.stats["rotations"]
+        assert torch.equal(r.w, r0.w)
+        assert torch.equal(r.v, r0.v)
