@@ -17,6 +17,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -366,6 +367,16 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
 // matrices between launches; unfinished matrices are relaunched.
 constexpr long long kBatchLogCap = 1ll << 16;
 
+// Tuned workgroup shapes of the batched Jacobi phase, per (class, pivot, size bucket).
+// JE_TUNE=0 keeps the default shapes (one wave LDS-resident, 512 threads otherwise).
+std::mutex g_tune_mu;
+std::map<int, int> g_tune;
+
+bool tuning_enabled() {
+  const char* e = std::getenv("JE_TUNE");
+  return !(e && e[0] == '0');
+}
+
 struct BatchLayout {
   size_t bytes = 0;
   std::vector<size_t> off;  // per member: offset of its workspace
@@ -599,6 +610,59 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   HIPCHK(launch_reset_b(dm, cnt, s));
   const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
   HIPCHK(launch_init_rows_b(dm, cnt, nmax, pivot, use_cert, s));
+  // workgroup shape of each class: tuned once per (class, pivot, size bucket) and cached
+  int shape_lds = 64, shape_hbm = 512;
+  {
+    std::vector<int> il, ih;
+    int nl = 0, nh = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int i = ord[k];
+      if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
+      else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
+    }
+    auto tuned = [&](bool lds, const std::vector<int>& lst, int nmx, int* shape) -> int {
+      if (lst.empty()) return JE_OK;
+      // the default shape first; the other replaces it only if it is 5% faster
+      const int a = lds ? 64 : 512, b = lds ? 128 : 256;
+      if ((lds && nmx > 128) || (!lds && nmx > 512)) return JE_OK;  // one shape only
+      const int key = (lds ? 1 : 2) * 1000 + pivot * 100 + (int)std::ceil(std::log2((double)nmx));
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) { *shape = it->second; return JE_OK; }
+      }
+      if (!tuning_enabled()) return JE_OK;
+      // the trial runs on the class itself (up to 1024 matrices, spread over its sizes):
+      // a small sample leaves the device half idle and favours the wrong shape
+      std::vector<int> smp;
+      const size_t want = std::min<size_t>(lst.size(), 1024);
+      for (size_t t = 0; t < want; ++t) smp.push_back(lst[t * lst.size() / want]);
+      HIPCHK(hipMemcpyAsync(d_idx_lds, smp.data(), smp.size() * 4, hipMemcpyHostToDevice, s));
+      const size_t offJ = precond ? BF(A) : BF(Asym);
+      // the FP64 matrices of the whole batch are saved in T and restored after each trial
+      HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(T), offJ, s));
+      float best = 1e30f;
+      float t_default = 0.f;
+      for (int shp : {a, b}) {
+        HIPCHK(hipMemsetAsync(d_cnt, 0, 8, s));
+        Timer tt(s);
+        HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)smp.size(), nmx, pivot, lds, shp, d_cnt,
+                                   (int)std::min<size_t>(smp.size(), lds ? 2048 : 1024), s));
+        const float ms = tt.stop();
+        if (shp == a) { t_default = ms; best = ms; *shape = a; }
+        else if (ms < 0.95f * t_default) { best = ms; *shape = shp; }
+        HIPCHK(launch_copy_mat_b(dm, cnt, nmax, offJ, BF(T), s));
+        HIPCHK(launch_get_diag_b(dm, cnt, nmax, offJ, s));
+        HIPCHK(launch_reset_b(dm, cnt, s));
+        HIPCHK(launch_init_rows_b(dm, cnt, nmax, pivot, use_cert, s));
+      }
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = *shape;
+      return JE_OK;
+    };
+    if (int r = tuned(true, il, nl, &shape_lds)) return r;
+    if (int r = tuned(false, ih, nh, &shape_hbm)) return r;
+  }
   std::vector<JCtl> hc(cnt);
   std::vector<char> done(cnt, 0);
   float ms_kernel = 0.f;
@@ -620,9 +684,11 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
     HIPCHK(hipStreamSynchronize(s));
     Timer tk(s);
     if (!il.empty())
-      HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, 64, d_cnt, (int)std::min<size_t>(il.size(), 2048), s));
+      HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, shape_lds,
+                                 d_cnt, (int)std::min<size_t>(il.size(), 2048), s));
     if (!ih.empty())
-      HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, 512, d_cnt + 1, (int)std::min<size_t>(ih.size(), 512), s));
+      HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, shape_hbm,
+                                 d_cnt + 1, (int)std::min<size_t>(ih.size(), 1024), s));
     ms_kernel += tk.stop();
     HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
     if (int r = collect()) return r;

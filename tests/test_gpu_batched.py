@@ -117,3 +117,18 @@ def test_batched_nonfinite_member():
     assert res[0].status == J.OK
     assert res[1].status == J.ERR_NONFINITE
     assert status == J.ERR_NONFINITE
+
+
+def test_tuned_shapes_do_not_change_results(monkeypatch):
+    """The workgroup shapes picked by the size-class tuner change no bit of the results."""
+    probs = problems([40, 100, 128, 150, 300, 500], 7900)
+    tol = min(tol_for(a, lam) for a, lam in probs)
+    mats = [torch.from_numpy(a).cuda() for a, _ in probs]
+    monkeypatch.setenv("JE_TUNE", "0")
+    _, r0 = J.eigh_batched(mats, tol=tol, pivot="gap", precond="fp32")
+    monkeypatch.setenv("JE_TUNE", "1")
+    _, r1 = J.eigh_batched(mats, tol=tol, pivot="gap", precond="fp32")
+    for x, y in zip(r0, r1):
+        assert x.stats["rotations"] == y.stats["rotations"]
+        assert torch.equal(x.w, y.w)
+        assert torch.equal(x.v, y.v)
