@@ -34,7 +34,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "jacobi_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-GREEDY, GAP = 0, 1
+GREEDY, GAP, RELATIVE = 0, 1, 2
 STOP_CERT, STOP_OFF, STOP_SCORE = 0, 1, 2
 OK, MAXROT, STALL, NONFINITE = 0, 1, 2, 3
 
@@ -74,6 +74,12 @@ def lib():
         L.orc_jacobi.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_longlong, ctypes.c_int, dp, ip, dp, ctypes.c_longlong,
                                  ctypes.POINTER(_Stats)]
+        L.orc_score_rel.restype = ctypes.c_double
+        L.orc_score_rel.argtypes = [ctypes.c_double] * 3
+        L.orc_svd1.restype = ctypes.c_int
+        L.orc_svd1.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_longlong, ctypes.c_int, dp, dp, ip, dp,
+                               ctypes.c_longlong, ctypes.POINTER(_Stats)]
         L.orc_jacobi_f32.restype = ctypes.c_int
         L.orc_jacobi_f32.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double]
@@ -89,6 +95,11 @@ def _dp(a):
 def score_gap(aii: float, ajj: float, aij: float) -> float:
     """eq. (1) for one pair (0 when a_ij == 0)."""
     return lib().orc_score_gap(aii, ajj, aij)
+
+
+def score_rel(aii: float, ajj: float, aij: float) -> float:
+    """Relative score of Sec. 4.2, (1/a_ii + 1/a_jj) L_ij, for an SPD 2 x 2 block."""
+    return lib().orc_score_rel(aii, ajj, aij)
 
 
 def rotation(app: float, aqq: float, apq: float):
@@ -247,3 +258,123 @@ def total_relative_error(lam_exact: np.ndarray, lam: np.ndarray) -> float:
     """Sec. 4 error measure: sum_i |lambda_i - lambda_hat_i| / ||A||_2 (both sorted)."""
     lam_exact = np.sort(lam_exact)
     return float(np.sum(np.abs(lam_exact - np.sort(lam))) / np.max(np.abs(lam_exact)))
+
+
+# ----------------------------------------------------------------- one-sided SVD (Alg. 2)
+@dataclass
+class SvdResult:
+    s: np.ndarray              # singular values, descending
+    u: np.ndarray | None       # m x n, columns b_k / s_k (0 where s_k == 0)
+    v: np.ndarray | None       # n x n right factor
+    x: np.ndarray              # final columns of B (as rows, n x m), unsorted
+    g: np.ndarray              # Gram matrix of the final columns, unsorted
+    rotations: int
+    rescans: int
+    pivots: np.ndarray
+    cs: np.ndarray
+    status: int
+    normF: float               # ||B^T B||_F of the input
+    thr: float
+    final_sel: float
+    sweeps32: int = 0
+
+
+def gram_rows(x: np.ndarray) -> np.ndarray:
+    """x x^T with every entry a dot product summed in index order (as the C loop does)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    g = np.empty((n, n))
+    for i in range(n):
+        for j in range(i, n):
+            s = 0.0
+            for a, b in zip(x[i], x[j]):
+                s += a * b
+            g[i, j] = g[j, i] = s
+    return g
+
+
+def svd_threshold(pivot: int, tol: float, n: int, normF: float) -> float:
+    """Stop threshold of the one-sided method.  Greedy and gap: Theorem 1 on A = B^T B,
+    tol ||A||_F / (2 n (n-1)) (|a_ij| >= L_ij, so the greedy rule implies the certificate).
+    Relative: tol / (2 n (n-1)); Lhat is scale-free and bounds the relative shifts of the
+    2 x 2 eigenvalues, so tol plays the part of a relative error."""
+    if n < 2:
+        return 0.0
+    if pivot == RELATIVE:
+        return tol / (2.0 * n * (n - 1))
+    return tol * normF / (2.0 * n * (n - 1))
+
+
+def svd(b: np.ndarray, tol: float, pivot: int = GAP, precond: str = "none",
+        abs_thr: float | None = None, maxrot: int | None = None, scan: int = 1,
+        sweeps32: int = 20, passes: int = 2, logcap: int | None = None,
+        want_uv: bool = True) -> SvdResult:
+    """One-sided Jacobi SVD of B (m x n, m >= n), Algorithm 2.
+
+    ``precond='fp32'`` (Sec. 2.1): right singular vectors in FP32 as the eigenvectors of
+    fl32(B^T B) from the cyclic FP32 Jacobi (refined ``passes - 1`` times as in ``eigh``),
+    re-orthogonalised by Householder QR -> V; the one-sided method then runs on B V with
+    its Gram matrix (B V)^T B V as the pivoting matrix.  ``'none'``: B itself (the setting
+    of Sec. 4.2, where global transformations would spoil relative accuracy)."""
+    b = np.asarray(b, dtype=np.float64)
+    m, n = b.shape
+    x = np.ascontiguousarray(b.T)
+    if not np.all(np.isfinite(x)):
+        return SvdResult(np.full(n, np.nan), None, None, x, np.full((n, n), np.nan), 0, 0,
+                         np.empty((0, 2), np.int32), np.empty((0, 2)), NONFINITE,
+                         float("nan"), float("nan"), float("nan"))
+    g0 = x @ x.T
+    normF = float(np.sqrt(np.sum(g0 * g0)))
+    thr = abs_thr if abs_thr is not None else svd_threshold(pivot, tol, n, normF)
+    vt = np.eye(n)
+    sw = 0
+    if precond == "fp32" and n > 1:
+        g0 = 0.5 * (g0 + g0.T)
+        _, v32, sw = jacobi_f32(g0, max_sweeps=sweeps32)
+        q = householder_q(v32.astype(np.float64))
+        for _ in range(passes - 1):
+            a1 = q.T @ (g0 @ q)
+            a1 = 0.5 * (a1 + a1.T)
+            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32, tol=F32_TOL2, rho=F32_RHO2)
+            sw += sw2
+            q = householder_q(q @ v2.astype(np.float64))
+        x = np.ascontiguousarray(q.T @ x)
+        vt = np.ascontiguousarray(q.T)
+    if maxrot is None:
+        maxrot = max(64, 40 * n * n)
+    if logcap is None:
+        logcap = min(maxrot, 40 * n * n + 64)
+    g = np.empty((n, n))
+    plog = np.empty((logcap, 2), dtype=np.int32)
+    cslog = np.empty((logcap, 2), dtype=np.float64)
+    st = _Stats()
+    lib().orc_svd1(_dp(x), m, n, pivot, float(thr), int(maxrot), scan, _dp(vt), _dp(g),
+                   plog.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(cslog), int(logcap),
+                   ctypes.byref(st))
+    r = int(st.rotations)
+    k = min(r, logcap)
+    sig = np.sqrt(np.diag(g))
+    order = np.argsort(-sig, kind="stable")
+    u = v = None
+    if want_uv:
+        safe = np.where(sig > 0, sig, 1.0)
+        u = np.where(sig[None, :] > 0, x.T / safe[None, :], 0.0)[:, order]
+        v = vt.T[:, order].copy()
+    return SvdResult(sig[order], u, v, x, g, r, int(st.rescans), plog[:k].copy(),
+                     cslog[:k].copy(), int(st.status), normF, thr, st.final_sel, sw)
+
+
+def hilbert_singular_values(n: int, dps: int):
+    """Singular values of the Cholesky factor C_n of the Hilbert matrix H_n (Sec. 4.2), as
+    mpmath numbers of ``dps`` digits, descending.  H_n = C_n C_n^T, so they are the square
+    roots of the eigenvalues of H_n = (1/(i+j-1)), computed by mpmath's symmetric eigensolver
+    in ``dps``-digit arithmetic (the entries of H_n are its only input)."""
+    import mpmath as mp
+    with mp.workdps(dps):
+        h = mp.matrix(n, n)
+        for i in range(n):
+            for j in range(n):
+                h[i, j] = mp.mpf(1) / (i + j + 1)
+        ev = mp.eigsy(h, eigvals_only=True)
+        vals = sorted((ev[i] for i in range(n)), reverse=True)
+        return [mp.sqrt(v) for v in vals]

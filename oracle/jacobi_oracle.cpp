@@ -40,6 +40,23 @@ double gap_score(double aii, double ajj, double aij) {
 // Classical greedy score: the magnitude of the off-diagonal entry.
 double greedy_score(double aij) { return std::fabs(aij); }
 
+// Relative score of Sec. 4.2 for a symmetric positive definite A:
+//   Lhat_ij = (1/a_ii + 1/a_jj) L_ij,
+// the sum of the relative shifts of the two eigenvalues of the 2 x 2 block.  Lhat does not
+// change when the block is scaled, so a_ii, a_jj, a_ij are first multiplied by the power of
+// two that brings max(a_ii, a_jj) into [1/2, 1) (exact): for a pair of tiny diagonal
+// entries a_ij^2 then stays in range.  0 when a_ij == 0, or when the scaled a_ij^2
+// underflows.
+double rel_score(double aii, double ajj, double aij) {
+  if (aij == 0.0) return 0.0;
+  int e;
+  (void)std::frexp(std::max(aii, ajj), &e);
+  double x = std::ldexp(aii, -e), y = std::ldexp(ajj, -e), a = std::ldexp(aij, -e);
+  double l = gap_score(x, y, a);
+  if (l == 0.0) return 0.0;
+  return (1.0 / x + 1.0 / y) * l;
+}
+
 // c, s such that G^T [[app, apq], [apq, aqq]] G is diagonal, G = [[c, -s], [s, c]] (Sec. 2).
 // t = s / c is the root of modulus <= 1 of t^2 + 2 theta t - 1 = 0, theta = (app - aqq)/(2 apq),
 // written without theta: t = sgn(delta) 2 apq / (|delta| + sqrt(delta^2 + 4 apq^2)),
@@ -75,9 +92,10 @@ struct Matrix {
   double at(int i, int j) const { return a[(size_t)i * n + j]; }
 };
 
-// Score of pair (i, j) under a strategy: 0 = greedy |a_ij|, 1 = gap L_ij.
+// Score of pair (i, j) under a strategy: 0 = greedy |a_ij|, 1 = gap L_ij, 2 = relative Lhat_ij.
 double pair_score(const Matrix& m, int i, int j, int strategy) {
   if (strategy == 1) return gap_score(m.at(i, i), m.at(j, j), m.at(i, j));
+  if (strategy == 2) return rel_score(m.at(i, i), m.at(j, j), m.at(i, j));
   return greedy_score(m.at(i, j));
 }
 
@@ -177,7 +195,7 @@ struct RowCache {
 
 extern "C" {
 
-enum { OR_GREEDY = 0, OR_GAP = 1 };
+enum { OR_GREEDY = 0, OR_GAP = 1, OR_REL = 2 };
 enum { OR_STOP_CERT = 0, OR_STOP_OFF = 1, OR_STOP_SCORE = 2 };
 enum { OR_OK = 0, OR_MAXROT = 1, OR_STALL = 2, OR_NONFINITE = 3 };
 
@@ -191,6 +209,8 @@ struct OrStats {
 };
 
 double orc_score_gap(double aii, double ajj, double aij) { return gap_score(aii, ajj, aij); }
+
+double orc_score_rel(double aii, double ajj, double aij) { return rel_score(aii, ajj, aij); }
 
 void orc_rotation(double app, double aqq, double apq, double* t, double* c, double* s) {
   rotation<double>(app, aqq, apq, t, c, s);
@@ -393,6 +413,124 @@ int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol, do
     if (off >= rho * prev) break;
   }
   return sweeps;
+}
+
+
+// Dot product of rows i and j of the row-major n x m array X, summed in index order.
+static double dot_rows(const double* X, int m, int i, int j) {
+  const double* x = X + (size_t)i * m;
+  const double* y = X + (size_t)j * m;
+  double s = 0.0;
+  for (int r = 0; r < m; ++r) s += x[r] * y[r];
+  return s;
+}
+
+// One-sided Jacobi SVD (Algorithm 2) of B (m x n, m >= n), held transposed: row k of the
+// row-major n x m array X is column b_k of B.  A pivot (p, q) is chosen on the Gram matrix
+// A = B^T B (the matrix the pivot scores of Sec. 3 are evaluated on, Sec. 2.1), the rotation
+// that makes b_p and b_q orthogonal is the one that diagonalises [[a_pp, a_pq], [a_pq, a_qq]]
+// (Sec. 2), and B <- B G(c, s, p, q).  A is never rotated: every entry is the dot product of
+// the current columns (dot_rows), so after the rotation rows p and q of A are recomputed.
+//   pivot : 0 greedy |a_ij|, 1 gap L_ij (eq. (1)), 2 relative Lhat_ij (Sec. 4.2)
+//   stop  : the best selection score is <= thr, or maxrot rotations
+//   scan  : 0 full O(n^2) scan per rotation, 1 per-row best cache (Sec. 3.2)
+//   Vt    : optional n x n row-major; its rows are rotated with those of X (so Vt^T = V
+//           accumulates B's right factor); the caller initialises it
+//   G     : n x n row-major output: A of the final columns
+//   plog, cslog : optional logs of (p, q) and (c, s)
+int orc_svd1(double* X, int m, int n, int pivot, double thr, long long maxrot, int scan,
+             double* Vt, double* G, int* plog, double* cslog, long long logcap, OrStats* st) {
+  std::memset(st, 0, sizeof(*st));
+  for (long long i = 0; i < (long long)n * m; ++i)
+    if (!std::isfinite(X[i])) {
+      st->status = OR_NONFINITE;
+      return OR_NONFINITE;
+    }
+  Matrix g{G, n};
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) {
+      double v = dot_rows(X, m, i, j);
+      G[(size_t)i * n + j] = v;
+      G[(size_t)j * n + i] = v;
+    }
+  RowCache sel{pivot};
+  if (scan == 1) sel.build(g);
+  long long rot = 0;
+  int status = OR_OK;
+  double vsel = 0.0;
+  for (;;) {
+    int p = -1, q = -1;
+    if (scan == 0) {
+      vsel = -1.0;
+      for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+          double v = pair_score(g, i, j, pivot);
+          if (v > vsel) {
+            vsel = v;
+            p = i;
+            q = j;
+          }
+        }
+    } else {
+      sel.argmax(&vsel, &p, &q);
+    }
+    if (n < 2) break;
+    if (vsel <= thr) break;
+    if (rot >= maxrot) {
+      status = OR_MAXROT;
+      break;
+    }
+    double apq = g.at(p, q);
+    if (apq == 0.0) {
+      status = OR_STALL;
+      break;
+    }
+    double t, c, s;
+    rotation<double>(g.at(p, p), g.at(q, q), apq, &t, &c, &s);
+    // [b_p, b_q] <- [b_p, b_q] [[c, -s], [s, c]]
+    double* xp = X + (size_t)p * m;
+    double* xq = X + (size_t)q * m;
+    for (int r = 0; r < m; ++r) {
+      double u = xp[r], w = xq[r];
+      xp[r] = c * u + s * w;
+      xq[r] = c * w - s * u;
+    }
+    if (Vt) {
+      double* vp = Vt + (size_t)p * n;
+      double* vq = Vt + (size_t)q * n;
+      for (int r = 0; r < n; ++r) {
+        double u = vp[r], w = vq[r];
+        vp[r] = c * u + s * w;
+        vq[r] = c * w - s * u;
+      }
+    }
+    if (plog && rot < logcap) {
+      plog[2 * rot] = p;
+      plog[2 * rot + 1] = q;
+    }
+    if (cslog && rot < logcap) {
+      cslog[2 * rot] = c;
+      cslog[2 * rot + 1] = s;
+    }
+    ++rot;
+    for (int k = 0; k < n; ++k) {
+      double v = dot_rows(X, m, p, k);
+      G[(size_t)p * n + k] = v;
+      G[(size_t)k * n + p] = v;
+    }
+    for (int k = 0; k < n; ++k) {
+      if (k == p) continue;
+      double v = dot_rows(X, m, q, k);
+      G[(size_t)q * n + k] = v;
+      G[(size_t)k * n + q] = v;
+    }
+    if (scan == 1) sel.refresh(g, p, q);
+  }
+  st->rotations = rot;
+  st->rescans = sel.rescans;
+  st->final_sel = vsel;
+  st->status = status;
+  return status;
 }
 
 }  // extern "C"

@@ -192,3 +192,42 @@ def random_symmetric(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = rng_for(seed)
     g = rng.standard_normal((n, n)) * scale
     return np.ascontiguousarray(0.5 * (g + g.T))
+
+
+# ----------------------------------------------------------------- SVD inputs
+SEED_SVD = 20261207  # rectangular matrices of prescribed singular values
+
+
+def hilbert_cholesky(n: int) -> np.ndarray:
+    """Closed-form lower-triangular Cholesky factor C_n of the Hilbert matrix (Sec. 4.2):
+    c_ij = sqrt(2j-1) ((i-1)!)^2 / ((i+j-1)! (i-j)!) for i >= j (1-based), 0 above the
+    diagonal.  The factorial ratio is formed exactly as a rational number and rounded once;
+    the square root is rounded once and the product once (about 1.5 ulp per entry)."""
+    from fractions import Fraction
+    c = np.zeros((n, n))
+    f = [math.factorial(k) for k in range(2 * n)]
+    for i in range(1, n + 1):
+        for j in range(1, i + 1):
+            ratio = Fraction(f[i - 1] ** 2, f[i + j - 1] * f[i - j])
+            c[i - 1, j - 1] = math.sqrt(2 * j - 1) * float(ratio)
+    return c
+
+
+def with_singular_values(m: int, sv: np.ndarray, seed: int) -> np.ndarray:
+    """B = U diag(sv) V^T (m x n, n = len(sv)) with Haar-distributed U (first n columns of
+    an m x m factor) and V."""
+    rng = rng_for(seed)
+    n = len(sv)
+    u = haar_orthogonal(m, rng)[:, :n]
+    v = haar_orthogonal(n, rng)
+    return np.ascontiguousarray((u * np.asarray(sv, dtype=np.float64)[None, :]) @ v.T)
+
+
+def svd_graded(m: int, n: int, seed: int, decades: float = 12.0) -> np.ndarray:
+    """Rectangular test matrix with singular values spread log-uniformly over `decades`
+    decades, plus a pair of close singular values (the gap score's case)."""
+    rng = rng_for(seed + 1)
+    sv = np.sort(10.0 ** (-decades * rng.random(n)))[::-1].copy()
+    if n >= 4:
+        sv[n // 2] = sv[n // 2 - 1] * (1.0 - 1e-9)
+    return with_singular_values(m, sv, seed)
