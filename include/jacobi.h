@@ -66,7 +66,9 @@ typedef void* je_stream;
 
 #define JE_MAX_N 8192
 
-enum je_pivot { JE_PIVOT_GREEDY = 0, JE_PIVOT_GAP = 1 };
+/* JE_PIVOT_RELATIVE is the relative score of Sec. 4.2, (1/a_ii + 1/a_jj) L_ij, for the
+ * positive semidefinite Gram matrix of jacobi_svd only. */
+enum je_pivot { JE_PIVOT_GREEDY = 0, JE_PIVOT_GAP = 1, JE_PIVOT_RELATIVE = 2 };
 enum je_precond { JE_PRECOND_NONE = 0, JE_PRECOND_FP32 = 1 };
 enum je_stop {
   JE_STOP_CERT = 0,  /* max_{i!=j} L_ij <= tol*||A||_F / (2n(n-1))   (Theorem 1)           */
@@ -145,6 +147,47 @@ int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const i
                         double* const* W, double* const* V, const int* ldv, double tol,
                         int pivot, int precond, const je_opts* opts, int* info,
                         je_stats* stats, je_stream stream);
+
+/* ---------------------------------------------------------------- one-sided SVD
+ * Singular values (and vectors) of B (m x n, m >= n) by the one-sided Jacobi method of
+ * Algorithm 2: a pivot (p, q) is chosen on the Gram matrix A = B^T B (the matrix the scores
+ * are evaluated on, Sec. 2.1), columns b_p and b_q are made orthogonal by the rotation
+ * that diagonalises [[a_pp, a_pq], [a_pq, a_qq]], and B <- B G(c, s, p, q).  A is never
+ * rotated: each entry is the dot product of the current columns, summed in index order, and
+ * rows p and q are recomputed after every rotation, so a_pp, a_qq, a_pq are always those of
+ * the columns being rotated.  Ties go to the lexicographically smallest pair.
+ *   pivot   JE_PIVOT_GREEDY |a_ij|, JE_PIVOT_GAP L_ij (eq. (1)), or JE_PIVOT_RELATIVE
+ *           (1/a_ii + 1/a_jj) L_ij (Sec. 4.2; evaluated on the block scaled by a power of
+ *           two so that max(a_ii, a_jj) is in [1/2, 1), which leaves it unchanged).
+ *   precond JE_PRECOND_FP32 (Sec. 2.1): right singular vectors from the FP32 decomposition
+ *           of fl32(B^T B) (passes and sweep caps from opts, as jacobi_eigh_ex),
+ *           re-orthogonalised in FP64 -> Q; the method then runs on B Q.  JE_PRECOND_NONE:
+ *           on B itself (Sec. 4.2: the global transformation would spoil the relative
+ *           accuracy of tiny singular values).
+ *   stop    best selection score <= thr, with thr = tol ||B^T B||_F / (2 n (n-1))
+ *           (Theorem 1 on A; greedy implies it since |a_ij| >= L_ij) for greedy and gap, and
+ *           thr = tol / (2 n (n-1)) for the scale-free relative score; opts->abs_thr > 0
+ *           overrides it.  At exit the columns satisfy |cos(b_i, b_j)| <= sqrt(1.5 thr) under
+ *           the relative score.  The greedy rule cannot go below the rounding level of the dot
+ *           products (about m u ||b_i|| ||b_j||): give it a tol above that.
+ *
+ * B: device, column-major, ldb >= m, read only.  S: device, n singular values in
+ * descending order (stable: equal values keep their column order); sigma_k = sqrt(a_kk)
+ * of the final columns.  U (may be NULL): device, column-major m x n, ldu >= m, column k =
+ * b_k / sigma_k (0 where sigma_k = 0).  V (may be NULL): device, column-major n x n,
+ * ldv >= n, the accumulated right factor (Q times the rotations), B V = U diag(S).
+ * opts (NULL = defaults): max_rotations (<= 0: 40 n^2 + 64), abs_thr, fp32_passes,
+ * fp32_max_sweeps, and pivot_log, which here is written directly by the kernel (device
+ * int32[2 * pivot_log_cap]: (p, q), 0-based, p < q).  opts->stop, polish_v and split_gemm
+ * are not used.  stats: rotations, rescans, final_max_score (the best selection score at
+ * exit), final_off (off(A) at exit), normF (||B^T B||_F), thr, sweeps32, a_hat_off (off of
+ * the preconditioned Gram matrix), timings.
+ * Range: the entries of B^T B must be finite (JE_ERR_NONFINITE otherwise), and under the
+ * gap or greedy score their squares too.
+ * Returns as jacobi_eigh_ex, with arguments numbered B = 1 ... opts = 13. */
+int jacobi_svd(const double* B, int m, int n, int ldb, double* S, double* U, int ldu, double* V,
+               int ldv, double tol, int pivot, int precond, const je_opts* opts,
+               je_stats* stats, je_stream stream);
 
 /* Device bytes the workspace pool holds for one solve of size n. */
 size_t jacobi_workspace_size(int n, int precond);

@@ -204,6 +204,34 @@ int orthonormalize(double*& X, double*& Xalt, double* R, int n, int ld, double* 
   return JE_OK;
 }
 
+// The preconditioner of Sec. 2.1 for the symmetric Asym (row-major, ld): an FP32 spectral
+// decomposition of fl32(Asym) re-orthogonalised by Newton-Schulz into X; with
+// o.fp32_passes = 2 the FP32 Jacobi runs again on fl32(X^T Asym X) and X <- X V_2,
+// re-orthogonalised.  X and Xo may be swapped; R, T, A are n x ld temporaries.
+int precond_q(const double* Asym, int n, int ld, double*& X, double*& Xo, double* R, double* T,
+              double* A, void* f32, const je_opts& o, double* part, double* scal, int* sweeps,
+              hipStream_t s) {
+  int sw = 0;
+  *sweeps = 0;
+  HIPCHK(run_precond_f32(Asym, n, ld, X, ld, f32, o.fp32_max_sweeps, kF32Tol1, kF32Rho1, &sw,
+                         s));
+  *sweeps += sw;
+  int r = orthonormalize(X, Xo, R, n, ld, part, scal, s);
+  if (r) return r;
+  for (int pass = 1; pass < o.fp32_passes; ++pass) {
+    HIPCHK(launch_dgemm(n, 0, 1.0, Asym, ld, X, ld, 0.0, nullptr, 0, T, ld, s));
+    HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, T, ld, 0.0, nullptr, 0, A, ld, s));
+    HIPCHK(launch_symmetrize(A, n, ld, s));
+    HIPCHK(run_precond_f32(A, n, ld, T, ld, f32, o.fp32_max_sweeps, kF32Tol2, kF32Rho2, &sw, s));
+    *sweeps += sw;
+    HIPCHK(launch_dgemm(n, 0, 1.0, X, ld, T, ld, 0.0, nullptr, 0, Xo, ld, s));
+    std::swap(X, Xo);
+    r = orthonormalize(X, Xo, R, n, ld, part, scal, s);
+    if (r) return r;
+  }
+  return JE_OK;
+}
+
 int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, double tol,
               int pivot, int precond, const je_opts& o, je_stats* st, hipStream_t s) {
   const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
@@ -237,29 +265,11 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   double* Ajac = w.Asym;
   double* Vw = w.Vw;
   if (precond) {
-    int sweeps = 0, sw = 0;
-    // pass 1: FP32 decomposition of fl32(A) -> B1, Newton-Schulz -> X
     double* X = w.Q;
     double* Xo = w.X;
-    HIPCHK(run_precond_f32(w.Asym, n, ld, X, ld, w.f32, o.fp32_max_sweeps, kF32Tol1, kF32Rho1,
-                           &sw, s));
-    sweeps += sw;
-    int r = orthonormalize(X, Xo, w.R, n, ld, w.rowsq, w.scal, s);
+    int r = precond_q(w.Asym, n, ld, X, Xo, w.R, w.T, w.A, w.f32, o, w.rowsq, w.scal,
+                      &S.sweeps32, s);
     if (r) return r;
-    for (int pass = 1; pass < o.fp32_passes; ++pass) {
-      // pass 2: FP32 decomposition of fl32(X^T A X) -> V2 (in T), X <- X V2
-      HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
-      HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
-      HIPCHK(launch_symmetrize(w.A, n, ld, s));
-      HIPCHK(run_precond_f32(w.A, n, ld, w.T, ld, w.f32, o.fp32_max_sweeps, kF32Tol2, kF32Rho2,
-                             &sw, s));
-      sweeps += sw;
-      HIPCHK(launch_dgemm(n, 0, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, Xo, ld, s));
-      std::swap(X, Xo);
-      r = orthonormalize(X, Xo, w.R, n, ld, w.rowsq, w.scal, s);
-      if (r) return r;
-    }
-    S.sweeps32 = sweeps;
     S.ms_precond = tp.stop();
     Timer tg(s);
     // A_hat = X^T (A X): T = A X, A_hat = X^T T, then exact symmetry
@@ -381,6 +391,143 @@ struct BatchLayout {
   size_t bytes = 0;
   std::vector<size_t> off;  // per member: offset of its workspace
 };
+
+// ------------------------------------------------------------------ one-sided SVD
+// Stop threshold: greedy and gap scores, Theorem 1 on A = B^T B; relative score, the same
+// form with ||A||_F replaced by 1 (the score is scale-free).
+double svd_thr(int pivot, double tol, int n, double normF) {
+  if (n < 2) return 0.0;
+  const double den = 2.0 * n * (double)(n - 1);
+  return pivot == JE_PIVOT_RELATIVE ? tol / den : tol * normF / den;
+}
+
+int svd_one(const double* B, int m, int n, int ldb, double* S, double* U, int ldu, double* V,
+            int ldv, double tol, int pivot, int precond, const je_opts& o, je_stats* st,
+            hipStream_t s) {
+  const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
+  const size_t ld = ld_of(n), ldx = ld_of(m);
+  const bool pre = precond && n > 1;
+  const size_t xm = al((size_t)n * ldx * 8), mat = al((size_t)n * ld * 8);
+  size_t bytes = 2 * xm + 2 * mat + 3 * al((size_t)n * 8) + 3 * al((size_t)n * 4) + al(64) +
+                 al(sizeof(JCtl));
+  if (pre) bytes += 5 * mat + al(precond_f32_bytes(n));
+  int err = JE_OK;
+  char* p = (char*)pool_get(bytes, &err);
+  if (!p) return err;
+  auto take = [&](size_t b) { char* r = p; p += al(b); return (void*)r; };
+  double* X = (double*)take(xm);
+  double* X2 = (double*)take(xm);
+  double* G = (double*)take(mat);
+  double* Vt = (double*)take(mat);
+  double* best = (double*)take((size_t)n * 8);
+  double* part = (double*)take((size_t)n * 8);
+  (void)take((size_t)n * 8);
+  int* arg = (int*)take((size_t)n * 4);
+  int* rank = (int*)take((size_t)n * 4);
+  int* flag = (int*)take((size_t)n * 4);
+  double* scal = (double*)take(64);
+  JCtl* ctl = (JCtl*)take(sizeof(JCtl));
+  double *Q = nullptr, *Qo = nullptr, *R = nullptr, *T = nullptr, *A = nullptr;
+  void* f32 = nullptr;
+  if (pre) {
+    Q = (double*)take(mat);
+    Qo = (double*)take(mat);
+    R = (double*)take(mat);
+    T = (double*)take(mat);
+    A = (double*)take(mat);
+    f32 = take(precond_f32_bytes(n));
+  }
+  je_stats Sx{};
+
+  // ---- 1. X = B^T, finiteness, A = X X^T, ||A||_F
+  Timer tp(s);
+  HIPCHK(hipMemsetAsync(flag, 0, 4, s));
+  HIPCHK(launch_svd_load(B, m, n, ldb, X, (int)ldx, flag, s));
+  HIPCHK(launch_svd_gram(X, (int)ldx, m, n, G, (int)ld, s));
+  HIPCHK(launch_fro2(G, n, (int)ld, part, scal, s));
+  int hflag = 0;
+  double normF = 0.0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&normF, scal, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hflag || !std::isfinite(normF)) return JE_ERR_NONFINITE;
+  Sx.normF = normF;
+  const double thr = o.abs_thr > 0.0 ? o.abs_thr : svd_thr(pivot, tol, n, normF);
+  Sx.thr = thr;
+
+  // ---- 2. preconditioner: right singular vectors of B from the FP32 decomposition of
+  // fl32(B^T B), re-orthogonalised -> Q; the one-sided method runs on B Q
+  double* Vr = V ? Vt : nullptr;
+  if (pre) {
+    int r = precond_q(G, n, (int)ld, Q, Qo, R, T, A, f32, o, part, scal, &Sx.sweeps32, s);
+    if (r) return r;
+    Sx.ms_precond = tp.stop();
+    Timer tg(s);
+    HIPCHK(launch_svd_rowmix(Q, (int)ld, X, (int)ldx, n, m, X2, (int)ldx, s));
+    std::swap(X, X2);
+    if (Vr) HIPCHK(launch_svd_transpose(Q, (int)ld, n, Vr, (int)ld, s));
+    HIPCHK(launch_svd_gram(X, (int)ldx, m, n, G, (int)ld, s));
+    HIPCHK(launch_offnorm(G, n, (int)ld, part, scal + 2, s));
+    HIPCHK(hipMemcpyAsync(&Sx.a_hat_off, scal + 2, 8, hipMemcpyDeviceToHost, s));
+    Sx.ms_gemm = tg.stop();
+  } else {
+    if (Vr) HIPCHK(launch_set_identity(Vr, n, (int)ld, s));
+    Sx.ms_precond = tp.stop();
+  }
+
+  // ---- 3. one-sided pivoted Jacobi
+  Timer tj(s);
+  SDesc d{};
+  d.X = X; d.m = m; d.ldx = (int)ldx;
+  d.Vt = Vr; d.ldv = (int)ld;
+  d.G = G; d.n = n; d.ldg = (int)ld;
+  d.best = best; d.arg = arg;
+  d.thr = thr; d.maxrot = maxrot; d.pivot = pivot;
+  d.plog = o.pivot_log; d.logcap = o.pivot_log ? o.pivot_log_cap : 0;
+  d.ctl = ctl;
+  HIPCHK(hipMemsetAsync(ctl, 0, sizeof(JCtl), s));
+  HIPCHK(launch_svd_jacobi(d, s));
+  JCtl hc{};
+  HIPCHK(hipMemcpyAsync(&hc, ctl, sizeof(JCtl), hipMemcpyDeviceToHost, s));
+  Sx.ms_jacobi = tj.stop();
+  Sx.ms_jacobi_kernel = Sx.ms_jacobi;
+  Sx.rotations = hc.rotations;
+  Sx.rescans = hc.rescans;
+  Sx.final_max_score = hc.final_sel;
+  Sx.status = hc.status == ST_MAXROT ? JE_WARN_MAXROT : (hc.status == ST_STALL ? JE_WARN_STALL : JE_OK);
+
+  // ---- 4. singular values (descending), vectors
+  Timer tf(s);
+  HIPCHK(launch_offnorm(G, n, (int)ld, part, scal + 3, s));
+  HIPCHK(hipMemcpyAsync(&Sx.final_off, scal + 3, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_svd_out(X, (int)ldx, m, G, (int)ld, Vr, (int)ld, n, rank, S, U, ldu, V, ldv, s));
+  HIPCHK(hipStreamSynchronize(s));
+  Sx.ms_finalize = tf.stop();
+  if (st) *st = Sx;
+  return Sx.status;
+}
+
+int check_svd_args(const double* B, int m, int n, int ldb, const double* S, const double* U,
+                   int ldu, const double* V, int ldv, double tol, int pivot, int precond,
+                   const je_opts& o) {
+  if (!B && n > 0) return -1;
+  if (m < 0 || m < n) return -2;
+  if (n < 0) return -3;
+  if (ldb < std::max(1, m)) return -4;
+  if (!S && n > 0) return -5;
+  if (U && ldu < std::max(1, m)) return -7;
+  if (V && ldv < std::max(1, n)) return -9;
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    if (!(o.abs_thr > 0.0)) return -10;
+  }
+  if (pivot != JE_PIVOT_GREEDY && pivot != JE_PIVOT_GAP && pivot != JE_PIVOT_RELATIVE)
+    return -11;
+  if (precond != JE_PRECOND_NONE && precond != JE_PRECOND_FP32) return -12;
+  if (o.fp32_max_sweeps < 0 || o.fp32_passes < 1 || o.fp32_passes > 2) return -13;
+  if (o.pivot_log && o.pivot_log_cap < 0) return -13;
+  return 0;
+}
+
 
 size_t bws_bytes(int n, int precond, long long cap) {
   size_t ld = ld_of(n);
@@ -927,6 +1074,22 @@ int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ld
 int jacobi_eigh(const double* A, int n, int lda, double* W, double* V, double tol, int pivot,
                 int precond) {
   return jacobi_eigh_ex(A, n, lda, W, V, n, tol, pivot, precond, nullptr, nullptr, nullptr);
+}
+
+int jacobi_svd(const double* B, int m, int n, int ldb, double* S, double* U, int ldu, double* V,
+               int ldv, double tol, int pivot, int precond, const je_opts* opts,
+               je_stats* stats, je_stream stream) {
+  je_opts o;
+  if (opts) o = *opts;
+  else je_opts_default(&o);
+  int a = check_svd_args(B, m, n, ldb, S, U, ldu, V, ldv, tol, pivot, precond, o);
+  if (a) return a;
+  if (n > JE_MAX_N) return JE_ERR_TOO_LARGE;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n == 0) return JE_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return svd_one(B, m, n, ldb, S, U, ldu, V, ldv, tol, pivot, precond, o, stats,
+                 (hipStream_t)stream);
 }
 
 int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const int* lda,

@@ -160,4 +160,42 @@ hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int*
                              size_t off, size_t qoff, int max_sweeps, double tol, double rho,
                              hipStream_t s);
 
+// ------------------------------------------------------------------ one-sided SVD
+constexpr int kSvdMaxN = 8192;
+
+// Device state of the one-sided Jacobi SVD: X = B^T (row k = column b_k, row stride ldx),
+// the right factor Vt (rows rotated with those of X; may be null), the Gram matrix G = X X^T
+// (row-major), the per-row best score cache and the control block.
+struct SDesc {
+  double* X;
+  int m, ldx;
+  double* Vt;
+  int ldv;
+  double* G;
+  int n, ldg;
+  double* best;
+  int* arg;
+  double thr;
+  long long maxrot;
+  int pivot;                    // 0 greedy, 1 gap, 2 relative
+  int* plog;                    // optional (p, q) log, logcap entries
+  long long logcap;
+  JCtl* ctl;
+};
+
+hipError_t launch_svd_load(const double* B, int m, int n, int ldb, double* X, int ldx, int* flag,
+                           hipStream_t s);
+hipError_t launch_svd_gram(const double* X, int ldx, int m, int n, double* G, int ldg,
+                           hipStream_t s);
+hipError_t launch_svd_rowmix(const double* Q, int ldq, const double* X, int ldx, int n, int m,
+                             double* Y, int ldy, hipStream_t s);
+hipError_t launch_svd_transpose(const double* Q, int ldq, int n, double* Vt, int ldv,
+                                hipStream_t s);
+// Row cache, then the whole rotation sequence in one launch (ends at the stop rule, the
+// rotation cap or a stall; ctl->done = 1).
+hipError_t launch_svd_jacobi(const SDesc& d, hipStream_t s);
+hipError_t launch_svd_out(const double* X, int ldx, int m, const double* G, int ldg,
+                          const double* Vt, int ldvt, int n, int* rank, double* S, double* U,
+                          int ldu, double* V, int ldv, hipStream_t s);
+
 }  // namespace je

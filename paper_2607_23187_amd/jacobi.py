@@ -15,13 +15,14 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjacobi.so")
 
-GREEDY, GAP = 0, 1
+GREEDY, GAP, RELATIVE = 0, 1, 2
 PRECOND_NONE, PRECOND_FP32 = 0, 1
 STOP_CERT, STOP_OFF, STOP_SCORE = 0, 1, 2
 OK, WARN_MAXROT, WARN_STALL, ERR_NONFINITE, ERR_NOMEM, ERR_DEVICE, ERR_TOO_LARGE = range(7)
 MAX_N = 8192
 
-_PIVOTS = {"greedy": GREEDY, "gap": GAP, GREEDY: GREEDY, GAP: GAP}
+_PIVOTS = {"greedy": GREEDY, "gap": GAP, "relative": RELATIVE, GREEDY: GREEDY, GAP: GAP,
+           RELATIVE: RELATIVE}
 _PRECONDS = {"none": PRECOND_NONE, "fp32": PRECOND_FP32, None: PRECOND_NONE,
              PRECOND_NONE: PRECOND_NONE, PRECOND_FP32: PRECOND_FP32}
 _STOPS = {"cert": STOP_CERT, "off": STOP_OFF, "score": STOP_SCORE,
@@ -50,6 +51,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["je_opts_default", "jacobi_eigh", "jacobi_eigh_ex", "jacobi_eigh_batched",
+           "jacobi_svd",
            "jacobi_workspace_size", "jacobi_strerror", "jacobi_release",
            "jacobi_server_create", "jacobi_server_submit", "jacobi_server_poll",
            "jacobi_server_pending", "jacobi_server_clock", "jacobi_server_destroy"]
@@ -86,6 +88,9 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(ip), dp, ip, ip, ctypes.POINTER(Opts),
                                       ctypes.POINTER(ip), ctypes.POINTER(Stats), vp]
     L.jacobi_eigh_batched.restype = ctypes.c_int
+    L.jacobi_svd.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, dp, ip, ip,
+                             ctypes.POINTER(Opts), ctypes.POINTER(Stats), vp]
+    L.jacobi_svd.restype = ctypes.c_int
     L.jacobi_workspace_size.argtypes = [ip, ip]
     L.jacobi_workspace_size.restype = ctypes.c_size_t
     L.jacobi_strerror.argtypes = [ip]
@@ -177,6 +182,57 @@ def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop=
     if plog is not None:
         plog = plog[: min(st.rotations, pivot_log_cap)]
     return Result(w, vt.t() if vt is not None else None, status, st.as_dict(), plog)
+
+
+@dataclass
+class SvdResult:
+    s: torch.Tensor                  # (n,) singular values, descending, float64, device
+    u: torch.Tensor | None           # (m, n)
+    v: torch.Tensor | None           # (n, n): b @ v == u * s
+    status: int
+    stats: dict
+    pivots: torch.Tensor | None      # (rotations, 2) int32 pivot log, 0-based
+
+
+def svd(b: torch.Tensor, tol: float = 2.0 ** -53, pivot="gap", precond="none",
+        want_u: bool = True, want_v: bool = True, abs_thr: float = 0.0, max_rotations: int = 0,
+        fp32_max_sweeps: int = 20, fp32_passes: int = 2, pivot_log_cap: int = 0,
+        stream: torch.cuda.Stream | None = None, check: bool = True) -> SvdResult:
+    """One-sided Jacobi SVD (Algorithm 2) of the float64 CUDA tensor ``b`` (m x n, m >= n)."""
+    if not isinstance(b, torch.Tensor) or not b.is_cuda:
+        raise TypeError("B must be a torch CUDA (HIP) tensor")
+    if b.dtype != torch.float64 or b.dim() != 2:
+        raise TypeError("B must be a 2-D float64 tensor")
+    L = load()
+    m, n = b.shape
+    bt = b.t().contiguous()          # column-major B, ldb = m
+    sv = torch.empty(n, dtype=torch.float64, device=b.device)
+    ut = torch.empty((n, m), dtype=torch.float64, device=b.device) if want_u else None
+    vt = torch.empty((n, n), dtype=torch.float64, device=b.device) if want_v else None
+    o = default_opts()
+    o.fp32_max_sweeps = int(fp32_max_sweeps)
+    o.fp32_passes = int(fp32_passes)
+    o.max_rotations = int(max_rotations)
+    o.abs_thr = float(abs_thr)
+    plog = None
+    if pivot_log_cap > 0:
+        plog = torch.full((pivot_log_cap, 2), -1, dtype=torch.int32, device=b.device)
+        o.pivot_log = plog.data_ptr()
+        o.pivot_log_cap = int(pivot_log_cap)
+    st = Stats()
+    s = stream if stream is not None else torch.cuda.current_stream(b.device)
+    with torch.cuda.device(b.device):
+        status = L.jacobi_svd(bt.data_ptr(), m, n, max(1, m), sv.data_ptr(),
+                              ut.data_ptr() if ut is not None else None, max(1, m),
+                              vt.data_ptr() if vt is not None else None, max(1, n), float(tol),
+                              _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o),
+                              ctypes.byref(st), ctypes.c_void_p(s.cuda_stream))
+    if check and (status < 0 or status >= ERR_NONFINITE):
+        raise RuntimeError(f"jacobi_svd failed: {status} ({strerror(status)})")
+    if plog is not None:
+        plog = plog[: min(st.rotations, pivot_log_cap)]
+    return SvdResult(sv, ut.t() if ut is not None else None, vt.t() if vt is not None else None,
+                     status, st.as_dict(), plog)
 
 
 def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", precond="fp32",

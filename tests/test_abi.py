@@ -80,3 +80,32 @@ def test_server_rejects_bad_arguments():
     assert not L.jacobi_server_create(2, 1 << 20, -1.0, 1, 1, ctypes.byref(o))
     assert L.jacobi_server_poll(None, None, 0, 0) == -1
     assert L.jacobi_server_pending(None) == -1
+
+
+def test_svd_argument_errors():
+    """jacobi_svd validates its arguments before any device call."""
+    L = J.load()
+    fake = ctypes.c_void_p(0x1000)
+
+    def svd(B, m, n, ldb, S, Up, ldu, V, ldv, tol, pivot=1, precond=0, opts=None):
+        return L.jacobi_svd(B, m, n, ldb, S, Up, ldu, V, ldv, tol, pivot, precond,
+                            ctypes.byref(opts) if opts is not None else None, None, None)
+
+    assert svd(None, 5, 4, 5, fake, None, 5, None, 4, 1e-12) == -1
+    assert svd(fake, 3, 4, 5, fake, None, 5, None, 4, 1e-12) == -2      # m < n
+    assert svd(fake, 5, -1, 5, fake, None, 5, None, 4, 1e-12) == -3
+    assert svd(fake, 5, 4, 4, fake, None, 5, None, 4, 1e-12) == -4
+    assert svd(fake, 5, 4, 5, None, None, 5, None, 4, 1e-12) == -5
+    assert svd(fake, 5, 4, 5, fake, fake, 4, None, 4, 1e-12) == -7
+    assert svd(fake, 5, 4, 5, fake, None, 5, fake, 3, 1e-12) == -9
+    assert svd(fake, 5, 4, 5, fake, None, 5, None, 4, 0.0) == -10
+    assert svd(fake, 5, 4, 5, fake, None, 5, None, 4, 1e-12, pivot=3) == -11
+    assert svd(fake, 5, 4, 5, fake, None, 5, None, 4, 1e-12, precond=2) == -12
+    o = J.default_opts()
+    o.fp32_passes = 3
+    assert svd(fake, 5, 4, 5, fake, None, 5, None, 4, 1e-12, opts=o) == -13
+    assert svd(fake, 5, 0, 5, fake, None, 5, None, 1, 1e-12) == 0
+    big = J.MAX_N + 1
+    assert svd(fake, big, big, big, fake, None, big, None, big, 1e-12) == J.ERR_TOO_LARGE
+    # the relative score is defined for the Gram matrix of the SVD only
+    assert _ex(fake, 4, 4, fake, None, 4, 1e-12, pivot=J.RELATIVE) == -8
