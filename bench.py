@@ -356,6 +356,74 @@ def bench_precision(args):
                       "n": n, "variants": out}), flush=True)
 
 
+def bench_svd(args):
+    """One-sided Jacobi SVD (Algorithm 2).  (a) Sec. 4.2: the closed-form Cholesky factor
+    C_100 of the Hilbert matrix, relative score, no preconditioning: time per solve, the
+    rotation rate, the relative error of the singular values against the multiprecision
+    reference, and the oracle on the same input.  (b) The preconditioned path (Sec. 2.1,
+    B V) on a 1024 x 512 matrix with singular values over 4 decades."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2607_23187_amd import inputs as I
+    from paper_2607_23187_amd import jacobi as J
+
+    J.load()
+    with open(os.path.join(ROOT, "tests", "golden", "hilbert_cholesky_sv.json")) as f:
+        ref = np.array([float(x) for x in json.load(f)["sv"]["100"]])
+    c = I.hilbert_cholesky(100)
+    cd = torch.from_numpy(c).to("cuda:0")
+    out = {}
+    times = []
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = J.svd(cd, tol=U, pivot="relative", max_rotations=400000)
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            times.append(time.perf_counter() - t)
+    s = r.s.cpu().numpy()
+    e = np.abs(s - ref) / ref
+    rot = int(r.stats["rotations"])
+    ms = 1e3 * float(np.median(times))
+    out["c100_relative"] = {
+        "ms_per_solve": ms, "rotations": rot, "us_per_rotation": 1e3 * r.stats["ms_jacobi"] / rot,
+        "rotations_per_s": rot / (r.stats["ms_jacobi"] / 1e3),
+        "max_rel_err_top10": float(e[:10].max()),
+        "median_log10_rel_err_bottom50": float(np.median(np.log10(e[50:] + 1e-17))),
+        "status": J.strerror(r.status)}
+    log(f"c100 relative: {ms:.1f} ms, {rot} rotations")
+    if not args.no_cpu:
+        t = time.perf_counter()
+        o = O.svd(c, U, pivot=O.RELATIVE, maxrot=400000, want_uv=True)
+        cs = time.perf_counter() - t
+        out["c100_relative"]["cpu_oracle"] = {"seconds": cs, "cores": 1,
+                                              "same_bits": bool(np.array_equal(o.s, s))}
+        log(f"c100 oracle: {cs:.2f} s")
+    b = I.svd_graded(1024, 512, seed=I.SEED_SVD, decades=4.0)
+    bd = torch.from_numpy(b).to("cuda:0")
+    for name, pre in (("precond_1024x512_gap", "fp32"),):
+        J.svd(bd, tol=U, pivot="gap", precond=pre)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = J.svd(bd, tol=U, pivot="gap", precond=pre)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t)
+        ls = np.linalg.svd(b, compute_uv=False)
+        st = r.stats
+        out[name] = {"ms_per_solve": ms, "rotations": int(st["rotations"]),
+                     "ms_precond": st["ms_precond"], "ms_bv_and_gram": st["ms_gemm"],
+                     "ms_jacobi": st["ms_jacobi"], "ms_finalize": st["ms_finalize"],
+                     "max_abs_err_over_u_smax": float(np.max(np.abs(r.s.cpu().numpy() - ls))
+                                                      / (U * ls[0])),
+                     "status": J.strerror(r.status)}
+        log(f"{name}: {ms:.1f} ms, {st['rotations']} rotations")
+    print(json.dumps({"workload": "one-sided Jacobi SVD: C_100 (Sec. 4.2, relative score, "
+                                  "no preconditioner); 1024x512, singular values over 4 decades",
+                      "variants": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,7 +436,7 @@ def main():
                     help="for counter runs: one device copy of 256 MiB (a reference kernel of "
                          "known traffic) followed by one solve, no timing output")
     ap.add_argument("--n-precision", type=int, default=4096)
-    ap.add_argument("--workload", choices=("single", "batch", "serve", "precision"),
+    ap.add_argument("--workload", choices=("single", "batch", "serve", "precision", "svd"),
                     default="single",
                     help="single: the n=1024 headline workload; batch: 2048 uneven matrices; "
                          "serve: a Poisson request stream through the library's server")
@@ -395,6 +463,9 @@ def main():
         return
     if args.workload == "precision":
         bench_precision(args)
+        return
+    if args.workload == "svd":
+        bench_svd(args)
         return
 
     import numpy as np

@@ -405,23 +405,25 @@ int svd_one(const double* B, int m, int n, int ldb, double* S, double* U, int ld
             int ldv, double tol, int pivot, int precond, const je_opts& o, je_stats* st,
             hipStream_t s) {
   const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
-  const size_t ld = ld_of(n), ldx = ld_of(m);
+  const size_t ld = ld_of(n);  // row stride of B (row-major), G, V^T and the preconditioner
   const bool pre = precond && n > 1;
-  const size_t xm = al((size_t)n * ldx * 8), mat = al((size_t)n * ld * 8);
-  size_t bytes = 2 * xm + 2 * mat + 3 * al((size_t)n * 8) + 3 * al((size_t)n * 4) + al(64) +
+  const size_t ym = al((size_t)m * ld * 8), mat = al((size_t)n * ld * 8);
+  size_t bytes = 2 * ym + 2 * mat + 5 * al((size_t)n * 8) + 3 * al((size_t)n * 4) + al(64) +
                  al(sizeof(JCtl));
   if (pre) bytes += 5 * mat + al(precond_f32_bytes(n));
   int err = JE_OK;
   char* p = (char*)pool_get(bytes, &err);
   if (!p) return err;
   auto take = [&](size_t b) { char* r = p; p += al(b); return (void*)r; };
-  double* X = (double*)take(xm);
-  double* X2 = (double*)take(xm);
+  double* Y = (double*)take(ym);
+  double* Y2 = (double*)take(ym);
   double* G = (double*)take(mat);
   double* Vt = (double*)take(mat);
   double* best = (double*)take((size_t)n * 8);
   double* part = (double*)take((size_t)n * 8);
-  (void)take((size_t)n * 8);
+  double* diag = (double*)take((size_t)n * 8);
+  double* rowp = (double*)take((size_t)n * 8);
+  double* rowq = (double*)take((size_t)n * 8);
   int* arg = (int*)take((size_t)n * 4);
   int* rank = (int*)take((size_t)n * 4);
   int* flag = (int*)take((size_t)n * 4);
@@ -439,11 +441,11 @@ int svd_one(const double* B, int m, int n, int ldb, double* S, double* U, int ld
   }
   je_stats Sx{};
 
-  // ---- 1. X = B^T, finiteness, A = X X^T, ||A||_F
+  // ---- 1. B row-major, finiteness, A = B^T B, ||A||_F
   Timer tp(s);
   HIPCHK(hipMemsetAsync(flag, 0, 4, s));
-  HIPCHK(launch_svd_load(B, m, n, ldb, X, (int)ldx, flag, s));
-  HIPCHK(launch_svd_gram(X, (int)ldx, m, n, G, (int)ld, s));
+  HIPCHK(launch_svd_load(B, m, n, ldb, Y, (int)ld, flag, s));
+  HIPCHK(launch_svd_gram(Y, (int)ld, m, n, G, (int)ld, s));
   HIPCHK(launch_fro2(G, n, (int)ld, part, scal, s));
   int hflag = 0;
   double normF = 0.0;
@@ -463,10 +465,10 @@ int svd_one(const double* B, int m, int n, int ldb, double* S, double* U, int ld
     if (r) return r;
     Sx.ms_precond = tp.stop();
     Timer tg(s);
-    HIPCHK(launch_svd_rowmix(Q, (int)ld, X, (int)ldx, n, m, X2, (int)ldx, s));
-    std::swap(X, X2);
+    HIPCHK(launch_svd_rowmix(Y, (int)ld, Q, (int)ld, m, n, Y2, (int)ld, s));
+    std::swap(Y, Y2);
     if (Vr) HIPCHK(launch_svd_transpose(Q, (int)ld, n, Vr, (int)ld, s));
-    HIPCHK(launch_svd_gram(X, (int)ldx, m, n, G, (int)ld, s));
+    HIPCHK(launch_svd_gram(Y, (int)ld, m, n, G, (int)ld, s));
     HIPCHK(launch_offnorm(G, n, (int)ld, part, scal + 2, s));
     HIPCHK(hipMemcpyAsync(&Sx.a_hat_off, scal + 2, 8, hipMemcpyDeviceToHost, s));
     Sx.ms_gemm = tg.stop();
@@ -478,10 +480,10 @@ int svd_one(const double* B, int m, int n, int ldb, double* S, double* U, int ld
   // ---- 3. one-sided pivoted Jacobi
   Timer tj(s);
   SDesc d{};
-  d.X = X; d.m = m; d.ldx = (int)ldx;
+  d.Y = Y; d.m = m; d.ldy = (int)ld;
   d.Vt = Vr; d.ldv = (int)ld;
   d.G = G; d.n = n; d.ldg = (int)ld;
-  d.best = best; d.arg = arg;
+  d.best = best; d.arg = arg; d.diag = diag; d.rowp = rowp; d.rowq = rowq;
   d.thr = thr; d.maxrot = maxrot; d.pivot = pivot;
   d.plog = o.pivot_log; d.logcap = o.pivot_log ? o.pivot_log_cap : 0;
   d.ctl = ctl;
@@ -500,7 +502,7 @@ int svd_one(const double* B, int m, int n, int ldb, double* S, double* U, int ld
   Timer tf(s);
   HIPCHK(launch_offnorm(G, n, (int)ld, part, scal + 3, s));
   HIPCHK(hipMemcpyAsync(&Sx.final_off, scal + 3, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(launch_svd_out(X, (int)ldx, m, G, (int)ld, Vr, (int)ld, n, rank, S, U, ldu, V, ldv, s));
+  HIPCHK(launch_svd_out(Y, (int)ld, m, G, (int)ld, Vr, (int)ld, n, rank, S, U, ldu, V, ldv, s));
   HIPCHK(hipStreamSynchronize(s));
   Sx.ms_finalize = tf.stop();
   if (st) *st = Sx;

@@ -163,18 +163,20 @@ hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int*
 // ------------------------------------------------------------------ one-sided SVD
 constexpr int kSvdMaxN = 8192;
 
-// Device state of the one-sided Jacobi SVD: X = B^T (row k = column b_k, row stride ldx),
-// the right factor Vt (rows rotated with those of X; may be null), the Gram matrix G = X X^T
-// (row-major), the per-row best score cache and the control block.
+// Device state of the one-sided Jacobi SVD: Y = B row-major (row stride ldy), the right
+// factor Vt = V^T (rows rotated with the columns of B; may be null), the Gram matrix
+// G = B^T B (row-major), the per-row best score cache, the diagonal of G and the last
+// recomputed rows p and q of G (device scratch of n entries each), the control block.
 struct SDesc {
-  double* X;
-  int m, ldx;
+  double* Y;
+  int m, ldy;
   double* Vt;
   int ldv;
   double* G;
   int n, ldg;
   double* best;
   int* arg;
+  double *diag, *rowp, *rowq;
   double thr;
   long long maxrot;
   int pivot;                    // 0 greedy, 1 gap, 2 relative
@@ -183,18 +185,21 @@ struct SDesc {
   JCtl* ctl;
 };
 
-hipError_t launch_svd_load(const double* B, int m, int n, int ldb, double* X, int ldx, int* flag,
+hipError_t launch_svd_load(const double* B, int m, int n, int ldb, double* Y, int ldy, int* flag,
                            hipStream_t s);
-hipError_t launch_svd_gram(const double* X, int ldx, int m, int n, double* G, int ldg,
+hipError_t launch_svd_gram(const double* Y, int ldy, int m, int n, double* G, int ldg,
                            hipStream_t s);
-hipError_t launch_svd_rowmix(const double* Q, int ldq, const double* X, int ldx, int n, int m,
-                             double* Y, int ldy, hipStream_t s);
+// Z = Y Q: the rows of B times the preconditioner.
+hipError_t launch_svd_rowmix(const double* Y, int ldy, const double* Q, int ldq, int m, int n,
+                             double* Z, int ldz, hipStream_t s);
 hipError_t launch_svd_transpose(const double* Q, int ldq, int n, double* Vt, int ldv,
                                 hipStream_t s);
 // Row cache, then the whole rotation sequence in one launch (ends at the stop rule, the
 // rotation cap or a stall; ctl->done = 1).
 hipError_t launch_svd_jacobi(const SDesc& d, hipStream_t s);
-hipError_t launch_svd_out(const double* X, int ldx, int m, const double* G, int ldg,
+// true when B and the per-row state of the rotation kernel fit in LDS
+bool svd_resident(int m, int n);
+hipError_t launch_svd_out(const double* Y, int ldy, int m, const double* G, int ldg,
                           const double* Vt, int ldvt, int n, int* rank, double* S, double* U,
                           int ldu, double* V, int ldv, hipStream_t s);
 
