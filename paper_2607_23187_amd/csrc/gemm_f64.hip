@@ -23,12 +23,12 @@ template <int TRANSA>
 __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __restrict__ A,
                                            int lda, const double* __restrict__ B, int ldb,
                                            double beta, const double* Cin, int ldcin, double* C,
-                                           int ldc) {
+                                           int ldc, int tile_i, int tile_j) {
   __shared__ double sA[GK][GB + 2];  // sA[k][i] = op(A)[i0 + i][k0 + k]
   __shared__ double sB[GK][GB + 2];  // sB[k][j] = B[k0 + k][j0 + j]
   constexpr int PER = GB * GK / 256;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int i0 = blockIdx.y * GB, j0 = blockIdx.x * GB;
+  const int i0 = tile_i * GB, j0 = tile_j * GB;
   const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
   d4 acc[2][2];
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int n, double alpha, const double
                                                int lda, const double* __restrict__ B, int ldb,
                                                double beta, const double* Cin, int ldcin,
                                                double* C, int ldc) {
-  dgemm_tile<TRANSA>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc);
+  dgemm_tile<TRANSA>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc, blockIdx.y, blockIdx.x);
 }
 
 __device__ __forceinline__ double* bm_ptr(BMat& b, size_t off) {
@@ -115,26 +115,39 @@ __device__ __forceinline__ double* bm_ptr(BMat& b, size_t off) {
 }
 
 // One product per matrix of a batch, operands chosen by BMat field offsets (leading
-// dimension b.ld for all of them); tiles past the matrix's n exit.
+// dimension b.ld for all of them); tiles past the matrix's n exit.  Workgroups are handed
+// to the 8 XCDs round-robin by linear index, so the 1-D grid is ordered to put every tile
+// of matrix z on XCD z mod 8: the tiles of a product then share the operand panels in one
+// L2 instead of fetching them into several.
+constexpr int kXcds = 8;
+
 template <int TRANSA>
-__global__ __launch_bounds__(256) void k_dgemm_b(BMat* __restrict__ mats, double alpha,
-                                                 size_t offA, size_t offB, double beta,
-                                                 size_t offCin, size_t offC) {
-  BMat& b = mats[blockIdx.z];
+__global__ __launch_bounds__(256) void k_dgemm_b(BMat* __restrict__ mats, int count, int nb,
+                                                 double alpha, size_t offA, size_t offB,
+                                                 double beta, size_t offCin, size_t offC) {
+  const int L = blockIdx.x, xcd = L % kXcds, slot = L / kXcds, T = nb * nb;
+  const int z = xcd + kXcds * (slot / T), t = slot % T;
+  if (z >= count) return;
+  BMat& b = mats[z];
   const int n = b.n;
-  if ((int)blockIdx.y * GB >= n || (int)blockIdx.x * GB >= n) return;
+  const int by = t / nb, bx = t % nb;
+  if (by * GB >= n || bx * GB >= n) return;
   dgemm_tile<TRANSA>(n, alpha, bm_ptr(b, offA), b.ld, bm_ptr(b, offB), b.ld, beta,
-                     beta != 0.0 ? bm_ptr(b, offCin) : nullptr, b.ld, bm_ptr(b, offC), b.ld);
+                     beta != 0.0 ? bm_ptr(b, offCin) : nullptr, b.ld, bm_ptr(b, offC), b.ld,
+                     by, bx);
 }
 
 hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
                           size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s) {
-  int nb = (nmax + GB - 1) / GB;
-  dim3 g(nb, nb, count), bl(256);
+  const int nb = (nmax + GB - 1) / GB;
+  const long long blocks = (long long)kXcds * ((count + kXcds - 1) / kXcds) * nb * nb;
+  dim3 g((unsigned)blocks), bl(256);
   if (transA)
-    hipLaunchKernelGGL(k_dgemm_b<1>, g, bl, 0, s, m, alpha, offA, offB, beta, offCin, offC);
+    hipLaunchKernelGGL(k_dgemm_b<1>, g, bl, 0, s, m, count, nb, alpha, offA, offB, beta, offCin,
+                       offC);
   else
-    hipLaunchKernelGGL(k_dgemm_b<0>, g, bl, 0, s, m, alpha, offA, offB, beta, offCin, offC);
+    hipLaunchKernelGGL(k_dgemm_b<0>, g, bl, 0, s, m, count, nb, alpha, offA, offB, beta, offCin,
+                       offC);
   return hipGetLastError();
 }
 
