@@ -146,8 +146,13 @@ def jacobi(a: np.ndarray, pivot: int = GAP, stop: int = STOP_CERT, thr: float = 
                         st.final_sel, st.final_cert, st.final_off, int(st.status))
 
 
-F32_TOL1, F32_RHO1 = 2.0 ** -22, 1.0   # first pass: FP32 floor of off(fl32(A)), or no progress
-F32_TOL2, F32_RHO2 = 0.0, 0.5          # refinement passes: until a sweep fails to halve off
+F32_TOL1, F32_RHO1 = 2.0 ** -22, 1.0   # single pass: FP32 floor of off(fl32(A)), or no progress
+# first of two passes: the refinement restarts from fl32(Q^T A Q), whose off-norm is at the
+# FP32 level whatever the first pass reached, so the first pass stops earlier
+F32_TOL1_REFINED = 2.0 ** -18
+# refinement passes: until a sweep fails to halve off, or off <= 2^-30 ||A32||_F (below
+# that what remains is the FP32-level coupling inside clusters that the pass skips)
+F32_TOL2, F32_RHO2 = 2.0 ** -30, 0.5
 
 
 def jacobi_f32(a: np.ndarray, max_sweeps: int = 20, tol: float = F32_TOL1,
@@ -226,7 +231,8 @@ def eigh(a: np.ndarray, tol: float, pivot: int = GAP, precond: str = "fp32",
     q = None
     sw = 0
     if precond == "fp32" and n > 1:
-        _, v32, sw = jacobi_f32(a, max_sweeps=sweeps32)
+        _, v32, sw = jacobi_f32(a, max_sweeps=sweeps32,
+                                 tol=F32_TOL1 if passes == 1 else F32_TOL1_REFINED)
         q = householder_q(v32.astype(np.float64))
         for _ in range(passes - 1):
             a1 = q.T @ (a @ q)
@@ -330,7 +336,8 @@ def svd(b: np.ndarray, tol: float, pivot: int = GAP, precond: str = "none",
     sw = 0
     if precond == "fp32" and n > 1:
         g0 = 0.5 * (g0 + g0.T)
-        _, v32, sw = jacobi_f32(g0, max_sweeps=sweeps32)
+        _, v32, sw = jacobi_f32(g0, max_sweeps=sweeps32,
+                                 tol=F32_TOL1 if passes == 1 else F32_TOL1_REFINED)
         q = householder_q(v32.astype(np.float64))
         for _ in range(passes - 1):
             a1 = q.T @ (g0 @ q)

@@ -69,7 +69,33 @@ long long default_maxrot(int n) { return 40ll * n * n + 64; }
 // A refinement pass works on a nearly diagonal fl32(Q^T A Q) whose off-diagonal entries FP32
 // holds with full relative precision; it sweeps until a sweep no longer halves off(A32).
 constexpr double kF32Tol1 = 0x1p-22, kF32Rho1 = 1.0;
-constexpr double kF32Tol2 = 0.0, kF32Rho2 = 0.5;
+constexpr double kF32Tol1Refined = 0x1p-18;
+// Stop tolerance of the first FP32 pass: its FP32 floor when it is the only pass; looser
+// when a refinement pass follows, which starts from fl32(Q^T A Q) (off ~ u_32 ||A|| however
+// far the first pass went), so the first pass's last sweeps below that level buy nothing.
+// JE_F32_TOL1_EXP=k sets 2^-k for the refined case.
+static double f32_tol1(int passes) {
+  if (passes <= 1) return kF32Tol1;
+  static const double t = [] {
+    const char* e = std::getenv("JE_F32_TOL1_EXP");
+    return e ? std::ldexp(1.0, -std::atoi(e)) : kF32Tol1Refined;
+  }();
+  return t;
+}
+constexpr double kF32Rho2 = 0.5;
+// Refinement pass: sweeps until a sweep fails to halve off, or off <= 2^-30 ||A||_F (below
+// that the remaining off-diagonal mass is the FP32-level coupling inside clusters that the
+// pass skips, and the sweep that would show the stall is saved).  JE_F32_TOL2_EXP=k sets
+// 2^-k (0: off).
+static double f32_tol2() {
+  static const double t = [] {
+    const char* e = std::getenv("JE_F32_TOL2_EXP");
+    if (!e) return 0x1p-30;
+    const int k = std::atoi(e);
+    return k > 0 ? std::ldexp(1.0, -k) : 0.0;
+  }();
+  return t;
+}
 
 // Workspace carving for one problem of size n.
 struct WS {
@@ -213,7 +239,7 @@ int precond_q(const double* Asym, int n, int ld, double*& X, double*& Xo, double
               hipStream_t s) {
   int sw = 0;
   *sweeps = 0;
-  HIPCHK(run_precond_f32(Asym, n, ld, X, ld, f32, o.fp32_max_sweeps, kF32Tol1, kF32Rho1, &sw,
+  HIPCHK(run_precond_f32(Asym, n, ld, X, ld, f32, o.fp32_max_sweeps, f32_tol1(o.fp32_passes), kF32Rho1, &sw,
                          s));
   *sweeps += sw;
   int r = orthonormalize(X, Xo, R, n, ld, part, scal, s);
@@ -222,7 +248,7 @@ int precond_q(const double* Asym, int n, int ld, double*& X, double*& Xo, double
     HIPCHK(launch_dgemm(n, 0, 1.0, Asym, ld, X, ld, 0.0, nullptr, 0, T, ld, s));
     HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, T, ld, 0.0, nullptr, 0, A, ld, s));
     HIPCHK(launch_symmetrize(A, n, ld, s));
-    HIPCHK(run_precond_f32(A, n, ld, T, ld, f32, o.fp32_max_sweeps, kF32Tol2, kF32Rho2, &sw, s));
+    HIPCHK(run_precond_f32(A, n, ld, T, ld, f32, o.fp32_max_sweeps, f32_tol2(), kF32Rho2, &sw, s));
     *sweeps += sw;
     HIPCHK(launch_dgemm(n, 0, 1.0, X, ld, T, ld, 0.0, nullptr, 0, Xo, ld, s));
     std::swap(X, Xo);
@@ -731,13 +757,13 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
                                r, s));
       return JE_OK;
     };
-    if (int r = f32pass(BF(Asym), offX, kF32Tol1, kF32Rho1)) return r;
+    if (int r = f32pass(BF(Asym), offX, f32_tol1(o.fp32_passes), kF32Rho1)) return r;
     if (int r = orthonormalize_b()) return r;
     for (int pass = 1; pass < o.fp32_passes; ++pass) {
       HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
       HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
       HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
-      if (int r = f32pass(BF(A), BF(T), kF32Tol2, kF32Rho2)) return r;
+      if (int r = f32pass(BF(A), BF(T), f32_tol2(), kF32Rho2)) return r;
       HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, offX, BF(T), 0.0, 0, offXb, s));
       std::swap(offX, offXb);
       if (int r = orthonormalize_b()) return r;

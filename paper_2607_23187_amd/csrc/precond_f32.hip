@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <vector>
 
@@ -107,13 +108,13 @@ __device__ __forceinline__ void inner_pair(int full, int r, int k, int& p, int& 
   }
 }
 
-// Both phases of an inner round read rows only.  With J the product of the round's disjoint
+// Two-phase inner round (the form used for 16-row blocks).  Both phases read rows only.  With J the product of the round's disjoint
 // rotations, the row phase forms M = J^T S and stores it transposed, W = M^T; the second
 // phase forms J^T W = (S J ... )^T, i.e. the rotated matrix J^T S J read by rows (it is
 // symmetric up to rounding; its upper triangle is the one used).  A lane keeps the same
 // pair and columns in both phases, so its c, s stay in registers.
 template <int PB>
-__device__ __forceinline__ void solve_body(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
+__device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
                                            float (*Ut)[Blk<PB>::PL], float* __restrict__ A,
                                            int np, int2 pr, float* __restrict__ Uo,
                                            int inner_max, int full, float tol2, float rho2) {
@@ -205,26 +206,189 @@ __device__ __forceinline__ void solve_body(float (*S)[Blk<PB>::PL], float (*W)[B
   }
 }
 
-// out (PM x PM, R x 4 entries per thread) = X^T Y if TA, else X Y; X, Y in LDS.
-template <int PB, bool TA, int R>
-__device__ __forceinline__ void tile_gemm(float (*X)[Blk<PB>::PL], float (*Y)[Blk<PB>::PL],
-                                          int ti, int tj, float (&acc)[R][4]) {
-  constexpr int PM = Blk<PB>::PM;
-#pragma unroll
-  for (int a = 0; a < R; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0f;
-#pragma unroll 4
-  for (int k = 0; k < PM; ++k) {
-    const float4 y = *reinterpret_cast<const float4*>(&Y[k][tj]);
-    const float yy[4] = {y.x, y.y, y.z, y.w};
-#pragma unroll
-    for (int a = 0; a < R; ++a) {
-      const float xv = TA ? X[k][ti + a] : X[ti + a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xv, yy[c], acc[a][c]);
+// Rotation of one pair of an inner round, from the current subproblem: cosine, sine, the
+// new diagonal entries and the new pivot entry (0, or a_pq itself when the pair is
+// skipped, see f32_noise_pair).
+struct RotF {
+  float c, s, napp, naqq, z;
+};
+
+template <int PL>
+__device__ __forceinline__ RotF pair_rot(const float (*S)[PL], int p, int q) {
+  const float app = S[p][p], aqq = S[q][q], apq = S[p][q];
+  RotF r{1.0f, 0.0f, app, aqq, apq};
+  if (!(apq == 0.0f || f32_noise_pair(app, aqq, apq))) {
+    float t;
+    rot_fast(app, aqq, apq, t, r.c, r.s);
+    r.napp = app + t * apq;
+    r.naqq = aqq - t * apq;
+    r.z = 0.0f;
+  }
+  return r;
+}
+
+// 2 x 2 block X = S[{pb, qb}][{pc, qc}] of the rotated subproblem J^T S J: rows by pair b,
+// then columns by pair c; the diagonal block of a pair (b == c) gets its new diagonal and
+// pivot entries exactly.
+__device__ __forceinline__ void rot_block(const RotF& rb, const RotF& rc, bool diag, float& x,
+                                          float& y, float& z, float& w) {
+  const float x1 = rb.c * x + rb.s * z, y1 = rb.c * y + rb.s * w;
+  const float z1 = rb.c * z - rb.s * x, w1 = rb.c * w - rb.s * y;
+  x = diag ? rb.napp : rc.c * x1 + rc.s * y1;
+  y = diag ? rb.z : rc.c * y1 - rc.s * x1;
+  z = diag ? rb.z : rc.c * z1 + rc.s * w1;
+  w = diag ? rb.naqq : rc.c * w1 - rc.s * z1;
+}
+
+// An inner round is one phase: the pairs of the round are disjoint, so J^T S J is, block by
+// block, X_bc -> J_b^T X_bc J_c over the 2 x 2 blocks of pair b's rows and pair c's columns.
+// Lane (kb, i) owns the blocks (kb, 2i) and (kb, 2i + 1) and columns 4i .. 4i + 3 of rows
+// p, q of U^T; it evaluates the three rotations it needs itself (the same instructions on
+// the same values in every lane, so all lanes agree).  S is double-buffered: a round reads
+// one buffer and writes the other, and a single barrier separates rounds.  S stays
+// symmetric up to rounding; its upper triangle is the one used.  (Used for 32-row blocks:
+// measured against the two-phase form, n = 4096 FP32 stage 243 -> 236 ms, batches
+// 272 -> 261 ms; for 16-row blocks, two waves per subproblem, the two-phase form is faster,
+// n = 1024 27.8 vs 34.7 ms.)
+template <int PB>
+__device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
+                                           float (*Ut)[Blk<PB>::PL], float* __restrict__ A,
+                                           int np, int2 pr, float* __restrict__ Uo,
+                                           int inner_max, int full, float tol2, float rho2) {
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, LB = PM / 4, PL = Blk<PB>::PL;
+  __shared__ float red[2][NT / 64];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < PM * PM; e += NT) {
+    int i = e / PM, j = e % PM;
+    S[i][j] = A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
+    Ut[i][j] = (i == j) ? 1.0f : 0.0f;
+  }
+  __syncthreads();
+  const int kb = tid / LB, li = tid % LB, jb = li * 4, kc = 2 * li;
+  const int nr = full ? PM - 1 : PB;
+  float(*Sc)[PL] = S;
+  float(*Sn)[PL] = W;
+  float prev_off = 3.4e38f;
+  for (int sw = 0; sw < inner_max; ++sw) {
+    for (int r = 0; r < nr; ++r) {
+      int pb, qb, p0, q0, p1, q1;
+      inner_pair<PB>(full, r, kb, pb, qb);
+      inner_pair<PB>(full, r, kc, p0, q0);
+      inner_pair<PB>(full, r, kc + 1, p1, q1);
+      float x0 = Sc[pb][p0], y0 = Sc[pb][q0], z0 = Sc[qb][p0], w0 = Sc[qb][q0];
+      float x1 = Sc[pb][p1], y1 = Sc[pb][q1], z1 = Sc[qb][p1], w1 = Sc[qb][q1];
+      const float4 up = *reinterpret_cast<const float4*>(&Ut[pb][jb]);
+      const float4 uq = *reinterpret_cast<const float4*>(&Ut[qb][jb]);
+      const RotF rb = pair_rot<PL>(Sc, pb, qb);
+      const RotF r0 = pair_rot<PL>(Sc, p0, q0);
+      const RotF r1 = pair_rot<PL>(Sc, p1, q1);
+      rot_block(rb, r0, kb == kc, x0, y0, z0, w0);
+      rot_block(rb, r1, kb == kc + 1, x1, y1, z1, w1);
+      Sn[pb][p0] = x0; Sn[pb][q0] = y0; Sn[qb][p0] = z0; Sn[qb][q0] = w0;
+      Sn[pb][p1] = x1; Sn[pb][q1] = y1; Sn[qb][p1] = z1; Sn[qb][q1] = w1;
+      float4 po, qo;
+      po.x = rb.c * up.x + rb.s * uq.x; qo.x = rb.c * uq.x - rb.s * up.x;
+      po.y = rb.c * up.y + rb.s * uq.y; qo.y = rb.c * uq.y - rb.s * up.y;
+      po.z = rb.c * up.z + rb.s * uq.z; qo.z = rb.c * uq.z - rb.s * up.z;
+      po.w = rb.c * up.w + rb.s * uq.w; qo.w = rb.c * uq.w - rb.s * up.w;
+      *reinterpret_cast<float4*>(&Ut[pb][jb]) = po;
+      *reinterpret_cast<float4*>(&Ut[qb][jb]) = qo;
+      __syncthreads();
+      float(*t)[PL] = Sc;
+      Sc = Sn;
+      Sn = t;
+    }
+    if (sw + 1 < inner_max) {
+      // off(S) and ||S||_F decide whether another inner sweep pays
+      float so = 0.0f, sd = 0.0f;
+      for (int e = tid; e < PM * PM; e += NT) {
+        int i = e / PM, j = e % PM;
+        float v = Sc[i][j] * Sc[i][j];
+        if (i == j) sd += v; else so += v;
+      }
+      for (int o = 32; o > 0; o >>= 1) { so += __shfl_xor(so, o); sd += __shfl_xor(sd, o); }
+      if ((tid & 63) == 0) { red[0][tid >> 6] = so; red[1][tid >> 6] = sd; }
+      __syncthreads();
+      float off = 0.0f, dg = 0.0f;
+      for (int w = 0; w < NT / 64; ++w) { off += red[0][w]; dg += red[1][w]; }
+      __syncthreads();
+      if (off <= tol2 * (off + dg) || off >= rho2 * prev_off) break;
+      prev_off = off;
     }
   }
+  if (Sc != S) {  // the result ends in S (callers read it there)
+    for (int e = tid; e < PM * PM; e += NT) {
+      int i = e / PM, j = e % PM;
+      S[i][j] = Sc[i][j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < PM * PM; e += NT) {
+    int i = e / PM, j = e % PM;
+    Uo[e] = Ut[j][i];
+    float v = (i <= j) ? S[i][j] : S[j][i];
+    A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
+  }
+}
+
+template <int PB>
+__device__ __forceinline__ void solve_body(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
+                                           float (*Ut)[Blk<PB>::PL], float* __restrict__ A,
+                                           int np, int2 pr, float* __restrict__ Uo,
+                                           int inner_max, int full, float tol2, float rho2) {
+  if constexpr (PB == 16)
+    solve_body_rows<PB>(S, W, Ut, A, np, pr, Uo, inner_max, full, tol2, rho2);
+  else
+    solve_body_blocks<PB>(S, W, Ut, A, np, pr, Uo, inner_max, full, tol2, rho2);
+}
+
+// out (PM x PM) = X^T Y if TA, else X Y; X, Y in LDS.  On the matrix cores
+// (v_mfma_f32_16x16x4f32): the output is split into 16 x 16 tiles, two per wave (wave w
+// owns tiles 2w and 2w + 1, row-major over the (PM/16)^2 tiles), K advances by 4 per
+// instruction.  Operand layout: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; result
+// D[i][j] in lane j + 16 (i / 4), register i % 4 (checked by an in-bounds probe).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int PB, bool TA>
+__device__ __forceinline__ void tile_mfma(float (*X)[Blk<PB>::PL], float (*Y)[Blk<PB>::PL],
+                                          f4 (&acc)[2]) {
+  constexpr int PM = Blk<PB>::PM, TT = PM / 16;
+  static_assert(Blk<PB>::NT / 64 * 2 == TT * TT, "two 16 x 16 tiles per wave");
+  const int l = threadIdx.x & 63, t0 = (threadIdx.x >> 6) * 2;
+  const int li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int ti = (t0 + u) / TT, tj = (t0 + u) % TT;
+    f4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < PM; k0 += 4) {
+      const float a = TA ? X[k0 + lk][16 * ti + li] : X[16 * ti + li][k0 + lk];
+      const float b = Y[k0 + lk][16 * tj + li];
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    acc[u] = c;
+  }
+}
+
+// Row and column (within the PM x PM output) of register v of tile u of this lane.
+template <int PB>
+__device__ __forceinline__ void tile_rc(int u, int v, int& i, int& j) {
+  constexpr int TT = Blk<PB>::PM / 16;
+  const int l = threadIdx.x & 63, t = (threadIdx.x >> 6) * 2 + u;
+  i = 16 * (t / TT) + 4 * (l >> 4) + v;
+  j = 16 * (t % TT) + (l & 15);
+}
+
+template <int PB>
+__device__ __forceinline__ void tile_store_lds(float (*T)[Blk<PB>::PL], const f4 (&acc)[2]) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int i, j;
+      tile_rc<PB>(u, v, i, j);
+      T[i][j] = acc[u][v];
+    }
 }
 
 // Block update of A for block pairs P < R: A_PR <- U_P^T A_PR U_R, mirrored to A_RP (so A
@@ -251,33 +415,31 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_block_apply_a(float* __restrict
     Ab[i][j] = A[(size_t)blk_row<PB>(pp.x, pp.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
   }
   __syncthreads();
-  const int ti = (tid / (PM / 4)) * 2, tj = (tid % (PM / 4)) * 4;
-  float acc[2][4];
-  tile_gemm<PB, true, 2>(Up, Ab, ti, tj, acc);  // T = U_P^T A_PR
+  f4 acc[2];
+  tile_mfma<PB, true>(Up, Ab, acc);  // T = U_P^T A_PR
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Ab[ti + a][tj + c] = acc[a][c];
+  tile_store_lds<PB>(Ab, acc);
   __syncthreads();
-  tile_gemm<PB, false, 2>(Ab, Ur, ti, tj, acc);  // T U_R
+  tile_mfma<PB, false>(Ab, Ur, acc);  // T U_R
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      int gi = blk_row<PB>(pp.x, pp.y, ti + a), gj = blk_row<PB>(pr.x, pr.y, tj + c);
-      A[(size_t)gi * np + gj] = acc[a][c];
-      A[(size_t)gj * np + gi] = acc[a][c];
+    for (int v = 0; v < 4; ++v) {
+      int i, j;
+      tile_rc<PB>(u, v, i, j);
+      const int gi = blk_row<PB>(pp.x, pp.y, i), gj = blk_row<PB>(pr.x, pr.y, j);
+      A[(size_t)gi * np + gj] = acc[u][v];
+      A[(size_t)gj * np + gi] = acc[u][v];
     }
 }
 
 // V <- V U_R on the columns of block pair R, for the tile of PM rows from r0 (RT threads,
-// VR x 4 entries each).
+// two 16 x 16 output tiles per wave on the matrix cores).
 template <int PB>
 __device__ __forceinline__ void vtile_body(float (*Ur)[Blk<PB>::PL], float (*Vb)[Blk<PB>::PL],
                                            float* __restrict__ V, int nrows, int np, int r0,
                                            int2 pr, const float* __restrict__ Uh) {
-  constexpr int PM = Blk<PB>::PM, RT = Blk<PB>::NT, VR = PM * PM / (4 * RT);
+  constexpr int PM = Blk<PB>::PM, RT = Blk<PB>::NT;
   const int tid = threadIdx.x;
   for (int e = tid; e < PM * PM; e += RT) {
     int i = e / PM, j = e % PM;
@@ -285,15 +447,16 @@ __device__ __forceinline__ void vtile_body(float (*Ur)[Blk<PB>::PL], float (*Vb)
     Vb[i][j] = (r0 + i < nrows) ? V[(size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j)] : 0.0f;
   }
   __syncthreads();
-  const int ti = (tid / (PM / 4)) * VR, tj = (tid % (PM / 4)) * 4;
-  float acc[VR][4];
-  tile_gemm<PB, false, VR>(Vb, Ur, ti, tj, acc);
+  f4 acc[2];
+  tile_mfma<PB, false>(Vb, Ur, acc);
 #pragma unroll
-  for (int a = 0; a < VR; ++a)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (r0 + ti + a < nrows)
-        V[(size_t)(r0 + ti + a) * np + blk_row<PB>(pr.x, pr.y, tj + c)] = acc[a][c];
+    for (int v = 0; v < 4; ++v) {
+      int i, j;
+      tile_rc<PB>(u, v, i, j);
+      if (r0 + i < nrows) V[(size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j)] = acc[u][v];
+    }
 }
 
 // One launch per round: blocks [0, nsolve) solve the round's block pairs (writing U of this
@@ -406,6 +569,12 @@ size_t precond_f32_bytes(int n) {
 static bool graphs_enabled() {
   const char* e = std::getenv("JE_F32_GRAPH");
   return e && e[0] == '1';
+}
+
+// JE_F32_TRACE=1: off(A32)/||A32||_F after every sweep of a single solve, on stderr.
+static bool f32_trace() {
+  static const bool on = std::getenv("JE_F32_TRACE") != nullptr;
+  return on;
 }
 
 template <int PB>
@@ -530,6 +699,9 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
     if ((e = off_norm()) != hipSuccess) { cleanup(); return e; }
     off = h[0];
     nrm = h[1];
+    if (f32_trace())
+      std::fprintf(stderr, "JE_F32_TRACE n=%d tol=%g rho=%g sweep=%d off/norm=%.3e ratio=%.3f\n", n,
+                   tol, rho, sw, off / nrm, off / prev);
     if (nb == 2 || off >= rho * prev) break;
   }
   cleanup();
@@ -651,29 +823,24 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
     Ab[i][j] = A[(size_t)blk_row<BPB>(pp.x, pp.y, i) * np + blk_row<BPB>(pr.x, pr.y, j)];
   }
   __syncthreads();
-  const int ti = (tid / (PM / 4)) * 2, tj = (tid % (PM / 4)) * 4;
-  float acc[2][4];
-  tile_gemm<BPB, true, 2>(Up, Ab, ti, tj, acc);
+  f4 acc[2];
+  tile_mfma<BPB, true>(Up, Ab, acc);
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Ab[ti + a][tj + c] = acc[a][c];
+  tile_store_lds<BPB>(Ab, acc);
   __syncthreads();
-  tile_gemm<BPB, false, 2>(Ab, Ur, ti, tj, acc);
+  tile_mfma<BPB, false>(Ab, Ur, acc);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      int gi = blk_row<BPB>(pp.x, pp.y, ti + a), gj = blk_row<BPB>(pr.x, pr.y, tj + c);
-      A[(size_t)gi * np + gj] = acc[a][c];
-      A[(size_t)gj * np + gi] = acc[a][c];
+    for (int v = 0; v < 4; ++v) {
+      int i, j;
+      tile_rc<BPB>(u, v, i, j);
+      const int gi = blk_row<BPB>(pp.x, pp.y, i), gj = blk_row<BPB>(pr.x, pr.y, j);
+      A[(size_t)gi * np + gj] = acc[u][v];
+      A[(size_t)gj * np + gi] = acc[u][v];
     }
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Up[ti + a][tj + c] = acc[a][c];
+  tile_store_lds<BPB>(Up, acc);
   __syncthreads();
   tile_sq<BPB>(Up, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
 }

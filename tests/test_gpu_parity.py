@@ -167,6 +167,33 @@ def test_full_pipeline_against_oracle(n, seed, pivot):
     assert r.stats["sweeps32"] >= 1
 
 
+@pytest.mark.parametrize("n", [48, 200, 1024, 2100])
+def test_preconditioner_quality(n):
+    """The FP32 stage (Sec. 2.1) must leave A_hat = Q^T A Q nearly diagonal: off(A_hat) at
+    the FP32 level after one pass, well below it after the refinement, and few FP64
+    rotations.  Covers the single-subproblem (n <= 64), 16-row-block and 32-row-block
+    forms of the blocked FP32 Jacobi."""
+    p = I.config_c2(n=n) if n >= 1024 else I.clustered(n, seed=900 + n)
+    lam2 = np.max(np.abs(p.lam))
+    tol = 10 * n * U * lam2 / np.linalg.norm(p.a)
+    say("preconditioner quality", n)
+    r1 = J.eigh(gpu(p.a), tol=tol, precond="fp32", fp32_passes=1)
+    r2 = J.eigh(gpu(p.a), tol=tol, precond="fp32", fp32_passes=2)
+    for r in (r1, r2):
+        assert r.status == J.OK
+        assert np.max(np.abs(r.w.cpu().numpy() - p.lam)) <= 10 * n * U * lam2
+    off1 = r1.stats["a_hat_off"] / r1.stats["normF"]
+    off2 = r2.stats["a_hat_off"] / r2.stats["normF"]
+    say(f"  off1={off1:.3e} off2={off2:.3e} rot1={r1.stats['rotations']} "
+        f"rot2={r2.stats['rotations']} sweeps={r1.stats['sweeps32']},{r2.stats['sweeps32']}")
+    # one pass: Q carries FP32 rounding, so off(Q^T A Q) ~ u_32 sqrt(n) ||A||_F
+    assert off1 <= 4 * 2.0 ** -24 * np.sqrt(n)
+    assert off2 <= 2.0 ** -22
+    # both recipes put about 3.5 n index pairs inside clusters too tight for FP32, which
+    # the FP64 phase resolves with a few rotations each; the rest must be nearly done
+    assert r2.stats["rotations"] <= 16 * n + 0.01 * n * n
+
+
 def test_c2_spectrum_pipeline():
     """Half clustered (relative spread 1e-8), half log-uniform over six decades."""
     n = 512
