@@ -115,18 +115,21 @@ __device__ __forceinline__ void inner_pair(int full, int r, int k, int& p, int& 
 // pair and columns in both phases, so its c, s stay in registers.
 template <int PB>
 __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
-                                           float (*Ut)[Blk<PB>::PL], float* __restrict__ A,
-                                           int np, int2 pr, float* __restrict__ Uo,
-                                           int inner_max, int full, float tol2, float rho2) {
+                                           float (*Ut)[Blk<PB>::PL], const float* Ain,
+                                           float* Aout, int np, int2 pr, float* __restrict__ Uo,
+                                           int inner_max, int full, float tol2, float rho2,
+                                           bool preloaded) {
   constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, LB = PM / 4;
   __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
-  for (int e = tid; e < PM * PM; e += NT) {
-    int i = e / PM, j = e % PM;
-    S[i][j] = A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
-    Ut[i][j] = (i == j) ? 1.0f : 0.0f;
+  if (!preloaded) {
+    for (int e = tid; e < PM * PM; e += NT) {
+      int i = e / PM, j = e % PM;
+      S[i][j] = Ain[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
+      Ut[i][j] = (i == j) ? 1.0f : 0.0f;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // pair kb, columns jb .. jb+3 (the LB lanes of a pair share one wave)
   const int kb = tid / LB, jb = (tid % LB) * 4;
   const int nr = full ? PM - 1 : PB;
@@ -202,7 +205,7 @@ __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (
     int i = e / PM, j = e % PM;
     Uo[e] = Ut[j][i];
     float v = (i <= j) ? S[i][j] : S[j][i];
-    A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
+    Aout[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
   }
 }
 
@@ -252,18 +255,21 @@ __device__ __forceinline__ void rot_block(const RotF& rb, const RotF& rc, bool d
 // n = 1024 27.8 vs 34.7 ms.)
 template <int PB>
 __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
-                                           float (*Ut)[Blk<PB>::PL], float* __restrict__ A,
-                                           int np, int2 pr, float* __restrict__ Uo,
-                                           int inner_max, int full, float tol2, float rho2) {
+                                           float (*Ut)[Blk<PB>::PL], const float* Ain,
+                                           float* Aout, int np, int2 pr, float* __restrict__ Uo,
+                                           int inner_max, int full, float tol2, float rho2,
+                                           bool preloaded) {
   constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, LB = PM / 4, PL = Blk<PB>::PL;
   __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
-  for (int e = tid; e < PM * PM; e += NT) {
-    int i = e / PM, j = e % PM;
-    S[i][j] = A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
-    Ut[i][j] = (i == j) ? 1.0f : 0.0f;
+  if (!preloaded) {
+    for (int e = tid; e < PM * PM; e += NT) {
+      int i = e / PM, j = e % PM;
+      S[i][j] = Ain[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
+      Ut[i][j] = (i == j) ? 1.0f : 0.0f;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int kb = tid / LB, li = tid % LB, jb = li * 4, kc = 2 * li;
   const int nr = full ? PM - 1 : PB;
   float(*Sc)[PL] = S;
@@ -327,19 +333,21 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
     int i = e / PM, j = e % PM;
     Uo[e] = Ut[j][i];
     float v = (i <= j) ? S[i][j] : S[j][i];
-    A[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
+    Aout[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
   }
 }
 
 template <int PB>
 __device__ __forceinline__ void solve_body(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
-                                           float (*Ut)[Blk<PB>::PL], float* __restrict__ A,
-                                           int np, int2 pr, float* __restrict__ Uo,
-                                           int inner_max, int full, float tol2, float rho2) {
+                                           float (*Ut)[Blk<PB>::PL], const float* Ain,
+                                           float* Aout, int np, int2 pr, float* __restrict__ Uo,
+                                           int inner_max, int full, float tol2, float rho2,
+                                           bool preloaded = false) {
   if constexpr (PB == 16)
-    solve_body_rows<PB>(S, W, Ut, A, np, pr, Uo, inner_max, full, tol2, rho2);
+    solve_body_rows<PB>(S, W, Ut, Ain, Aout, np, pr, Uo, inner_max, full, tol2, rho2, preloaded);
   else
-    solve_body_blocks<PB>(S, W, Ut, A, np, pr, Uo, inner_max, full, tol2, rho2);
+    solve_body_blocks<PB>(S, W, Ut, Ain, Aout, np, pr, Uo, inner_max, full, tol2, rho2,
+                          preloaded);
 }
 
 // out (PM x PM) = X^T Y if TA, else X Y; X, Y in LDS.  On the matrix cores
@@ -470,11 +478,155 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_block_round(
   constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL;
   __shared__ __align__(16) float lds[3][PM][PL];
   if ((int)blockIdx.x < nsolve) {
-    solve_body<PB>(lds[0], lds[1], lds[2], A, np, pairs[blockIdx.x],
+    solve_body<PB>(lds[0], lds[1], lds[2], A, A, np, pairs[blockIdx.x],
                    U + (size_t)blockIdx.x * PM * PM, inner_max, full, tol2, rho2);
   } else {
     const int b = blockIdx.x - nsolve, R = b / nvt, rt = b - R * nvt;
     vtile_body<PB>(lds[0], lds[1], V, nrows, np, rt * PM, vpairs[R], vU + (size_t)R * PM * PM);
+  }
+}
+
+// 16 x 16 tile (ti, tj) of op(X) Y on the matrix cores, K a multiple of 4; X, Y in LDS,
+// op(X)[i][k] = X[k][xc + i] if TA else X[i][xc + k], Y[k][j] = Y[k][yc + j].
+template <int PL, bool TA>
+__device__ __forceinline__ f4 mfma_tile(const float (*X)[PL], int xc, const float (*Y)[PL], int yc,
+                                        int K, int ti, int tj) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  f4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const float a = TA ? X[k0 + lk][xc + 16 * ti + li] : X[16 * ti + li][xc + k0 + lk];
+    const float b = Y[k0 + lk][yc + 16 * tj + li];
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  return c;
+}
+
+// Fused round r >= 2 of a sweep.  The block update of round r - 1 is not launched on its
+// own: one launch runs
+//   blocks [0, nb2)             the subproblem solves of round r,
+//   [nb2, nb2 + na)             the A update of round r - 1 (pair blocks P < R),
+//   [nb2 + na, nb2 + na + nb2)  the copy of round r - 1's within-pair blocks,
+//   [.., + nvt nb2)             the V update of round r - 1,
+// reading Acur and writing Anxt, so that no workgroup reads what another one writes.  Acur
+// holds round r - 1's pair blocks after its solves and every other block before round
+// r - 1's update.  A solve of round r pairs blocks I, J that round r - 1 had in different
+// pairs P (I in half hI) and R (J in half hJ), so it forms its cross block itself as
+// U_P(:, hI)^T A_PR U_R(:, hJ) and reads its diagonal blocks as they are; the A update
+// leaves the blocks paired in round r to those solves.  apply_only (the last round of a
+// sweep): only the A update of round r - 1, for every block, and the copy of its whole
+// pair blocks.  pos[X] = 2 * (index of the pair holding block X) + (X is its second block).
+template <int PB>
+__global__ __launch_bounds__(Blk<PB>::NT) void k_block_fused(
+    const float* __restrict__ Acur, float* __restrict__ Anxt, int np, int nb2,
+    const int2* __restrict__ pairs_r, const int* __restrict__ pos_r,
+    const int2* __restrict__ pairs_p, const int* __restrict__ pos_p,
+    const float* __restrict__ Uprev, float* __restrict__ Ucur, int apply_only,
+    float* __restrict__ V, int nrows, int nvt) {
+  constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL, NT = Blk<PB>::NT, TB = PB / 16;
+  __shared__ __align__(16) float lds[3][PM][PL];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int ns = apply_only ? 0 : nb2, na = nb2 * (nb2 - 1) / 2;
+  int b = blockIdx.x;
+  if (b < ns) {
+    // ---- solve of round r, pair b = (I, J)
+    float(*S)[PL] = lds[0];
+    float(*W)[PL] = lds[1];
+    float(*Ut)[PL] = lds[2];
+    const int2 pr = pairs_r[b];
+    const int pi = pos_p[pr.x], pj = pos_p[pr.y];
+    const int P = pi >> 1, hI = pi & 1, R = pj >> 1, hJ = pj & 1;
+    const int2 PP = pairs_p[P], RR = pairs_p[R];
+    const float* UP = Uprev + (size_t)P * PM * PM;
+    const float* UR = Uprev + (size_t)R * PM * PM;
+    for (int e = tid; e < PM * PM; e += NT) {
+      const int i = e / PM, j = e % PM;
+      W[i][j] = Acur[(size_t)blk_row<PB>(PP.x, PP.y, i) * np + blk_row<PB>(RR.x, RR.y, j)];
+      Ut[i][j] = UR[e];
+    }
+    __syncthreads();
+    // T = A_PR U_R(:, hJ): PM x PB, one 16 x 16 tile per wave
+    const f4 t = mfma_tile<PL, false>(W, 0, Ut, hJ * PB, PM, w / TB, w % TB);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[16 * (w / TB) + 4 * (l >> 4) + v][16 * (w % TB) + (l & 15)] = t[v];
+    for (int e = tid; e < PM * PM; e += NT) W[e / PM][e % PM] = UP[e];
+    __syncthreads();
+    // X = U_P(:, hI)^T T: PB x PB, tiles on the first TB^2 waves
+    f4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (w < TB * TB) x = mfma_tile<PL, true>(W, hI * PB, S, 0, PM, w / TB, w % TB);
+    __syncthreads();
+    if (w < TB * TB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * (w / TB) + 4 * (l >> 4) + v, j = 16 * (w % TB) + (l & 15);
+        S[i][PB + j] = x[v];
+        S[PB + j][i] = x[v];
+      }
+    }
+    for (int e = tid; e < PB * PB; e += NT) {
+      const int i = e / PB, j = e % PB;
+      S[i][j] = Acur[(size_t)(pr.x * PB + i) * np + pr.x * PB + j];
+      S[PB + i][PB + j] = Acur[(size_t)(pr.y * PB + i) * np + pr.y * PB + j];
+    }
+    for (int e = tid; e < PM * PM; e += NT) Ut[e / PM][e % PM] = (e / PM == e % PM) ? 1.0f : 0.0f;
+    __syncthreads();
+    solve_body<PB>(S, W, Ut, Acur, Anxt, np, pr, Ucur + (size_t)b * PM * PM, 1, 0, 0.0f, 0.0f,
+                   true);
+    return;
+  }
+  b -= ns;
+  if (b < na) {
+    // ---- A update of round r - 1 for pair blocks P < R
+    float(*Up)[PL] = lds[0];
+    float(*Ur)[PL] = lds[1];
+    float(*Ab)[PL] = lds[2];
+    int P = 0;
+    while (b >= nb2 - 1 - P) { b -= nb2 - 1 - P; ++P; }
+    const int R = P + 1 + b;
+    const int2 PP = pairs_p[P], RR = pairs_p[R];
+    for (int e = tid; e < PM * PM; e += NT) {
+      const int i = e / PM, j = e % PM;
+      Up[i][j] = Uprev[(size_t)P * PM * PM + e];
+      Ur[i][j] = Uprev[(size_t)R * PM * PM + e];
+      Ab[i][j] = Acur[(size_t)blk_row<PB>(PP.x, PP.y, i) * np + blk_row<PB>(RR.x, RR.y, j)];
+    }
+    __syncthreads();
+    f4 acc[2];
+    tile_mfma<PB, true>(Up, Ab, acc);
+    __syncthreads();
+    tile_store_lds<PB>(Ab, acc);
+    __syncthreads();
+    tile_mfma<PB, false>(Ab, Ur, acc);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i, j;
+        tile_rc<PB>(u, v, i, j);
+        const int X = i < PB ? PP.x : PP.y, Y = j < PB ? RR.x : RR.y;
+        if (!apply_only && (pos_r[X] >> 1) == (pos_r[Y] >> 1)) continue;  // paired in round r
+        const int gi = blk_row<PB>(PP.x, PP.y, i), gj = blk_row<PB>(RR.x, RR.y, j);
+        Anxt[(size_t)gi * np + gj] = acc[u][v];
+        Anxt[(size_t)gj * np + gi] = acc[u][v];
+      }
+    return;
+  }
+  b -= na;
+  if (b < nb2) {
+    // ---- copy of round r - 1's pair block b: its off-diagonal blocks, or all of it
+    const int2 PP = pairs_p[b];
+    for (int e = tid; e < PM * PM; e += NT) {
+      const int i = e / PM, j = e % PM;
+      if (!apply_only && ((i < PB) == (j < PB))) continue;  // diagonal blocks: the solves'
+      const size_t g = (size_t)blk_row<PB>(PP.x, PP.y, i) * np + blk_row<PB>(PP.x, PP.y, j);
+      Anxt[g] = Acur[g];
+    }
+    return;
+  }
+  b -= nb2;
+  {
+    const int R = b / nvt, rt = b - R * nvt;
+    vtile_body<PB>(lds[0], lds[1], V, nrows, np, rt * PM, pairs_p[R], Uprev + (size_t)R * PM * PM);
   }
 }
 
@@ -556,6 +708,7 @@ static size_t blocked_bytes(int n) {
   b += 2 * (nb / 2) * PM * PM * 4;                // U of every block pair of two rounds
   b += (nb - 1 > 0 ? nb - 1 : 1) * (nb / 2) * 8;  // pair table of all rounds
   b += 2 * np * 8 + 256;                          // partial sums + result
+  b += np * np * 4 + (nb - 1 > 0 ? nb - 1 : 1) * nb * 4 + 256;  // second A32, block positions
   return (b + 4095) & ~(size_t)4095;
 }
 
@@ -577,6 +730,16 @@ static bool f32_trace() {
   return on;
 }
 
+// Fused rounds (the A update of a round launched with the next round's solves); JE_F32_FUSED=0
+// launches every A update on its own.
+static bool fused_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("JE_F32_FUSED");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 template <int PB>
 static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int ldq,
                               void* scratch, int max_sweeps, double tol, double rho, int* sweeps,
@@ -589,7 +752,9 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
   float* U = (float*)p; p += 2 * (size_t)nb2 * PM * PM * 4;
   int2* pairs = (int2*)p; p += (size_t)rounds * nb2 * 8;
   double* part = (double*)p; p += 2 * (size_t)np * 8;
-  double* res = (double*)p;
+  double* res = (double*)p; p += 256;
+  float* A32b = (float*)p; p += (size_t)np * np * 4;
+  int* pos = (int*)p;
   hipError_t e;
   // circle-method block pairs of every round (block nb - 1 fixed)
   std::vector<int2> tab((size_t)rounds * nb2);
@@ -603,6 +768,17 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
   if ((e = hipMemcpyAsync(pairs, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s)) !=
       hipSuccess)
     return e;
+  // pos[r nb + X] = 2 * (pair of round r holding block X) + (X is its second block)
+  std::vector<int> ptab((size_t)rounds * nb);
+  for (int r = 0; r < rounds; ++r)
+    for (int k = 0; k < nb2; ++k) {
+      const int2 q = tab[(size_t)r * nb2 + k];
+      ptab[(size_t)r * nb + q.x] = 2 * k;
+      ptab[(size_t)r * nb + q.y] = 2 * k + 1;
+    }
+  if ((e = hipMemcpyAsync(pos, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return e;
   // the table is host memory read by an asynchronous copy: it must outlive the copy
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   {
@@ -614,9 +790,12 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
                        n, np);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  // Acur holds the current A32; fused rounds write the other buffer and swap
+  float* Acur = A32;
+  float* Anxt = A32b;
   double h[2];
   auto off_norm = [&]() -> hipError_t {
-    hipLaunchKernelGGL(k_off_norm_f32, dim3((np + 3) / 4), dim3(256), 0, s, A32, np, part);
+    hipLaunchKernelGGL(k_off_norm_f32, dim3((np + 3) / 4), dim3(256), 0, s, Acur, np, part);
     hipLaunchKernelGGL(k_off_norm_sum, dim3(1), dim3(256), 0, s, part, np, res);
     hipError_t r = hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, s);
     if (r == hipSuccess) r = hipStreamSynchronize(s);
@@ -635,22 +814,43 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
   auto round_launch = [&](int nsolve, const int2* pr, float* Uw, int full) {
     const int nv = vround >= 0 ? nvt * nb2 : 0;
     const int2* vp = vround >= 0 ? pairs + (size_t)vround * nb2 : pairs;
-    hipLaunchKernelGGL(k_block_round<PB>, dim3(nsolve + nv), dim3(NT), 0, s, A32, np, pr, Uw,
+    hipLaunchKernelGGL(k_block_round<PB>, dim3(nsolve + nv), dim3(NT), 0, s, Acur, np, pr, Uw,
                        nsolve, inner, full, (float)(tol * tol), (float)(rho * rho), V32, n, vp,
                        ubuf(g - 1), nvt);
   };
+  // Rounds 0 and 1 of a sweep are launched as solves + V update, then the A update (round
+  // 1's update is deferred); from round 2 on, each round is one fused launch that also
+  // carries the previous round's A update, and the sweep ends with that update for its
+  // last round.  A sweep swaps the buffers nb - 2 times (even), so every sweep starts from
+  // the same buffer.
+  const bool fused = fused_enabled() && nb >= 4;
+  const int na = nb2 * (nb2 - 1) / 2;
   auto sweep_launches = [&](hipStream_t st) {
     for (int r = 0; r < rounds; ++r, ++g) {
       const int2* pr = pairs + (size_t)r * nb2;
       const int nv = vround >= 0 ? nvt * nb2 : 0;
       const int2* vp = vround >= 0 ? pairs + (size_t)vround * nb2 : pairs;
-      hipLaunchKernelGGL(k_block_round<PB>, dim3(nb2 + nv), dim3(NT), 0, st, A32, np, pr, ubuf(g),
-                         nb2, inner, r == 0 ? 1 : 0, (float)(tol * tol), (float)(rho * rho), V32,
-                         n, vp, ubuf(g - 1), nvt);
-      if (nb2 > 1)
-        hipLaunchKernelGGL(k_block_apply_a<PB>, dim3(nb2 * (nb2 - 1) / 2), dim3(NT), 0, st, A32,
-                           np, pr, ubuf(g), nb2);
+      if (!fused || r < 2) {
+        hipLaunchKernelGGL(k_block_round<PB>, dim3(nb2 + nv), dim3(NT), 0, st, Acur, np, pr,
+                           ubuf(g), nb2, inner, r == 0 ? 1 : 0, (float)(tol * tol),
+                           (float)(rho * rho), V32, n, vp, ubuf(g - 1), nvt);
+        if (nb2 > 1 && !(fused && r == 1))
+          hipLaunchKernelGGL(k_block_apply_a<PB>, dim3(na), dim3(NT), 0, st, Acur, np, pr,
+                             ubuf(g), nb2);
+      } else {
+        hipLaunchKernelGGL(k_block_fused<PB>, dim3(nb2 + na + nb2 + nv), dim3(NT), 0, st, Acur,
+                           Anxt, np, nb2, pr, pos + (size_t)r * nb, pairs + (size_t)(r - 1) * nb2,
+                           pos + (size_t)(r - 1) * nb, ubuf(g - 1), ubuf(g), 0, V32, n, nvt);
+        std::swap(Acur, Anxt);
+      }
       vround = r;
+    }
+    if (fused) {
+      // the A update of the sweep's last round (its factors are ubuf(g - 1))
+      hipLaunchKernelGGL(k_block_fused<PB>, dim3(na + nb2), dim3(NT), 0, st, Acur, Anxt, np, nb2,
+                         pairs, pos, pairs + (size_t)(rounds - 1) * nb2,
+                         pos + (size_t)(rounds - 1) * nb, ubuf(g - 1), ubuf(g), 1, V32, n, nvt);
+      std::swap(Acur, Anxt);
     }
   };
   // From the second sweep on, a sweep's launches depend only on the parity of its first
@@ -676,6 +876,8 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
         }
         const long long g_save = g;
         const int v_save = vround;
+        float* const a_save = Acur;
+        float* const b_save = Anxt;
         hipGraph_t gr = nullptr;
         if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
           cleanup();
@@ -688,6 +890,8 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
         if (e != hipSuccess) { cleanup(); return e; }
         g = g_save;
         vround = v_save;
+        Acur = a_save;
+        Anxt = b_save;
       }
       if ((e = hipGraphLaunch(ex[par], s)) != hipSuccess) { cleanup(); return e; }
       g += rounds;
@@ -784,7 +988,7 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_solve_b(
   const int r = b.f_round;
   const int2 pr = block_pair(b.nb, r, k);
   const int par = (b.f_sweeps * (b.nb - 1) + r) & 1;
-  solve_body<BPB>(lds[0], lds[1], lds[2], b.A32, b.np, pr, ubuf_b(b, par) + (size_t)k * PM * PM,
+  solve_body<BPB>(lds[0], lds[1], lds[2], b.A32, b.A32, b.np, pr, ubuf_b(b, par) + (size_t)k * PM * PM,
                   b.nb == 2 ? max_inner : 1, r == 0 ? 1 : 0, tol2, rho2);
   // the solved block as written back: its upper triangle, mirrored
   for (int e = threadIdx.x; e < PM * PM; e += Blk<BPB>::NT) {
