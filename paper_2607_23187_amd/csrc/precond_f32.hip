@@ -143,6 +143,10 @@ __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (
       const float apq = S[p][q];
       const float4 x = *reinterpret_cast<const float4*>(&S[p][jb]);
       const float4 y = *reinterpret_cast<const float4*>(&S[q][jb]);
+      // rows p, q of U^T belong to this pair's lanes alone in this round: rotated here,
+      // beside the first phase, off the second phase's dependency chain
+      const float4 up = *reinterpret_cast<const float4*>(&Ut[p][jb]);
+      const float4 uq = *reinterpret_cast<const float4*>(&Ut[q][jb]);
       float c = 1.0f, s = 0.0f;
       const bool skip = apq == 0.0f || f32_noise_pair(app, aqq, apq);
       if (!skip) {
@@ -156,6 +160,15 @@ __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (
       W[jb + 1][p] = c * x.y + s * y.y; W[jb + 1][q] = c * y.y - s * x.y;
       W[jb + 2][p] = c * x.z + s * y.z; W[jb + 2][q] = c * y.z - s * x.z;
       W[jb + 3][p] = c * x.w + s * y.w; W[jb + 3][q] = c * y.w - s * x.w;
+      {
+        float4 po, qo;
+        po.x = c * up.x + s * uq.x; qo.x = c * uq.x - s * up.x;
+        po.y = c * up.y + s * uq.y; qo.y = c * uq.y - s * up.y;
+        po.z = c * up.z + s * uq.z; qo.z = c * uq.z - s * up.z;
+        po.w = c * up.w + s * uq.w; qo.w = c * uq.w - s * up.w;
+        *reinterpret_cast<float4*>(&Ut[p][jb]) = po;
+        *reinterpret_cast<float4*>(&Ut[q][jb]) = qo;
+      }
       __syncthreads();
       {
         const float4 wx = *reinterpret_cast<const float4*>(&W[p][jb]);
@@ -171,15 +184,6 @@ __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (
         }
         *reinterpret_cast<float4*>(&S[p][jb]) = make_float4(xo[0], xo[1], xo[2], xo[3]);
         *reinterpret_cast<float4*>(&S[q][jb]) = make_float4(yo[0], yo[1], yo[2], yo[3]);
-        const float4 up = *reinterpret_cast<const float4*>(&Ut[p][jb]);
-        const float4 uq = *reinterpret_cast<const float4*>(&Ut[q][jb]);
-        float4 po, qo;
-        po.x = c * up.x + s * uq.x; qo.x = c * uq.x - s * up.x;
-        po.y = c * up.y + s * uq.y; qo.y = c * uq.y - s * up.y;
-        po.z = c * up.z + s * uq.z; qo.z = c * uq.z - s * up.z;
-        po.w = c * up.w + s * uq.w; qo.w = c * uq.w - s * up.w;
-        *reinterpret_cast<float4*>(&Ut[p][jb]) = po;
-        *reinterpret_cast<float4*>(&Ut[q][jb]) = qo;
       }
       __syncthreads();
     }
