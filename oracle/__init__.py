@@ -342,7 +342,9 @@ def svd(b: np.ndarray, tol: float, pivot: int = GAP, precond: str = "none",
         for _ in range(passes - 1):
             a1 = q.T @ (g0 @ q)
             a1 = 0.5 * (a1 + a1.T)
-            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32, tol=F32_TOL2, rho=F32_RHO2)
+            # refinement without the off-norm floor: a graded B puts eigenvalues of B^T B
+            # far below 2^-30 ||B^T B||, and their vectors need the longer refinement
+            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32, tol=0.0, rho=F32_RHO2)
             sw += sw2
             q = householder_q(q @ v2.astype(np.float64))
         x = np.ascontiguousarray(q.T @ x)

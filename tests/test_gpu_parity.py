@@ -167,12 +167,13 @@ def test_full_pipeline_against_oracle(n, seed, pivot):
     assert r.stats["sweeps32"] >= 1
 
 
-@pytest.mark.parametrize("n", [48, 200, 1024, 2100])
+@pytest.mark.parametrize("n", [48, 80, 200, 1024, 2100])
 def test_preconditioner_quality(n):
     """The FP32 stage (Sec. 2.1) must leave A_hat = Q^T A Q nearly diagonal: off(A_hat) at
     the FP32 level after one pass, well below it after the refinement, and few FP64
     rotations.  Covers the single-subproblem (n <= 64), 16-row-block and 32-row-block
-    forms of the blocked FP32 Jacobi."""
+    forms of the blocked FP32 Jacobi, and the fused rounds from their smallest case (n = 80:
+    six 16-row blocks, five rounds per sweep) up."""
     p = I.config_c2(n=n) if n >= 1024 else I.clustered(n, seed=900 + n)
     lam2 = np.max(np.abs(p.lam))
     tol = 10 * n * U * lam2 / np.linalg.norm(p.a)
