@@ -995,7 +995,35 @@ hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, hipS
 
 // ------------------------------------------------------------------ J5: apply the log to V
 // Each block holds `R` rows of V in LDS, transposed (column index major) so that lane r
-// touches row r's entries p and q in consecutive banks; the log is read with scalar loads.
+// touches row r's entries p and q in consecutive banks.  The log is staged 64 entries at a
+// time, one per lane (a coalesced load), and each entry is broadcast to the wave with
+// readlane, so the rotations' LDS chain never waits on a memory load.
+__device__ __forceinline__ void apply_log_rows(double* __restrict__ tile, int R, int rows,
+                                               const RotEntry* __restrict__ log, long long m) {
+  const int lane = threadIdx.x;
+  for (long long e0 = 0; e0 < m; e0 += 64) {
+    const int cnt = (int)(m - e0 < 64 ? m - e0 : 64);
+    int lp = 0, lq = 0;
+    double lc = 1.0, ls = 0.0;
+    if (lane < cnt) {
+      const RotEntry g = log[e0 + lane];
+      lp = g.p; lq = g.q; lc = g.c; ls = g.s;
+    }
+#pragma unroll 4
+    for (int k = 0; k < cnt; ++k) {
+      const int p = __builtin_amdgcn_readlane(lp, k), q = __builtin_amdgcn_readlane(lq, k);
+      const double c = readlane_d(lc, k), s = readlane_d(ls, k);
+      if (lane < rows) {
+        double* xp = tile + p * R + lane;
+        double* xq = tile + q * R + lane;
+        const double x = *xp, y = *xq;
+        *xp = c * x + s * y;
+        *xq = c * y - s * x;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void k_apply_log(double* __restrict__ V, int n, int ldv,
                                                   const RotEntry* __restrict__ log,
                                                   long long m, int R) {
@@ -1008,16 +1036,7 @@ __global__ __launch_bounds__(64) void k_apply_log(double* __restrict__ V, int n,
     tile[j * R + r] = V[(size_t)(r0 + r) * ldv + j];
   }
   __syncthreads();
-  if (lane < rows) {
-    for (long long e = 0; e < m; ++e) {
-      const RotEntry g = log[e];
-      double* xp = tile + g.p * R + lane;
-      double* xq = tile + g.q * R + lane;
-      const double x = *xp, y = *xq;
-      *xp = g.c * x + g.s * y;
-      *xq = g.c * y - g.s * x;
-    }
-  }
+  apply_log_rows(tile, R, rows, log, m);
   __syncthreads();
   for (int idx = lane; idx < rows * n; idx += 64) {
     int r = idx / n, j = idx - r * n;
@@ -1041,7 +1060,6 @@ __global__ __launch_bounds__(64) void k_apply_log_b(BMat* __restrict__ mats) {
   if (m <= 0) return;
   double* V = b.Vw;
   const int ldv = b.ld;
-  const RotEntry* log = b.jd.log;
   const int lane = threadIdx.x;
   const int rows = min(R, n - r0);
   for (int idx = lane; idx < rows * n; idx += 64) {
@@ -1049,16 +1067,7 @@ __global__ __launch_bounds__(64) void k_apply_log_b(BMat* __restrict__ mats) {
     tile[j * R + r] = V[(size_t)(r0 + r) * ldv + j];
   }
   __syncthreads();
-  if (lane < rows) {
-    for (long long e = 0; e < m; ++e) {
-      const RotEntry g = log[e];
-      double* xp = tile + g.p * R + lane;
-      double* xq = tile + g.q * R + lane;
-      const double x = *xp, y = *xq;
-      *xp = g.c * x + g.s * y;
-      *xq = g.c * y - g.s * x;
-    }
-  }
+  apply_log_rows(tile, R, rows, b.jd.log, m);
   __syncthreads();
   for (int idx = lane; idx < rows * n; idx += 64) {
     int r = idx / n, j = idx - r * n;
