@@ -19,7 +19,10 @@
  * Q^T A Q, whose off-diagonal entries are O(||A|| u_32).  By default the FP32
  * decomposition is refined once (fp32_passes = 2): the FP32 Jacobi runs again on
  * fl32(Q^T A Q) and Q <- Q V_2, re-orthogonalised; fp32_passes = 1 is the single FP32
- * decomposition.
+ * decomposition.  FP32 sweeps stop when off(A32) <= 2^-22 ||A32||_F or a sweep does not
+ * lower it (single pass); the first of two passes stops at 2^-18; the refinement sweeps
+ * until a sweep fails to halve off or off <= 2^-30 ||A32||_F (jacobi_svd: no 2^-30 bound);
+ * every pass is capped at fp32_max_sweeps.
  *
  * Stop rule (default, Theorem 1): stop once max_{i != j} L_ij <= eps with
  *   eps = tol * ||A||_F / (2 n (n - 1)),
