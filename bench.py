@@ -27,6 +27,7 @@ U = 2.0 ** -53
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2607_23187_amd", "csrc", "jacobi_kernels.hip")
 PMC_FILE = os.path.join(ROOT, "profiles", "jacobi_kernel_c2_pmc.json")
+QUEUE_PMC_FILE = os.path.join(ROOT, "profiles", "jacobi_queue_c4_pmc.json")
 COUNTS_FILE = os.path.join(ROOT, "tests", "golden", "c2_oracle_counts.json")
 
 
@@ -95,6 +96,19 @@ def roofline(stats, n):
             "kernel_ms": ms, "us_per_rotation": ms * 1e3 / max(1, rot)}
 
 
+def queue_traffic(batch):
+    """HBM bytes of the batched solve's persistent Jacobi launches, from the FETCH_SIZE and
+    WRITE_SIZE counters in profiles/ (scaled by the reference copy), when they were taken
+    on the current kernel source and batch; else None."""
+    try:
+        pm = json.load(open(QUEUE_PMC_FILE))
+    except (OSError, ValueError):
+        return None
+    if pm.get("kernel_source_sha256_16") != kernel_hash() or pm.get("batch") != batch:
+        return None
+    return pm.get("hbm_bytes_per_batched_solve")
+
+
 def cpu_baseline(a_np, n):
     """The oracle, untuned, on a bounded sample of the same solve: one FP32 sweep, one
     Householder QR + the two products of Q^T A Q, and 20000 FP64 rotations; scaled to one
@@ -154,6 +168,16 @@ def bench_batch(args):
               for p in probs)
     sizes = np.array([p.a.shape[0] for p in probs])
     torch.cuda.synchronize()
+    if args.profile_run:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        st, res = J.eigh_batched(mats, tol=tol, pivot="gap", precond=args.precond)
+        torch.cuda.synchronize()
+        log(f"profile run: copy 268435456 B; batched solve status {st}")
+        return
 
     def run_batched():
         torch.cuda.synchronize()
@@ -218,7 +242,8 @@ def bench_batch(args):
         "roofline": {"bound": "hbm", "achieved": algo / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (algo / (kern_ms * 1e-3) / 1e9) / HBM_PEAK_GBS if kern_ms > 0 else 0.0,
-                     "traffic": None, "kernel": "k_jacobi_queue (persistent, one workgroup per matrix)",
+                     "traffic": queue_traffic(len(probs)),
+                     "kernel": "k_jacobi_queue (persistent, one workgroup per matrix)",
                      "algorithmic_bytes": algo, "kernel_ms": kern_ms},
     }
     print(json.dumps(out), flush=True)

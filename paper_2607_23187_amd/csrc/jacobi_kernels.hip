@@ -921,6 +921,16 @@ static int mirror_mode() {
   return (e && e[0] == '0') ? 0 : 1;
 }
 
+// The persistent batched launch defaults to the timestamp mode (JE_MIRROR=1 selects mirror
+// mode): with hundreds of matrices in flight the mirrored column stores, each dirtying a
+// cache line for 8 bytes, make HBM writes the larger cost (2048-matrix batch: 42 GB written
+// against 17 GB of algorithmic row traffic; kernel 61 -> 50 ms without them), while one
+// matrix alone is faster in mirror mode (5.11 vs 5.25 us per rotation at n = 1024).
+static int queue_mirror_mode() {
+  const char* e = getenv("JE_MIRROR");
+  return (e && e[0] == '1') ? 1 : 0;
+}
+
 // Threads per workgroup for the HBM-resident kernel: 512 (two waves per SIMD, 256 VGPRs
 // per lane); rows per thread RM = ceil(n / NT).
 template <bool GAP, bool MIR>
@@ -949,7 +959,8 @@ template <int NT, int RM, bool GAP, bool LDSA>
 static hipError_t launch_queue_one(BMat* m, const int* idx, int count, int nmax, int* counter,
                                    int grid, hipStream_t s) {
   size_t sh = lds_bytes(nmax, LDSA);
-  auto fn = k_jacobi_queue<NT, RM, GAP, LDSA, true>;
+  auto fn = (LDSA || queue_mirror_mode()) ? k_jacobi_queue<NT, RM, GAP, LDSA, true>
+                                          : k_jacobi_queue<NT, RM, GAP, LDSA, false>;
   if (sh > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);

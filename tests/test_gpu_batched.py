@@ -132,3 +132,24 @@ def test_tuned_shapes_do_not_change_results(monkeypatch):
         assert x.stats["rotations"] == y.stats["rotations"]
         assert torch.equal(x.w, y.w)
         assert torch.equal(x.v, y.v)
+
+
+@pytest.mark.parametrize("pivot", ["greedy", "gap"])
+def test_batched_timestamp_and_mirror_modes_agree(pivot, monkeypatch):
+    """The persistent batched launch keeps A current either by mirrored column stores
+    (JE_MIRROR=1) or by per-row write timestamps (the default): same arithmetic, so the same
+    rotation counts and bits, including across log drains (without the preconditioner the
+    520-row matrix needs more rotations than one log holds)."""
+    probs = problems([129, 200, 300, 520], 8100)
+    tol = min(tol_for(a, lam) for a, lam in probs)
+    mats = [torch.from_numpy(a).cuda() for a, _ in probs]
+    say("batched modes", pivot)
+    monkeypatch.setenv("JE_MIRROR", "1")
+    _, rm = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="none")
+    monkeypatch.delenv("JE_MIRROR")
+    _, rt = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="none")
+    for x, y in zip(rm, rt):
+        assert x.status == y.status == J.OK
+        assert x.stats["rotations"] == y.stats["rotations"]
+        assert torch.equal(x.w, y.w)
+        assert torch.equal(x.v, y.v)
