@@ -2,12 +2,14 @@
 // greedy or the gap-aware pivot score of eq. (1)), for gfx950.
 //
 // Data layout (one problem):
-//   A      row-major n x ld FP64, full symmetric storage.  A rotation (p, q) rewrites
-//          rows p and q only (two coalesced row stores), never columns p and q.  Each row
-//          carries the rotation number ts[k] that last wrote it; the current value of
-//          entry (k, l) is A[k][l] if ts[k] >= ts[l] and A[l][k] otherwise.  This trades
-//          the 2n scattered column stores of a mirrored update for a per-element choice
-//          of address on load.
+//   A      row-major n x ld FP64, full symmetric storage, kept current in one of two
+//          modes.  Mirror mode (one matrix): a rotation (p, q) stores rows p and q
+//          (coalesced) and mirrors them into columns p and q, so every load is a
+//          contiguous row segment.  Timestamp mode (batches): rows p and q only; each row
+//          carries the rotation number ts[k] that last wrote it, and the current value of
+//          entry (k, l) is A[k][l] if ts[k] >= ts[l] and A[l][k] otherwise, which trades
+//          the 2n scattered column stores for a per-element choice of address on load.
+//          Both modes perform the same arithmetic.  A LDS-resident A (small n) is mirrored.
 //   diag   the diagonal lives in LDS / registers, never in A.
 //   caches per row k: best selection score over l != k (value, column, a_kl, stale flag)
 //          and, for greedy pivoting with the Theorem 1 stop rule, the best L_kl.  A stale
