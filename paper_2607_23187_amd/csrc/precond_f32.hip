@@ -247,6 +247,17 @@ __device__ __forceinline__ void rot_block(const RotF& rb, const RotF& rc, bool d
   w = diag ? rb.naqq : rc.c * w1 - rc.s * z1;
 }
 
+// The rotation evaluated by lane `src` of this wave (cross-lane read, ds_bpermute).
+__device__ __forceinline__ RotF fetch_rot(const RotF& x, int src) {
+  RotF r;
+  r.c = __shfl(x.c, src);
+  r.s = __shfl(x.s, src);
+  r.napp = __shfl(x.napp, src);
+  r.naqq = __shfl(x.naqq, src);
+  r.z = __shfl(x.z, src);
+  return r;
+}
+
 // An inner round is one phase: the pairs of the round are disjoint, so J^T S J is, block by
 // block, X_bc -> J_b^T X_bc J_c over the 2 x 2 blocks of pair b's rows and pair c's columns.
 // Lane (kb, i) owns the blocks (kb, 2i) and (kb, 2i + 1) and columns 4i .. 4i + 3 of rows
@@ -274,6 +285,7 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
     }
     __syncthreads();
   }
+  const int lane = tid & 63;
   const int kb = tid / LB, li = tid % LB, jb = li * 4, kc = 2 * li;
   const int nr = full ? PM - 1 : PB;
   float(*Sc)[PL] = S;
@@ -289,9 +301,12 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
       float x1 = Sc[pb][p1], y1 = Sc[pb][q1], z1 = Sc[qb][p1], w1 = Sc[qb][q1];
       const float4 up = *reinterpret_cast<const float4*>(&Ut[pb][jb]);
       const float4 uq = *reinterpret_cast<const float4*>(&Ut[qb][jb]);
-      const RotF rb = pair_rot<PL>(Sc, pb, qb);
-      const RotF r0 = pair_rot<PL>(Sc, p0, q0);
-      const RotF r1 = pair_rot<PL>(Sc, p1, q1);
+      // lane l evaluates the rotation of pair l mod (PM/2) (each pair twice per wave) and
+      // every lane fetches the three it needs from those lanes (no barrier: same wave)
+      int pm, qm;
+      inner_pair<PB>(full, r, lane % (PM / 2), pm, qm);
+      const RotF mine = pair_rot<PL>(Sc, pm, qm);
+      const RotF rb = fetch_rot(mine, kb), r0 = fetch_rot(mine, kc), r1 = fetch_rot(mine, kc + 1);
       rot_block(rb, r0, kb == kc, x0, y0, z0, w0);
       rot_block(rb, r1, kb == kc + 1, x1, y1, z1, w1);
       Sn[pb][p0] = x0; Sn[pb][q0] = y0; Sn[qb][p0] = z0; Sn[qb][q0] = w0;
