@@ -216,8 +216,15 @@ int ns_step(double*& X, double*& Xalt, double* R, int n, int ld, double* part, d
   return JE_OK;
 }
 
-// Newton-Schulz steps on X until ||I - X^T X||_F <= 4 n u (at most 6); X may be swapped
-// with Xalt.
+// Newton-Schulz is done once a step starts from ||I - X^T X||_F <= 4 n u, or from a
+// residual r whose square is below n u / 2: a step leaves about (3/4) r^2 plus rounding, so
+// the step that would only confirm convergence is skipped.
+bool ns_converged(double rn, int n) {
+  const double nu = n * 0x1p-53;
+  return rn <= 4.0 * nu || rn * rn <= 0.5 * nu;
+}
+
+// Newton-Schulz steps on X until converged (at most 6); X may be swapped with Xalt.
 int orthonormalize(double*& X, double*& Xalt, double* R, int n, int ld, double* part,
                    double* scal, hipStream_t s) {
   for (int itn = 0; itn < 6; ++itn) {
@@ -225,7 +232,7 @@ int orthonormalize(double*& X, double*& Xalt, double* R, int n, int ld, double* 
     int r = ns_step(X, Xalt, R, n, ld, part, scal, &rn, s);
     if (r) return r;
     HIPCHK(hipStreamSynchronize(s));
-    if (rn <= 4.0 * n * 0x1p-53) break;
+    if (ns_converged(rn, n)) break;
   }
   return JE_OK;
 }
@@ -748,6 +755,9 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
       std::swap(offX, offXb);
       if (int r = collect()) return r;
       bool all = true;
+      // (the batch steps until every member starts a step at 4 n u: a member's step count
+      // must not depend on its batch-mates' residuals, so that a problem gives the same
+      // bits alone and in a batch)
       for (int i = 0; i < cnt; ++i) all = all && hi[i].rnorm <= 4.0 * hm[i].n * 0x1p-53;
       if (all) break;
     }
