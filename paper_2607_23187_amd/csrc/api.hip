@@ -746,19 +746,21 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   // ---- 2. preconditioner
   float ms_gemm = 0.f;
   size_t offX = BF(X), offXb = BF(Xb);
+  // Newton-Schulz on every member: a member stops stepping once it meets the single
+  // problem's rule (ns_converged); its later steps in the batch take R = 0 and leave X
+  // bit for bit, so its result does not depend on its batch-mates.
   auto orthonormalize_b = [&]() -> int {
+    HIPCHK(launch_ns_reset_b(dm, cnt, s));
     for (int itn = 0; itn < 6; ++itn) {
-      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s));
-      HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s));
+      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s, 1));
+      HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s, 1));
       HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(R), 1, s));
       HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, offX, BF(R), 1.0, offX, offXb, s));
       std::swap(offX, offXb);
+      HIPCHK(launch_ns_flag_b(dm, cnt, s));
       if (int r = collect()) return r;
       bool all = true;
-      // (the batch steps until every member starts a step at 4 n u: a member's step count
-      // must not depend on its batch-mates' residuals, so that a problem gives the same
-      // bits alone and in a batch)
-      for (int i = 0; i < cnt; ++i) all = all && hi[i].rnorm <= 4.0 * hm[i].n * 0x1p-53;
+      for (int i = 0; i < cnt; ++i) all = all && ns_converged(hi[i].rnorm, hm[i].n);
       if (all) break;
     }
     return JE_OK;

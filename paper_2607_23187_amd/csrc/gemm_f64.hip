@@ -124,7 +124,8 @@ constexpr int kXcds = 8;
 template <int TRANSA>
 __global__ __launch_bounds__(256) void k_dgemm_b(BMat* __restrict__ mats, int count, int nb,
                                                  double alpha, size_t offA, size_t offB,
-                                                 double beta, size_t offCin, size_t offC) {
+                                                 double beta, size_t offCin, size_t offC,
+                                                 int ns_mask) {
   const int L = blockIdx.x, xcd = L % kXcds, slot = L / kXcds, T = nb * nb;
   const int z = xcd + kXcds * (slot / T), t = slot % T;
   if (z >= count) return;
@@ -132,35 +133,71 @@ __global__ __launch_bounds__(256) void k_dgemm_b(BMat* __restrict__ mats, int co
   const int n = b.n;
   const int by = t / nb, bx = t % nb;
   if (by * GB >= n || bx * GB >= n) return;
+  if (ns_mask && b.ns_done) {  // converged member: C = 0 (its update then leaves X as is)
+    double* C = bm_ptr(b, offC);
+    for (int e = threadIdx.x; e < GB * GB; e += 256) {
+      const int i = by * GB + e / GB, j = bx * GB + e % GB;
+      if (i < n && j < n) C[(size_t)i * b.ld + j] = 0.0;
+    }
+    return;
+  }
   dgemm_tile<TRANSA>(n, alpha, bm_ptr(b, offA), b.ld, bm_ptr(b, offB), b.ld, beta,
                      beta != 0.0 ? bm_ptr(b, offCin) : nullptr, b.ld, bm_ptr(b, offC), b.ld,
                      by, bx);
 }
 
 hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
-                          size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s) {
+                          size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s,
+                          int ns_mask) {
   const int nb = (nmax + GB - 1) / GB;
   const long long blocks = (long long)kXcds * ((count + kXcds - 1) / kXcds) * nb * nb;
   dim3 g((unsigned)blocks), bl(256);
   if (transA)
     hipLaunchKernelGGL(k_dgemm_b<1>, g, bl, 0, s, m, count, nb, alpha, offA, offB, beta, offCin,
-                       offC);
+                       offC, ns_mask);
   else
     hipLaunchKernelGGL(k_dgemm_b<0>, g, bl, 0, s, m, count, nb, alpha, offA, offB, beta, offCin,
-                       offC);
+                       offC, ns_mask);
   return hipGetLastError();
 }
 
-__global__ void k_add_identity_b(BMat* __restrict__ mats, size_t off, double scale) {
+__global__ void k_add_identity_b(BMat* __restrict__ mats, size_t off, double scale,
+                                 int ns_mask) {
   BMat& b = mats[blockIdx.y];
+  if (ns_mask && b.ns_done) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < b.n) bm_ptr(b, off)[(size_t)i * b.ld + i] += scale;
 }
 
 hipError_t launch_add_identity_b(BMat* m, int count, int nmax, size_t off, double scale,
-                                 hipStream_t s) {
+                                 hipStream_t s, int ns_mask) {
   hipLaunchKernelGGL(k_add_identity_b, dim3((nmax + 255) / 256, count), dim3(256), 0, s, m, off,
-                     scale);
+                     scale, ns_mask);
+  return hipGetLastError();
+}
+
+__global__ void k_ns_reset_b(BMat* __restrict__ mats, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) mats[i].ns_done = 0;
+}
+
+// Convergence rule of a Newton-Schulz step that started from residual r (the same rule as
+// a single problem's): r <= 4 n u, or r^2 <= n u / 2 (the step left about (3/4) r^2).
+__global__ void k_ns_flag_b(BMat* __restrict__ mats, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  BMat& b = mats[i];
+  const double r = b.scal[1], nu = b.n * 0x1p-53;
+  if (r <= 4.0 * nu || r * r <= 0.5 * nu) b.ns_done = 1;
+}
+
+hipError_t launch_ns_reset_b(BMat* m, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_ns_reset_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_flag_b(BMat* m, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_ns_flag_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count);
   return hipGetLastError();
 }
 

@@ -115,6 +115,8 @@ struct BMat {
   JDesc jd;
   long long log_base;
   int j_done;
+  // Newton-Schulz: set once the member has converged; its later steps are exact no-ops
+  int ns_done;
 };
 
 // Per-matrix results gathered into one array, so the host reads a batch with one copy.
@@ -145,10 +147,16 @@ hipError_t launch_jacobi_queue(BMat* m, const int* idx, int count, int nmax, int
                                hipStream_t s);
 hipError_t launch_apply_log_b(BMat* m, int count, int nmax, hipStream_t s);
 hipError_t launch_sort_output_b(BMat* m, int count, int nmax, hipStream_t s);
+// ns_mask: members with ns_done get C = 0 (no product), resp. no identity added
 hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
-                          size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s);
+                          size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s,
+                          int ns_mask = 0);
 hipError_t launch_add_identity_b(BMat* m, int count, int nmax, size_t off, double scale,
-                                 hipStream_t s);
+                                 hipStream_t s, int ns_mask = 0);
+// Newton-Schulz bookkeeping of a batch: clear every ns_done, or set it for the members whose
+// residual of this step (scal[1]) meets the convergence rule
+hipError_t launch_ns_reset_b(BMat* m, int count, hipStream_t s);
+hipError_t launch_ns_flag_b(BMat* m, int count, hipStream_t s);
 hipError_t launch_symmetrize_b(BMat* m, int count, int nmax, size_t off, hipStream_t s);
 // FP32 stage of a batch: fl32 of the matrix at `off` (padded), V32 = I, sweeps with the
 // given stop rule until every matrix is done (each at its own pace, at most max_sweeps);
