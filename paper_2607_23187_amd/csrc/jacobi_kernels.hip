@@ -385,9 +385,50 @@ __device__ __forceinline__ Cand read_cand(const Cand& x, int w, bool with_u) {
 // Wave-uniform argmax of three candidates at once (independent chains interleave).  For b
 // and c the result's u bounds every value but the winner's: the winning lane offers its
 // second value, the others their best.
+// Winner lane of one argmax given its key maximum m (the second half of wave_argmax_lane).
+__device__ __forceinline__ int argmax_finish(double score, int key, int k32, int m) {
+  if (m < 0) return -1;
+  unsigned long long b = __ballot(k32 == m);
+  int w = __ffsll((long long)b) - 1;
+  b &= b - 1;
+  if (b) {
+    double bs = readlane_d(score, w);
+    int bk = __builtin_amdgcn_readlane(key, w);
+    while (b) {
+      int l = __ffsll((long long)b) - 1;
+      b &= b - 1;
+      double x = readlane_d(score, l);
+      int kx = __builtin_amdgcn_readlane(key, l);
+      if (x > bs || (x == bs && kx < bk)) { bs = x; bk = kx; w = l; }
+    }
+  }
+  return w;
+}
+
+// Three wave_argmax_lane at once: the three key butterflies are interleaved so that the
+// DPP wait states of one chain are filled by the others.
+__device__ __forceinline__ void wave_argmax_lane3(double sa, int ka, double sb, int kb, double sc,
+                                                  int kc, int& la, int& lb, int& lc) {
+  const int a = key32(sa), b = key32(sb), c = key32(sc);
+  int ma = a, mb = b, mc = c;
+  ma = max(ma, dpp_i<0xB1>(ma)); mb = max(mb, dpp_i<0xB1>(mb)); mc = max(mc, dpp_i<0xB1>(mc));
+  ma = max(ma, dpp_i<0x4E>(ma)); mb = max(mb, dpp_i<0x4E>(mb)); mc = max(mc, dpp_i<0x4E>(mc));
+  ma = max(ma, dpp_i<0x141>(ma)); mb = max(mb, dpp_i<0x141>(mb)); mc = max(mc, dpp_i<0x141>(mc));
+  ma = max(ma, dpp_i<0x140>(ma)); mb = max(mb, dpp_i<0x140>(mb)); mc = max(mc, dpp_i<0x140>(mc));
+  auto rows = [](int m) {
+    const int r0 = __builtin_amdgcn_readlane(m, 0), r1 = __builtin_amdgcn_readlane(m, 16);
+    const int r2 = __builtin_amdgcn_readlane(m, 32), r3 = __builtin_amdgcn_readlane(m, 48);
+    return max(max(r0, r1), max(r2, r3));
+  };
+  const int Ma = rows(ma), Mb = rows(mb), Mc = rows(mc);
+  la = argmax_finish(sa, ka, a, Ma);
+  lb = argmax_finish(sb, kb, b, Mb);
+  lc = argmax_finish(sc, kc, c, Mc);
+}
+
 __device__ __forceinline__ void wave_best3(Cand& a, int ka, Cand& b, int kb, Cand& c, int kc) {
-  const int la = wave_argmax_lane(a.s, ka), lb = wave_argmax_lane(b.s, kb),
-            lc = wave_argmax_lane(c.s, kc);
+  int la, lb, lc;
+  wave_argmax_lane3(a.s, ka, b.s, kb, c.s, kc, la, lb, lc);
   const int lane = lane_id();
   const double ub = wave_max_ub(lane == lb ? b.u : b.s);
   const double uc = wave_max_ub(lane == lc ? c.u : c.s);
