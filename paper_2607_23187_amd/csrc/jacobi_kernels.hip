@@ -430,8 +430,18 @@ __device__ __forceinline__ void wave_best3(Cand& a, int ka, Cand& b, int kb, Can
   int la, lb, lc;
   wave_argmax_lane3(a.s, ka, b.s, kb, c.s, kc, la, lb, lc);
   const int lane = lane_id();
-  const double ub = wave_max_ub(lane == lb ? b.u : b.s);
-  const double uc = wave_max_ub(lane == lc ? c.u : c.s);
+  // bounds of b and c (wave_max_ub of each, the two butterflies interleaved)
+  int mb = key32(lane == lb ? b.u : b.s), mc = key32(lane == lc ? c.u : c.s);
+  mb = max(mb, dpp_i<0xB1>(mb)); mc = max(mc, dpp_i<0xB1>(mc));
+  mb = max(mb, dpp_i<0x4E>(mb)); mc = max(mc, dpp_i<0x4E>(mc));
+  mb = max(mb, dpp_i<0x141>(mb)); mc = max(mc, dpp_i<0x141>(mc));
+  mb = max(mb, dpp_i<0x140>(mb)); mc = max(mc, dpp_i<0x140>(mc));
+  auto ub_of = [](int m) {
+    const int r = max(max(__builtin_amdgcn_readlane(m, 0), __builtin_amdgcn_readlane(m, 16)),
+                      max(__builtin_amdgcn_readlane(m, 32), __builtin_amdgcn_readlane(m, 48)));
+    return r < 0 ? -1.0 : (double)__int_as_float(r) * (1.0 + 0x1p-22);
+  };
+  const double ub = ub_of(mb), uc = ub_of(mc);
   a = read_cand(a, la, false);
   b = read_cand(b, lb, false);
   c = read_cand(c, lc, false);
