@@ -340,6 +340,46 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sec41(args):
+    """Sec. 4.1 on the GPU: n = 1000, eigenvalues 1 + exp(-alpha k) (a cluster near 1 for
+    alpha = 1) next to 2 + (k - 1)/(h - 1), k = 1..h, alpha in {1, 0.01}; gap-aware against
+    greedy pivots to the same Theorem 1 certificate, with the paper's single low-precision
+    decomposition (fp32_passes = 1) and with the refined one (2).  Reports rotations, time
+    and the eigenvalue error against the construction spectrum."""
+    import numpy as np
+    import torch
+
+    from paper_2607_23187_amd import inputs as I
+    from paper_2607_23187_amd import jacobi as J
+
+    J.load()
+    n = args.n_sec41
+    out = {}
+    for alpha in (1.0, 0.01):
+        p = I.sec41(n=n, alpha=alpha)
+        a = torch.from_numpy(p.a).to("cuda:0")
+        lam2 = float(np.max(np.abs(p.lam)))
+        tol = 10 * n * U * lam2 / float(np.linalg.norm(p.a))
+        for passes in (1, 2):
+            for pivot in ("gap", "greedy"):
+                J.eigh(a, tol=tol, pivot=pivot, precond="fp32", fp32_passes=passes)  # warmup
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = J.eigh(a, tol=tol, pivot=pivot, precond="fp32", fp32_passes=passes)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t) * 1e3
+                w = r.w.cpu().numpy()
+                err = float(np.max(np.abs(w - p.lam))) / (n * U * lam2)
+                key = f"alpha={alpha:g} passes={passes} {pivot}"
+                out[key] = {"ms": ms, "rotations": int(r.stats["rotations"]),
+                            "eig_err_over_n_u_norm2": err, "fp64_accurate": bool(err <= 10),
+                            "total_relative_error": float(np.sum(np.abs(w - p.lam)) / lam2)}
+                log(f"{key}: {ms:.1f} ms, {r.stats['rotations']} rotations")
+    print(json.dumps({"workload": f"Sec. 4.1: n={n}, 1+exp(-alpha k) cluster next to "
+                                  "2+(k-1)/(h-1), FP32 preconditioner, Theorem 1 stop",
+                      "n": n, "variants": out}), flush=True)
+
+
 def bench_precision(args):
     """Precision variant of the contraction (n = 4096, clusters of 8 with offsets 1e-10):
     Q^T A Q from FP64 MFMA products against three-slice BF16 products with FP32
@@ -469,7 +509,9 @@ def main():
                     help="for counter runs: one device copy of 256 MiB (a reference kernel of "
                          "known traffic) followed by one solve, no timing output")
     ap.add_argument("--n-precision", type=int, default=4096)
-    ap.add_argument("--workload", choices=("single", "batch", "serve", "precision", "svd"),
+    ap.add_argument("--n-sec41", type=int, default=1000)
+    ap.add_argument("--workload", choices=("single", "batch", "serve", "precision", "svd",
+                                           "sec41"),
                     default="single",
                     help="single: the n=1024 headline workload; batch: 2048 uneven matrices; "
                          "serve: a Poisson request stream through the library's server")
@@ -499,6 +541,9 @@ def main():
         return
     if args.workload == "svd":
         bench_svd(args)
+        return
+    if args.workload == "sec41":
+        bench_sec41(args)
         return
 
     import numpy as np
