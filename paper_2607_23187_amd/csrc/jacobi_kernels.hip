@@ -538,33 +538,31 @@ __device__ __forceinline__ double reduce_sum_slot(const Slots<NW>& S, int b, int
 __device__ __forceinline__ void refresh_entry(double& bs, int& ba, double& bv, double& bu,
                                               int& bst, int p, int q, double sp, double xp,
                                               double sq, double xq) {
-  const bool qb = sq > sp;
-  const double v = qb ? sq : sp, a = qb ? xq : xp, o = qb ? sp : sq;
-  const int col = qb ? q : p;
-  // fresh row whose best column moved: exact when above the bound of the other entries
   const bool hit = (ba == p) || (ba == q);
-  const bool up = v > bu;
-  // fresh row, best column untouched: insert (sp, p) then (sq, q)
-  const bool b1 = better(sp, p, bs, ba);
-  const double bs1 = b1 ? sp : bs, bv1 = b1 ? xp : bv, bu1 = fmax(bu, b1 ? bs : sp);
-  const int ba1 = b1 ? p : ba;
-  const bool b2 = better(sq, q, bs1, ba1);
-  const double bs2 = b2 ? sq : bs1, bv2 = b2 ? xq : bv1, bu2 = fmax(bu1, b2 ? bs1 : sq);
-  const int ba2 = b2 ? q : ba1;
-  // stale row: exact again when strictly above its bound
-  const bool sup = v > bs;
-  double nbs, nbv, nbu;
-  int nba, nst;
-  if (bst) {
-    nbs = sup ? v : bs; nbv = sup ? a : bv; nbu = sup ? fmax(bs, o) : bu; nba = sup ? col : ba;
-    nst = sup ? 0 : 1;
-  } else if (hit) {
-    nbs = up ? v : bu; nbv = up ? a : bv; nbu = up ? fmax(bu, o) : bu; nba = up ? col : ba;
-    nst = up ? 0 : 1;
+  if (__builtin_expect(bst || hit, 0)) {
+    // stale row (bs bounds all its scores) or fresh row whose best column moved (bu bounds
+    // the others): exact again when the larger new score is strictly above that bound
+    const bool qb = sq > sp;
+    const double v = qb ? sq : sp, a = qb ? xq : xp, o = qb ? sp : sq;
+    const int col = qb ? q : p;
+    const double bound = bst ? bs : bu;
+    const bool up = v > bound;
+    bs = up ? v : bound;
+    bv = up ? a : bv;
+    bu = up ? fmax(bound, o) : bu;
+    ba = up ? col : ba;
+    bst = up ? 0 : 1;
   } else {
-    nbs = bs2; nbv = bv2; nbu = bu2; nba = ba2; nst = 0;
+    // fresh row, best column untouched: insert (sp, p) then (sq, q)
+    const bool b1 = better(sp, p, bs, ba);
+    const double bs1 = b1 ? sp : bs, bv1 = b1 ? xp : bv, bu1 = fmax(bu, b1 ? bs : sp);
+    const int ba1 = b1 ? p : ba;
+    const bool b2 = better(sq, q, bs1, ba1);
+    bs = b2 ? sq : bs1;
+    bv = b2 ? xq : bv1;
+    bu = fmax(bu1, b2 ? bs1 : sq);
+    ba = b2 ? q : ba1;
   }
-  bs = nbs; bv = nbv; bu = nbu; ba = nba; bst = nst;
 }
 
 // Per-thread top two of the new row p (or q): best (score, column, value), second value.
