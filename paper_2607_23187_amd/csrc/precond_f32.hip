@@ -468,10 +468,14 @@ __device__ __forceinline__ void vtile_body(float (*Ur)[Blk<PB>::PL], float (*Vb)
                                            int2 pr, const float* __restrict__ Uh) {
   constexpr int PM = Blk<PB>::PM, RT = Blk<PB>::NT;
   const int tid = threadIdx.x;
-  for (int e = tid; e < PM * PM; e += RT) {
-    int i = e / PM, j = e % PM;
-    Ur[i][j] = Uh[e];
-    Vb[i][j] = (r0 + i < nrows) ? V[(size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j)] : 0.0f;
+  // four consecutive columns per lane (they lie in one block: PB is a multiple of 4)
+  for (int e = tid; e < PM * PM / 4; e += RT) {
+    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+    *reinterpret_cast<float4*>(&Ur[i][j]) = *reinterpret_cast<const float4*>(Uh + i * PM + j);
+    *reinterpret_cast<float4*>(&Vb[i][j]) =
+        (r0 + i < nrows)
+            ? *reinterpret_cast<const float4*>(V + (size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j))
+            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
   __syncthreads();
   f4 acc[2];
@@ -1039,11 +1043,13 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
   const float* Uh = ubuf_b(bm, par) + (size_t)R * PM * PM;
   float* A = bm.A32;
   const int np = bm.np, tid = threadIdx.x;
-  for (int e = tid; e < PM * PM; e += NT) {
-    int i = e / PM, j = e % PM;
-    Up[i][j] = Ug[e];
-    Ur[i][j] = Uh[e];
-    Ab[i][j] = A[(size_t)blk_row<BPB>(pp.x, pp.y, i) * np + blk_row<BPB>(pr.x, pr.y, j)];
+  // four consecutive columns per lane (they lie in one block: BPB is a multiple of 4)
+  for (int e = tid; e < PM * PM / 4; e += NT) {
+    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+    *reinterpret_cast<float4*>(&Up[i][j]) = *reinterpret_cast<const float4*>(Ug + i * PM + j);
+    *reinterpret_cast<float4*>(&Ur[i][j]) = *reinterpret_cast<const float4*>(Uh + i * PM + j);
+    *reinterpret_cast<float4*>(&Ab[i][j]) = *reinterpret_cast<const float4*>(
+        A + (size_t)blk_row<BPB>(pp.x, pp.y, i) * np + blk_row<BPB>(pr.x, pr.y, j));
   }
   __syncthreads();
   f4 acc[2];
@@ -1052,19 +1058,28 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
   tile_store_lds<BPB>(Ab, acc);
   __syncthreads();
   tile_mfma<BPB, false>(Ab, Ur, acc);
+  __syncthreads();
+  // the new block A_PR by rows in Up and transposed (A_RP by rows) in Ab, so that both are
+  // stored four consecutive columns per lane
+  tile_store_lds<BPB>(Up, acc);
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int i, j;
       tile_rc<BPB>(u, v, i, j);
-      const int gi = blk_row<BPB>(pp.x, pp.y, i), gj = blk_row<BPB>(pr.x, pr.y, j);
-      A[(size_t)gi * np + gj] = acc[u][v];
-      A[(size_t)gj * np + gi] = acc[u][v];
+      Ab[j][i] = acc[u][v];
     }
   __syncthreads();
-  tile_store_lds<BPB>(Up, acc);
-  __syncthreads();
+  for (int e = tid; e < PM * PM / 4; e += NT) {
+    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+    *reinterpret_cast<float4*>(A + (size_t)blk_row<BPB>(pp.x, pp.y, i) * np +
+                               blk_row<BPB>(pr.x, pr.y, j)) =
+        *reinterpret_cast<const float4*>(&Up[i][j]);
+    *reinterpret_cast<float4*>(A + (size_t)blk_row<BPB>(pr.x, pr.y, i) * np +
+                               blk_row<BPB>(pp.x, pp.y, j)) =
+        *reinterpret_cast<const float4*>(&Ab[i][j]);
+  }
   tile_sq<BPB>(Up, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
 }
 
