@@ -49,6 +49,62 @@ __device__ __forceinline__ int blk_row(int I, int J, int i) {
   return i < PB ? I * PB + i : J * PB + (i - PB);
 }
 
+// LDS staging of PM x PM operands, four consecutive columns per lane (16-byte accesses;
+// PB is a multiple of 4, so the four never straddle two blocks).  Block (rows of pair rp,
+// columns of pair cp) of a padded np x np matrix:
+template <int PB>
+__device__ __forceinline__ void load_pair_block(float (*T)[Blk<PB>::PL],
+                                                const float* __restrict__ A, int np, int2 rp,
+                                                int2 cp) {
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
+  for (int e = threadIdx.x; e < PM * PM / 4; e += NT) {
+    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+    *reinterpret_cast<float4*>(&T[i][j]) = *reinterpret_cast<const float4*>(
+        A + (size_t)blk_row<PB>(rp.x, rp.y, i) * np + blk_row<PB>(cp.x, cp.y, j));
+  }
+}
+
+// a row-major PM x PM factor:
+template <int PB>
+__device__ __forceinline__ void load_factor(float (*T)[Blk<PB>::PL], const float* __restrict__ U) {
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
+  for (int e = threadIdx.x; e < PM * PM / 4; e += NT) {
+    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+    *reinterpret_cast<float4*>(&T[i][j]) = *reinterpret_cast<const float4*>(U + i * PM + j);
+  }
+}
+
+// the identity:
+template <int PB>
+__device__ __forceinline__ void set_identity(float (*T)[Blk<PB>::PL]) {
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
+  for (int e = threadIdx.x; e < PM * PM / 4; e += NT) {
+    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+    *reinterpret_cast<float4*>(&T[i][j]) = make_float4(i == j ? 1.0f : 0.0f, i == j + 1 ? 1.0f : 0.0f,
+                                                       i == j + 2 ? 1.0f : 0.0f, i == j + 3 ? 1.0f : 0.0f);
+  }
+}
+
+// Write-back of a solved subproblem: U (row-major PM x PM) = Ut^T, and the block pair of
+// A from the upper triangle of S, mirrored.
+template <int PB>
+__device__ __forceinline__ void store_solved(const float (*S)[Blk<PB>::PL],
+                                             const float (*Ut)[Blk<PB>::PL],
+                                             float* __restrict__ Uo, float* __restrict__ Aout,
+                                             int np, int2 pr) {
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
+  for (int e = threadIdx.x; e < PM * PM / 4; e += NT) {
+    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+    const float4 u = make_float4(Ut[j][i], Ut[j + 1][i], Ut[j + 2][i], Ut[j + 3][i]);
+    const float4 v = make_float4(i <= j ? S[i][j] : S[j][i], i <= j + 1 ? S[i][j + 1] : S[j + 1][i],
+                                 i <= j + 2 ? S[i][j + 2] : S[j + 2][i],
+                                 i <= j + 3 ? S[i][j + 3] : S[j + 3][i]);
+    *reinterpret_cast<float4*>(Uo + i * PM + j) = u;
+    *reinterpret_cast<float4*>(Aout + (size_t)blk_row<PB>(pr.x, pr.y, i) * np +
+                               blk_row<PB>(pr.x, pr.y, j)) = v;
+  }
+}
+
 // One workgroup per block pair: Jacobi on the PM x PM subproblem in LDS.  The solved block
 // goes back into A (upper triangle, mirrored, so A stays exactly symmetric) and its
 // orthogonal factor U = product of the rotations into U.  Every rotation ends like the
@@ -123,11 +179,8 @@ __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (
   __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
   if (!preloaded) {
-    for (int e = tid; e < PM * PM; e += NT) {
-      int i = e / PM, j = e % PM;
-      S[i][j] = Ain[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
-      Ut[i][j] = (i == j) ? 1.0f : 0.0f;
-    }
+    load_pair_block<PB>(S, Ain, np, pr, pr);
+    set_identity<PB>(Ut);
     __syncthreads();
   }
   // pair kb, columns jb .. jb+3 (the LB lanes of a pair share one wave)
@@ -205,12 +258,7 @@ __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (
       prev_off = off;
     }
   }
-  for (int e = tid; e < PM * PM; e += NT) {
-    int i = e / PM, j = e % PM;
-    Uo[e] = Ut[j][i];
-    float v = (i <= j) ? S[i][j] : S[j][i];
-    Aout[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
-  }
+  store_solved<PB>(S, Ut, Uo, Aout, np, pr);
 }
 
 // Rotation of one pair of an inner round, from the current subproblem: cosine, sine, the
@@ -278,11 +326,8 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
   __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
   if (!preloaded) {
-    for (int e = tid; e < PM * PM; e += NT) {
-      int i = e / PM, j = e % PM;
-      S[i][j] = Ain[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)];
-      Ut[i][j] = (i == j) ? 1.0f : 0.0f;
-    }
+    load_pair_block<PB>(S, Ain, np, pr, pr);
+    set_identity<PB>(Ut);
     __syncthreads();
   }
   const int lane = tid & 63;
@@ -348,12 +393,7 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
     }
     __syncthreads();
   }
-  for (int e = tid; e < PM * PM; e += NT) {
-    int i = e / PM, j = e % PM;
-    Uo[e] = Ut[j][i];
-    float v = (i <= j) ? S[i][j] : S[j][i];
-    Aout[(size_t)blk_row<PB>(pr.x, pr.y, i) * np + blk_row<PB>(pr.x, pr.y, j)] = v;
-  }
+  store_solved<PB>(S, Ut, Uo, Aout, np, pr);
 }
 
 template <int PB>
@@ -561,18 +601,15 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_block_fused(
     const int2 PP = pairs_p[P], RR = pairs_p[R];
     const float* UP = Uprev + (size_t)P * PM * PM;
     const float* UR = Uprev + (size_t)R * PM * PM;
-    for (int e = tid; e < PM * PM; e += NT) {
-      const int i = e / PM, j = e % PM;
-      W[i][j] = Acur[(size_t)blk_row<PB>(PP.x, PP.y, i) * np + blk_row<PB>(RR.x, RR.y, j)];
-      Ut[i][j] = UR[e];
-    }
+    load_pair_block<PB>(W, Acur, np, PP, RR);
+    load_factor<PB>(Ut, UR);
     __syncthreads();
     // T = A_PR U_R(:, hJ): PM x PB, one 16 x 16 tile per wave
     const f4 t = mfma_tile<PL, false>(W, 0, Ut, hJ * PB, PM, w / TB, w % TB);
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) S[16 * (w / TB) + 4 * (l >> 4) + v][16 * (w % TB) + (l & 15)] = t[v];
-    for (int e = tid; e < PM * PM; e += NT) W[e / PM][e % PM] = UP[e];
+    load_factor<PB>(W, UP);
     __syncthreads();
     // X = U_P(:, hI)^T T: PB x PB, tiles on the first TB^2 waves
     f4 x = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -586,12 +623,14 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_block_fused(
         S[PB + j][i] = x[v];
       }
     }
-    for (int e = tid; e < PB * PB; e += NT) {
-      const int i = e / PB, j = e % PB;
-      S[i][j] = Acur[(size_t)(pr.x * PB + i) * np + pr.x * PB + j];
-      S[PB + i][PB + j] = Acur[(size_t)(pr.y * PB + i) * np + pr.y * PB + j];
+    for (int e = tid; e < PB * PB / 4; e += NT) {
+      const int i = e / (PB / 4), j = (e % (PB / 4)) * 4;
+      *reinterpret_cast<float4*>(&S[i][j]) =
+          *reinterpret_cast<const float4*>(Acur + (size_t)(pr.x * PB + i) * np + pr.x * PB + j);
+      *reinterpret_cast<float4*>(&S[PB + i][PB + j]) =
+          *reinterpret_cast<const float4*>(Acur + (size_t)(pr.y * PB + i) * np + pr.y * PB + j);
     }
-    for (int e = tid; e < PM * PM; e += NT) Ut[e / PM][e % PM] = (e / PM == e % PM) ? 1.0f : 0.0f;
+    set_identity<PB>(Ut);
     __syncthreads();
     solve_body<PB>(S, W, Ut, Acur, Anxt, np, pr, Ucur + (size_t)b * PM * PM, 1, 0, 0.0f, 0.0f,
                    true);
@@ -607,12 +646,9 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_block_fused(
     while (b >= nb2 - 1 - P) { b -= nb2 - 1 - P; ++P; }
     const int R = P + 1 + b;
     const int2 PP = pairs_p[P], RR = pairs_p[R];
-    for (int e = tid; e < PM * PM; e += NT) {
-      const int i = e / PM, j = e % PM;
-      Up[i][j] = Uprev[(size_t)P * PM * PM + e];
-      Ur[i][j] = Uprev[(size_t)R * PM * PM + e];
-      Ab[i][j] = Acur[(size_t)blk_row<PB>(PP.x, PP.y, i) * np + blk_row<PB>(RR.x, RR.y, j)];
-    }
+    load_factor<PB>(Up, Uprev + (size_t)P * PM * PM);
+    load_factor<PB>(Ur, Uprev + (size_t)R * PM * PM);
+    load_pair_block<PB>(Ab, Acur, np, PP, RR);
     __syncthreads();
     f4 acc[2];
     tile_mfma<PB, true>(Up, Ab, acc);
@@ -620,29 +656,46 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_block_fused(
     tile_store_lds<PB>(Ab, acc);
     __syncthreads();
     tile_mfma<PB, false>(Ab, Ur, acc);
+    __syncthreads();
+    // the new block by rows in Up and transposed in Ab: both orientations are stored four
+    // consecutive columns per lane
+    tile_store_lds<PB>(Up, acc);
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int i, j;
         tile_rc<PB>(u, v, i, j);
-        const int X = i < PB ? PP.x : PP.y, Y = j < PB ? RR.x : RR.y;
-        if (!apply_only && (pos_r[X] >> 1) == (pos_r[Y] >> 1)) continue;  // paired in round r
-        const int gi = blk_row<PB>(PP.x, PP.y, i), gj = blk_row<PB>(RR.x, RR.y, j);
-        Anxt[(size_t)gi * np + gj] = acc[u][v];
-        Anxt[(size_t)gj * np + gi] = acc[u][v];
+        Ab[j][i] = acc[u][v];
       }
+    __syncthreads();
+    for (int e = tid; e < PM * PM / 4; e += NT) {
+      const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+      const int X = i < PB ? PP.x : PP.y, Y = j < PB ? RR.x : RR.y;
+      if (!apply_only && (pos_r[X] >> 1) == (pos_r[Y] >> 1)) continue;  // paired in round r
+      *reinterpret_cast<float4*>(Anxt + (size_t)blk_row<PB>(PP.x, PP.y, i) * np +
+                                 blk_row<PB>(RR.x, RR.y, j)) =
+          *reinterpret_cast<const float4*>(&Up[i][j]);
+    }
+    for (int e = tid; e < PM * PM / 4; e += NT) {
+      const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;  // row i of A_RP, columns j..j+3
+      const int X = j < PB ? PP.x : PP.y, Y = i < PB ? RR.x : RR.y;
+      if (!apply_only && (pos_r[X] >> 1) == (pos_r[Y] >> 1)) continue;
+      *reinterpret_cast<float4*>(Anxt + (size_t)blk_row<PB>(RR.x, RR.y, i) * np +
+                                 blk_row<PB>(PP.x, PP.y, j)) =
+          *reinterpret_cast<const float4*>(&Ab[i][j]);
+    }
     return;
   }
   b -= na;
   if (b < nb2) {
     // ---- copy of round r - 1's pair block b: its off-diagonal blocks, or all of it
     const int2 PP = pairs_p[b];
-    for (int e = tid; e < PM * PM; e += NT) {
-      const int i = e / PM, j = e % PM;
+    for (int e = tid; e < PM * PM / 4; e += NT) {
+      const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
       if (!apply_only && ((i < PB) == (j < PB))) continue;  // diagonal blocks: the solves'
       const size_t g = (size_t)blk_row<PB>(PP.x, PP.y, i) * np + blk_row<PB>(PP.x, PP.y, j);
-      Anxt[g] = Acur[g];
+      *reinterpret_cast<float4*>(Anxt + g) = *reinterpret_cast<const float4*>(Acur + g);
     }
     return;
   }
