@@ -502,7 +502,7 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_block_apply_a(float* __restrict
 
 // V <- V U_R on the columns of block pair R, for the tile of PM rows from r0 (RT threads,
 // two 16 x 16 output tiles per wave on the matrix cores).
-template <int PB>
+template <int PB, bool STAGED = false>
 __device__ __forceinline__ void vtile_body(float (*Ur)[Blk<PB>::PL], float (*Vb)[Blk<PB>::PL],
                                            float* __restrict__ V, int nrows, int np, int r0,
                                            int2 pr, const float* __restrict__ Uh) {
@@ -520,14 +520,29 @@ __device__ __forceinline__ void vtile_body(float (*Ur)[Blk<PB>::PL], float (*Vb)
   __syncthreads();
   f4 acc[2];
   tile_mfma<PB, false>(Vb, Ur, acc);
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      int i, j;
-      tile_rc<PB>(u, v, i, j);
-      if (r0 + i < nrows) V[(size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j)] = acc[u][v];
+  if constexpr (STAGED) {
+    // through LDS, so that rows are stored four consecutive columns per lane (measured
+    // faster for the batched steps, 165 -> 152 us, and not for the fused rounds, where the
+    // two extra barriers cost more)
+    __syncthreads();
+    tile_store_lds<PB>(Vb, acc);
+    __syncthreads();
+    for (int e = tid; e < PM * PM / 4; e += RT) {
+      const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
+      if (r0 + i < nrows)
+        *reinterpret_cast<float4*>(V + (size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j)) =
+            *reinterpret_cast<const float4*>(&Vb[i][j]);
     }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i, j;
+        tile_rc<PB>(u, v, i, j);
+        if (r0 + i < nrows) V[(size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j)] = acc[u][v];
+      }
+  }
 }
 
 // One launch per round: blocks [0, nsolve) solve the round's block pairs (writing U of this
@@ -1149,7 +1164,7 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_v_b(
   const int R = bl / nvt, rt = bl - R * nvt;
   const int r = b.f_round;
   const int par = (b.f_sweeps * (b.nb - 1) + r) & 1;
-  vtile_body<BPB>(lds[0], lds[1], b.V32, b.n, b.np, rt * PM, block_pair(b.nb, r, R),
+  vtile_body<BPB, true>(lds[0], lds[1], b.V32, b.n, b.np, rt * PM, block_pair(b.nb, r, R),
                   ubuf_b(b, par) + (size_t)R * PM * PM);
 }
 
