@@ -29,6 +29,7 @@ namespace je {
 // every thread four entries of S.
 template <int PB>
 struct Blk {
+  static_assert(PB % 4 == 0, "tiles move four consecutive floats per lane");
   static constexpr int PM = 2 * PB;
   static constexpr int PL = PM + 4;
   static constexpr int NT = PB * PM / 4;
@@ -66,7 +67,8 @@ __device__ __forceinline__ void load_pair_block(float (*T)[Blk<PB>::PL],
 
 // a row-major PM x PM factor:
 template <int PB>
-__device__ __forceinline__ void load_factor(float (*T)[Blk<PB>::PL], const float* __restrict__ U) {
+__device__ __forceinline__ void load_factor(float (*T)[Blk<PB>::PL],
+                                            const float* __restrict__ U) {
   constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
   for (int e = threadIdx.x; e < PM * PM / 4; e += NT) {
     const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
@@ -80,8 +82,9 @@ __device__ __forceinline__ void set_identity(float (*T)[Blk<PB>::PL]) {
   constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
   for (int e = threadIdx.x; e < PM * PM / 4; e += NT) {
     const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
-    *reinterpret_cast<float4*>(&T[i][j]) = make_float4(i == j ? 1.0f : 0.0f, i == j + 1 ? 1.0f : 0.0f,
-                                                       i == j + 2 ? 1.0f : 0.0f, i == j + 3 ? 1.0f : 0.0f);
+    *reinterpret_cast<float4*>(&T[i][j]) =
+        make_float4(i == j ? 1.0f : 0.0f, i == j + 1 ? 1.0f : 0.0f, i == j + 2 ? 1.0f : 0.0f,
+                    i == j + 3 ? 1.0f : 0.0f);
   }
 }
 
@@ -96,9 +99,9 @@ __device__ __forceinline__ void store_solved(const float (*S)[Blk<PB>::PL],
   for (int e = threadIdx.x; e < PM * PM / 4; e += NT) {
     const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
     const float4 u = make_float4(Ut[j][i], Ut[j + 1][i], Ut[j + 2][i], Ut[j + 3][i]);
-    const float4 v = make_float4(i <= j ? S[i][j] : S[j][i], i <= j + 1 ? S[i][j + 1] : S[j + 1][i],
-                                 i <= j + 2 ? S[i][j + 2] : S[j + 2][i],
-                                 i <= j + 3 ? S[i][j + 3] : S[j + 3][i]);
+    const float4 v =
+        make_float4(i <= j ? S[i][j] : S[j][i], i <= j + 1 ? S[i][j + 1] : S[j + 1][i],
+                    i <= j + 2 ? S[i][j + 2] : S[j + 2][i], i <= j + 3 ? S[i][j + 3] : S[j + 3][i]);
     *reinterpret_cast<float4*>(Uo + i * PM + j) = u;
     *reinterpret_cast<float4*>(Aout + (size_t)blk_row<PB>(pr.x, pr.y, i) * np +
                                blk_row<PB>(pr.x, pr.y, j)) = v;
@@ -513,9 +516,9 @@ __device__ __forceinline__ void vtile_body(float (*Ur)[Blk<PB>::PL], float (*Vb)
     const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
     *reinterpret_cast<float4*>(&Ur[i][j]) = *reinterpret_cast<const float4*>(Uh + i * PM + j);
     *reinterpret_cast<float4*>(&Vb[i][j]) =
-        (r0 + i < nrows)
-            ? *reinterpret_cast<const float4*>(V + (size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j))
-            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        (r0 + i < nrows) ? *reinterpret_cast<const float4*>(
+                               V + (size_t)(r0 + i) * np + blk_row<PB>(pr.x, pr.y, j))
+                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
   __syncthreads();
   f4 acc[2];
