@@ -1098,7 +1098,9 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
     BMat* __restrict__ mats, const int* __restrict__ act, const int* __restrict__ prefix,
     int count) {
   constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL, NT = Blk<BPB>::NT;
-  __shared__ __align__(16) float Up[PM][PL], Ur[PM][PL], Ab[PM][PL];
+  static_assert(2 * NT * 4 == PM * PM, "two four-float groups of a tile per thread");
+  // two LDS tiles (four workgroups per CU): U_R waits in registers until U_P is consumed
+  __shared__ __align__(16) float X[PM][PL], Y[PM][PL];
   const int j = find_mat(prefix, count, blockIdx.x);
   BMat& bm = mats[act[j]];
   const int nb2 = bm.nb / 2;
@@ -1114,44 +1116,49 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
   const float* Uh = ubuf_b(bm, par) + (size_t)R * PM * PM;
   float* A = bm.A32;
   const int np = bm.np, tid = threadIdx.x;
-  // four consecutive columns per lane (they lie in one block: BPB is a multiple of 4)
-  for (int e = tid; e < PM * PM / 4; e += NT) {
-    const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
-    *reinterpret_cast<float4*>(&Up[i][j]) = *reinterpret_cast<const float4*>(Ug + i * PM + j);
-    *reinterpret_cast<float4*>(&Ur[i][j]) = *reinterpret_cast<const float4*>(Uh + i * PM + j);
-    *reinterpret_cast<float4*>(&Ab[i][j]) = *reinterpret_cast<const float4*>(
-        A + (size_t)blk_row<BPB>(pp.x, pp.y, i) * np + blk_row<BPB>(pr.x, pr.y, j));
-  }
+  // four consecutive columns per lane (they lie in one block: BPB is a multiple of 4):
+  // X = U_P, Y = A_PR, registers = U_R
+  const int i0 = tid / (PM / 4), j0 = (tid % (PM / 4)) * 4, i1 = i0 + NT / (PM / 4);
+  const float4 ur0 = *reinterpret_cast<const float4*>(Uh + i0 * PM + j0);
+  const float4 ur1 = *reinterpret_cast<const float4*>(Uh + i1 * PM + j0);
+  *reinterpret_cast<float4*>(&X[i0][j0]) = *reinterpret_cast<const float4*>(Ug + i0 * PM + j0);
+  *reinterpret_cast<float4*>(&X[i1][j0]) = *reinterpret_cast<const float4*>(Ug + i1 * PM + j0);
+  *reinterpret_cast<float4*>(&Y[i0][j0]) = *reinterpret_cast<const float4*>(
+      A + (size_t)blk_row<BPB>(pp.x, pp.y, i0) * np + blk_row<BPB>(pr.x, pr.y, j0));
+  *reinterpret_cast<float4*>(&Y[i1][j0]) = *reinterpret_cast<const float4*>(
+      A + (size_t)blk_row<BPB>(pp.x, pp.y, i1) * np + blk_row<BPB>(pr.x, pr.y, j0));
   __syncthreads();
   f4 acc[2];
-  tile_mfma<BPB, true>(Up, Ab, acc);
+  tile_mfma<BPB, true>(X, Y, acc);  // T = U_P^T A_PR
   __syncthreads();
-  tile_store_lds<BPB>(Ab, acc);
+  tile_store_lds<BPB>(Y, acc);
+  *reinterpret_cast<float4*>(&X[i0][j0]) = ur0;
+  *reinterpret_cast<float4*>(&X[i1][j0]) = ur1;
   __syncthreads();
-  tile_mfma<BPB, false>(Ab, Ur, acc);
+  tile_mfma<BPB, false>(Y, X, acc);  // T U_R
   __syncthreads();
-  // the new block A_PR by rows in Up and transposed (A_RP by rows) in Ab, so that both are
+  // the new block A_PR by rows in X and transposed (A_RP by rows) in Y, so that both are
   // stored four consecutive columns per lane
-  tile_store_lds<BPB>(Up, acc);
+  tile_store_lds<BPB>(X, acc);
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int i, j;
       tile_rc<BPB>(u, v, i, j);
-      Ab[j][i] = acc[u][v];
+      Y[j][i] = acc[u][v];
     }
   __syncthreads();
   for (int e = tid; e < PM * PM / 4; e += NT) {
     const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
     *reinterpret_cast<float4*>(A + (size_t)blk_row<BPB>(pp.x, pp.y, i) * np +
                                blk_row<BPB>(pr.x, pr.y, j)) =
-        *reinterpret_cast<const float4*>(&Up[i][j]);
+        *reinterpret_cast<const float4*>(&X[i][j]);
     *reinterpret_cast<float4*>(A + (size_t)blk_row<BPB>(pr.x, pr.y, i) * np +
                                blk_row<BPB>(pp.x, pp.y, j)) =
-        *reinterpret_cast<const float4*>(&Ab[i][j]);
+        *reinterpret_cast<const float4*>(&Y[i][j]);
   }
-  tile_sq<BPB>(Up, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
+  tile_sq<BPB>(X, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
 }
 
 __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_v_b(
