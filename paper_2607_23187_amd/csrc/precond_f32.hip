@@ -1183,10 +1183,14 @@ __device__ __forceinline__ void off_norm_wg(const float* __restrict__ A, int np,
                                             double& nrm) {
   __shared__ double w[2][4];
   double so = 0.0, sd = 0.0;
-  for (size_t e = threadIdx.x; e < (size_t)np * np; e += 256) {
-    int i = (int)(e / np), j = (int)(e - (size_t)i * np);
+  // entries e = threadIdx.x + 256 k in increasing order; (i, j) advanced without division
+  // (np <= 8192, so e fits an int)
+  int i = (int)threadIdx.x / np, j = (int)threadIdx.x - i * np;
+  for (int e = threadIdx.x; e < np * np; e += 256) {
     double v = A[e];
     if (i == j) sd += v * v; else so += v * v;
+    j += 256;
+    while (j >= np) { j -= np; ++i; }
   }
   so = wave_sum_fast(so);
   sd = wave_sum_fast(sd);
@@ -1204,14 +1208,13 @@ __global__ __launch_bounds__(256) void k_f32_start_b(BMat* __restrict__ mats, si
   BMat& b = mats[blockIdx.x];
   const double* S = *reinterpret_cast<double* const*>(reinterpret_cast<const char*>(&b) + off);
   const int n = b.n, np = b.np;
-  for (size_t e = threadIdx.x; e < (size_t)np * np; e += 256) {
-    int i = (int)(e / np), j = (int)(e - (size_t)i * np);
-    b.A32[e] = (i < n && j < n) ? (float)S[(size_t)i * b.ld + j] : 0.0f;
-  }
-  for (size_t e = threadIdx.x; e < (size_t)n * np; e += 256) {
-    int i = (int)(e / np), j = (int)(e - (size_t)i * np);
-    b.V32[e] = (i == j) ? 1.0f : 0.0f;
-  }
+  // rows by waves, columns by lanes (np is a multiple of 64)
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int i = wv; i < np; i += 4)
+    for (int j = ln; j < np; j += 64)
+      b.A32[(size_t)i * np + j] = (i < n && j < n) ? (float)S[(size_t)i * b.ld + j] : 0.0f;
+  for (int i = wv; i < n; i += 4)
+    for (int j = ln; j < np; j += 64) b.V32[(size_t)i * np + j] = (i == j) ? 1.0f : 0.0f;
   __syncthreads();
   double o, nr;
   off_norm_wg(b.A32, np, o, nr);
@@ -1259,9 +1262,9 @@ __global__ void k_f32_done_b(const BMat* __restrict__ mats, int count, int* __re
 __global__ void k_f32_gather_b(BMat* __restrict__ mats, size_t qoff) {
   BMat& b = mats[blockIdx.y];
   double* Q = *reinterpret_cast<double**>(reinterpret_cast<char*>(&b) + qoff);
-  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)b.n * b.n) return;
-  int i = (int)(idx / b.n), j = (int)(idx - (size_t)i * b.n);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // n <= 8192: fits an int
+  if (idx >= b.n * b.n) return;
+  const int i = idx / b.n, j = idx - i * b.n;
   Q[(size_t)i * b.ld + j] = (double)b.V32[(size_t)i * b.np + j];
 }
 
