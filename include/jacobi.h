@@ -39,7 +39,14 @@
  *   - V (may be NULL = eigenvalues only) is column-major with leading dimension ldv >= n:
  *     component i of the eigenvector of W[k] is V[i + k*ldv].
  *   - All calls are blocking: work is enqueued on `stream` (NULL = the null stream of
- *     the current device) and the call returns once it has completed.
+ *     the current device) and the call returns once it has completed, so statistics are
+ *     valid on return.  (The solve takes decisions on the host from device state between
+ *     its launches: when the rotation log is full it is drained into V, and Newton-Schulz
+ *     stops once converged; an asynchronous form would have to move these decisions onto
+ *     the device.)
+ *   - Inputs whose largest entry lies outside [2^-60, 2^60] are scaled by a power of two
+ *     (exact) before the solve and the eigenvalues scaled back, so squares and the FP32
+ *     copy stay in range; other inputs are solved as given.
  *   - The library owns a per-device workspace pool (grown on demand, released by
  *     jacobi_release()).  Calls from several host threads are serialised internally.
  *
@@ -50,7 +57,8 @@
  *                     still orthogonal)
  *   JE_WARN_STALL     the best remaining pivot has a_pq == 0 (nothing to annihilate)
  *                     while the stop rule does not hold; W, V hold the current iterate
- *   JE_ERR_NONFINITE  A holds NaN or Inf in its upper triangle; outputs untouched
+ *   JE_ERR_NONFINITE  A holds NaN or Inf in its upper triangle (outputs untouched), or
+ *                     the preconditioned matrix is not finite
  *   JE_ERR_NOMEM      device memory for the workspace could not be allocated
  *   JE_ERR_DEVICE     a HIP runtime call failed (no device, launch failure, ...)
  *   JE_ERR_TOO_LARGE  n exceeds JE_MAX_N
@@ -104,6 +112,18 @@ typedef struct je_opts {
                              /* matrix cores with FP32 accumulation (FP32-level      */
                              /* accuracy of A_hat: a precision variant, not FP64-     */
                              /* accurate eigenvalues); 0: FP64 MFMA products     (0)  */
+  int sort;                  /* 1: W ascending, V's columns permuted to match; 0: W in  */
+                             /* the order of the final diagonal                  (1)  */
+  int update_mode;           /* HBM-resident FP64 phase: 0 automatic (mirror for one    */
+                             /* problem, timestamp for batches), 1 mirror (rows and   */
+                             /* columns p, q stored), 2 timestamp (rows only); same   */
+                             /* results                                          (0)  */
+  int tune;                  /* batched: time the workgroup shapes of each size class  */
+                             /* once per process and keep the faster (same results)(1)*/
+  int graph;                 /* 1: FP32 sweeps replayed from captured HIP graphs   (0)  */
+  int profile;               /* 1: phase timers of the FP64 Jacobi kernel into        */
+                             /* je_stats.prof_ns (slows the kernel slightly)     (0)  */
+  int fp32_block;            /* rows per block of the FP32 stage: 0 by n, 16 or 32 (0) */
 } je_opts;
 
 /* Statistics of one solve (host struct, filled before return). */
@@ -124,6 +144,11 @@ typedef struct je_stats {
                              /* events on `stream` around each launch)             */
   double a_hat_off;          /* off(A_hat) = sqrt(sum_{i != j} a_ij^2) of the matrix   */
                              /* the FP64 phase starts from (0 if not measured)       */
+  double prof_ns[6];         /* opts.profile: ns per rotation in the wave reductions,  */
+                             /* the barrier, the cross-wave reduction, row rescans,  */
+                             /* the rotation parameters and the row updates          */
+  float ms_apply_log;        /* applying the rotation log to V (HIP events on stream) */
+  int scale_exp;             /* the input was scaled by 2^scale_exp (0: not scaled)   */
 } je_stats;
 
 void je_opts_default(je_opts* opts);
@@ -140,16 +165,27 @@ int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ld
                    int pivot, int precond, const je_opts* opts, je_stats* stats,
                    je_stream stream);
 
-/* `batch` independent problems of (possibly different) sizes solved together.
- * A, W, V: HOST arrays of `batch` device pointers (V[b] may be NULL);
- * n, lda, ldv: HOST int arrays; info: HOST int array receiving each problem's status;
- * stats: HOST array of `batch` je_stats or NULL.  The whole batch shares tol, pivot,
- * precond and opts (opts->pivot_log is ignored).  Returns the worst status (errors before
- * warnings) or a negative argument index. */
+/* `batch` independent problems of (possibly different) sizes solved together: the same
+ * phases as jacobi_eigh_ex, each launch covering the whole batch, the FP64 phase as
+ * persistent launches whose workgroups take the next matrix from a device queue.  Every
+ * problem gives the same bits as a solve of its own.
+ * All arrays are DEVICE memory: A, W, V are device arrays of `batch` device pointers (V may
+ * be NULL = eigenvalues only, or hold NULL entries), n and lda device int arrays, info a
+ * device int array receiving each problem's status; V[b] has leading dimension n[b].  The
+ * whole batch shares tol, pivot, precond and opts (opts->pivot_log is ignored).  Returns
+ * the worst status (errors before warnings) or a negative argument index
+ * (A = 2 ... stream = 12).  Stream-ordered like the other calls, and blocking. */
 int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const int* lda,
-                        double* const* W, double* const* V, const int* ldv, double tol,
-                        int pivot, int precond, const je_opts* opts, int* info,
-                        je_stats* stats, je_stream stream);
+                        double* const* W, double* const* V, double tol, int pivot,
+                        int precond, const je_opts* opts, int* info, je_stream stream);
+
+/* As jacobi_eigh_batched with the arrays in HOST memory (each entry still a device
+ * pointer), explicit ldv (NULL = n) and per-problem statistics (HOST array of `batch`
+ * je_stats, or NULL): the form for callers that build the batch on the host. */
+int jacobi_eigh_batched_host(int batch, const double* const* A, const int* n, const int* lda,
+                             double* const* W, double* const* V, const int* ldv, double tol,
+                             int pivot, int precond, const je_opts* opts, int* info,
+                             je_stats* stats, je_stream stream);
 
 /* ---------------------------------------------------------------- one-sided SVD
  * Singular values (and vectors) of B (m x n, m >= n) by the one-sided Jacobi method of

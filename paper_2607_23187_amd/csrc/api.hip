@@ -73,28 +73,23 @@ constexpr double kF32Tol1Refined = 0x1p-18;
 // Stop tolerance of the first FP32 pass: its FP32 floor when it is the only pass; looser
 // when a refinement pass follows, which starts from fl32(Q^T A Q) (off ~ u_32 ||A|| however
 // far the first pass went), so the first pass's last sweeps below that level buy nothing.
-// JE_F32_TOL1_EXP=k sets 2^-k for the refined case.
-static double f32_tol1(int passes) {
-  if (passes <= 1) return kF32Tol1;
-  static const double t = [] {
-    const char* e = std::getenv("JE_F32_TOL1_EXP");
-    return e ? std::ldexp(1.0, -std::atoi(e)) : kF32Tol1Refined;
-  }();
-  return t;
-}
+static double f32_tol1(int passes) { return passes <= 1 ? kF32Tol1 : kF32Tol1Refined; }
 constexpr double kF32Rho2 = 0.5;
 // Refinement pass: sweeps until a sweep fails to halve off, or off <= 2^-30 ||A||_F (below
 // that the remaining off-diagonal mass is the FP32-level coupling inside clusters that the
-// pass skips, and the sweep that would show the stall is saved).  JE_F32_TOL2_EXP=k sets
-// 2^-k (0: off).
-static double f32_tol2() {
-  static const double t = [] {
-    const char* e = std::getenv("JE_F32_TOL2_EXP");
-    if (!e) return 0x1p-30;
-    const int k = std::atoi(e);
-    return k > 0 ? std::ldexp(1.0, -k) : 0.0;
-  }();
-  return t;
+// pass skips, and the sweep that would show the stall is saved).
+constexpr double kF32Tol2 = 0x1p-30;
+
+// Range of the entries solved as given: outside it the input is scaled by a power of two
+// (exact) so that squares in FP64 and the FP32 copy of the preconditioner stay in range.
+constexpr double kRangeLo = 0x1p-60, kRangeHi = 0x1p60;
+
+// Exponent e with 2^e maxabs in [1/2, 1) when maxabs is outside the range, else 0.
+int range_exp(double maxabs) {
+  if (!(maxabs > 0.0) || (maxabs >= kRangeLo && maxabs <= kRangeHi)) return 0;
+  int e = 0;
+  (void)std::frexp(maxabs, &e);
+  return -e;
 }
 
 // Workspace carving for one problem of size n.
@@ -246,8 +241,8 @@ int precond_q(const double* Asym, int n, int ld, double*& X, double*& Xo, double
               hipStream_t s, bool refine_floor = true) {
   int sw = 0;
   *sweeps = 0;
-  HIPCHK(run_precond_f32(Asym, n, ld, X, ld, f32, o.fp32_max_sweeps, f32_tol1(o.fp32_passes), kF32Rho1, &sw,
-                         s));
+  HIPCHK(run_precond_f32(Asym, n, ld, X, ld, f32, o.fp32_max_sweeps, f32_tol1(o.fp32_passes),
+                         kF32Rho1, &sw, o.fp32_block, o.graph != 0, s));
   *sweeps += sw;
   int r = orthonormalize(X, Xo, R, n, ld, part, scal, s);
   if (r) return r;
@@ -255,8 +250,9 @@ int precond_q(const double* Asym, int n, int ld, double*& X, double*& Xo, double
     HIPCHK(launch_dgemm(n, 0, 1.0, Asym, ld, X, ld, 0.0, nullptr, 0, T, ld, s));
     HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, T, ld, 0.0, nullptr, 0, A, ld, s));
     HIPCHK(launch_symmetrize(A, n, ld, s));
-    HIPCHK(run_precond_f32(A, n, ld, T, ld, f32, o.fp32_max_sweeps, refine_floor ? f32_tol2() : 0.0,
-                           kF32Rho2, &sw, s));
+    HIPCHK(run_precond_f32(A, n, ld, T, ld, f32, o.fp32_max_sweeps,
+                           refine_floor ? kF32Tol2 : 0.0, kF32Rho2, &sw, o.fp32_block,
+                           o.graph != 0, s));
     *sweeps += sw;
     HIPCHK(launch_dgemm(n, 0, 1.0, X, ld, T, ld, 0.0, nullptr, 0, Xo, ld, s));
     std::swap(X, Xo);
@@ -277,23 +273,34 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   const int ld = ld_of(n);
   je_stats S{};
 
-  // ---- 1. symmetric copy, finiteness, ||A||_F
+  // ---- 1. symmetric copy, finiteness, range, ||A||_F
   Timer tp(s);
   HIPCHK(hipMemsetAsync(w.flag, 0, 4, s));
   HIPCHK(launch_symcopy(Au, n, lda, w.Asym, ld, w.diag, nullptr, w.flag, s));
-  HIPCHK(launch_fro2(w.Asym, n, ld, w.rowsq, w.scal, s));
+  HIPCHK(launch_maxabs(w.Asym, n, ld, w.rowsq, w.scal + 4, s));
   int flag = 0;
-  double normF = 0.0;
+  double maxabs = 0.0;
   HIPCHK(hipMemcpyAsync(&flag, w.flag, 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&normF, w.scal, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&maxabs, w.scal + 4, 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (flag) return JE_ERR_NONFINITE;
-  S.normF = normF;
+  // out-of-range input: solved as 2^e A (exact), eigenvalues scaled back
+  const int e_scale = range_exp(maxabs);
+  if (e_scale) HIPCHK(launch_scale(w.Asym, n, ld, w.diag, e_scale, s));
+  S.scale_exp = e_scale;
+  double normF = 0.0;
+  HIPCHK(launch_fro2(w.Asym, n, ld, w.rowsq, w.scal, s));
+  HIPCHK(hipMemcpyAsync(&normF, w.scal, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!std::isfinite(normF)) return JE_ERR_NONFINITE;
+  // thresholds and reported norms refer to the caller's A; the solve runs on 2^e A
+  const double unscale = std::ldexp(1.0, -e_scale);
+  S.normF = normF * unscale;
   double thr;
-  if (o.abs_thr > 0.0) thr = o.abs_thr;
+  if (o.abs_thr > 0.0) thr = std::ldexp(o.abs_thr, e_scale);
   else if (o.stop == JE_STOP_CERT) thr = tol * normF / (2.0 * n * (double)(n - 1));
   else thr = tol * normF;
-  S.thr = thr;
+  S.thr = thr * unscale;
 
   // ---- 2. preconditioner
   double* Ajac = w.Asym;
@@ -321,6 +328,8 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
     HIPCHK(launch_offnorm(w.A, n, ld, w.rowsq, w.scal + 2, s));
     HIPCHK(hipMemcpyAsync(&S.a_hat_off, w.scal + 2, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (!std::isfinite(S.a_hat_off)) return JE_ERR_NONFINITE;
+    S.a_hat_off *= unscale;
   } else {
     HIPCHK(launch_set_identity(Vw, n, ld, s));
     S.ms_precond = tp.stop();
@@ -337,21 +346,22 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   d.thr = thr; d.maxrot = maxrot; d.pivot = pivot; d.stop = o.stop;
   if (precond) HIPCHK(launch_get_diag(Ajac, n, ld, w.diag, s));
   HIPCHK(hipMemsetAsync(w.ctl, 0, sizeof(JCtl), s));
-  // JE_PROFILE=1: per-phase timers of the Jacobi kernel, printed to stderr per solve
-  static const bool profile = std::getenv("JE_PROFILE") != nullptr;
+  // opts.profile: per-phase timers of the Jacobi kernel
+  const bool profile = o.profile != 0;
   if (profile) {
     HIPCHK(hipMemsetAsync(w.prof, 0, 64, s));
     d.prof = w.prof;
   }
   HIPCHK(launch_init_rows(d, s));
   const bool lds = jacobi_fits_lds(n);
+  const bool mirror = o.update_mode != 2;  // one problem: mirror mode unless asked otherwise
   long long base_rot = 0;
   JCtl hc{};
   float ms_apply = 0.f;
   float ms_kernel = 0.f;
   for (;;) {
     Timer tk(s);
-    HIPCHK(launch_jacobi(d, base_rot, lds, s));
+    HIPCHK(launch_jacobi(d, base_rot, lds, mirror, s));
     ms_kernel += tk.stop();
     HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(JCtl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -368,22 +378,18 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   }
   S.ms_jacobi = tj.stop() - ms_apply;
   if (profile) {
+    // the timers tick at 100 MHz (10 ns)
     long long pr[8];
     HIPCHK(hipMemcpy(pr, w.prof, 64, hipMemcpyDeviceToHost));
-    double r = (double)std::max<long long>(1, hc.rotations);
-    std::fprintf(stderr,
-                 "JE_PROFILE n=%d rot=%lld rescans=%lld ns/rot: wave %.0f barrier %.0f cross %.0f "
-                 "rescan %.0f params %.0f rotate %.0f total %.0f  shader-clock %.0f MHz\n",
-                 n, hc.rotations, hc.rescans, pr[0] * 10 / r, pr[1] * 10 / r, pr[2] * 10 / r,
-                 pr[3] * 10 / r, pr[4] * 10 / r, pr[5] * 10 / r,
-                 (pr[0] + pr[1] + pr[2] + pr[3] + pr[4] + pr[5]) * 10 / r,
-                 pr[7] > 0 ? (double)pr[6] / (pr[7] * 10.0) * 1000.0 : 0.0);
+    const double r = (double)std::max<long long>(1, hc.rotations);
+    for (int k = 0; k < 6; ++k) S.prof_ns[k] = pr[k] * 10.0 / r;
   }
   S.ms_jacobi_kernel = ms_kernel;
+  S.ms_apply_log = ms_apply;
   S.rotations = hc.rotations;
   S.rescans = hc.rescans;
-  S.final_max_score = hc.final_cert;
-  S.final_off = hc.final_off;
+  S.final_max_score = hc.final_cert * unscale;
+  S.final_off = hc.final_off * unscale;
   S.status = hc.status == ST_MAXROT ? JE_WARN_MAXROT : (hc.status == ST_STALL ? JE_WARN_STALL : JE_OK);
 
   // ---- 4. polish, sort, output
@@ -395,7 +401,7 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
     if (r) return r;
     Vw = X;
   }
-  HIPCHK(launch_sort_output(w.diag, n, Vw, ld, W, V, ldv, w.rank, s));
+  HIPCHK(launch_sort_output(w.diag, n, Vw, ld, W, V, ldv, w.rank, o.sort, -e_scale, s));
   HIPCHK(hipStreamSynchronize(s));
   S.ms_finalize = tf.stop() + ms_apply;
   if (st) *st = S;
@@ -412,14 +418,9 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
 constexpr long long kBatchLogCap = 1ll << 16;
 
 // Tuned workgroup shapes of the batched Jacobi phase, per (class, pivot, size bucket).
-// JE_TUNE=0 keeps the default shapes (one wave LDS-resident, 512 threads otherwise).
+// opts.tune = 0 keeps the default shapes (one wave LDS-resident, 512 threads otherwise).
 std::mutex g_tune_mu;
 std::map<int, int> g_tune;
-
-bool tuning_enabled() {
-  const char* e = std::getenv("JE_TUNE");
-  return !(e && e[0] == '0');
-}
 
 struct BatchLayout {
   size_t bytes = 0;
@@ -687,11 +688,27 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   };
   je_stats S{};
   Timer tp(s);
-  // ---- 1. symmetric copies, finiteness, ||A||_F
+  // ---- 1. symmetric copies, finiteness, range, ||A||_F
   HIPCHK(launch_reset_b(dm, cnt, s));
   HIPCHK(launch_symcopy_b(dm, cnt, nmax, s));
+  HIPCHK(launch_maxabs_b(dm, cnt, nmax, BF(Asym), 4, s));
+  if (int r = collect()) return r;
+  // out-of-range members are solved as 2^e A (exact), their eigenvalues scaled back
+  {
+    bool any = false;
+    for (int i = 0; i < cnt; ++i) {
+      hm[i].a_exp = hi[i].nonfinite ? 0 : range_exp(hi[i].maxabs);
+      any = any || hm[i].a_exp != 0;
+    }
+    if (any) {
+      if (int r = upload()) return r;
+      HIPCHK(launch_scale_b(dm, cnt, nmax, BF(Asym), s));
+    }
+  }
   HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(Asym), 0, s));
   if (int r = collect()) return r;
+  for (int i = 0; i < cnt; ++i)
+    if (!hi[i].nonfinite && !std::isfinite(hi[i].normF)) hi[i].nonfinite = 1;
   // members with a non-finite entry leave the batch here (status JE_ERR_NONFINITE, outputs
   // untouched, as for a single problem)
   int worst = JE_OK;
@@ -729,7 +746,7 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
     const int nn = x.n;
     JDesc& d = x.jd;
     double thr;
-    if (o.abs_thr > 0.0) thr = o.abs_thr;
+    if (o.abs_thr > 0.0) thr = std::ldexp(o.abs_thr, x.a_exp);
     else if (o.stop == JE_STOP_CERT) thr = tol * nrm[i] / (2.0 * nn * (double)(nn - 1));
     else thr = tol * nrm[i];
     d.A = precond ? x.A : x.Asym;
@@ -779,7 +796,7 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
       HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
       HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
       HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
-      if (int r = f32pass(BF(A), BF(T), f32_tol2(), kF32Rho2)) return r;
+      if (int r = f32pass(BF(A), BF(T), kF32Tol2, kF32Rho2)) return r;
       HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, offX, BF(T), 0.0, 0, offXb, s));
       std::swap(offX, offXb);
       if (int r = orthonormalize_b()) return r;
@@ -801,6 +818,10 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   HIPCHK(launch_reset_b(dm, cnt, s));
   const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
   HIPCHK(launch_init_rows_b(dm, cnt, nmax, pivot, use_cert, s));
+  // a batch keeps rows only (timestamp mode) unless asked otherwise: with hundreds of
+  // matrices in flight the mirrored column stores, each dirtying a cache line for 8 bytes,
+  // make HBM writes the larger cost
+  const bool mirror = o.update_mode == 1;
   // workgroup shape of each class: tuned once per (class, pivot, size bucket) and cached
   int shape_lds = 64, shape_hbm = 512;
   {
@@ -822,7 +843,7 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
         auto it = g_tune.find(key);
         if (it != g_tune.end()) { *shape = it->second; return JE_OK; }
       }
-      if (!tuning_enabled()) return JE_OK;
+      if (!o.tune) return JE_OK;
       // the trial runs on the class itself (up to 1024 matrices, spread over its sizes):
       // a small sample leaves the device half idle and favours the wrong shape
       std::vector<int> smp;
@@ -837,7 +858,8 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
       for (int shp : {a, b}) {
         HIPCHK(hipMemsetAsync(d_cnt, 0, 8, s));
         Timer tt(s);
-        HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)smp.size(), nmx, pivot, lds, shp, d_cnt,
+        HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)smp.size(), nmx, pivot, lds, mirror,
+                                   shp, d_cnt,
                                    (int)std::min<size_t>(smp.size(), lds ? 2048 : 1024), s));
         const float ms = tt.stop();
         if (shp == a) { t_default = ms; best = ms; *shape = a; }
@@ -875,11 +897,12 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
     HIPCHK(hipStreamSynchronize(s));
     Timer tk(s);
     if (!il.empty())
-      HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, shape_lds,
-                                 d_cnt, (int)std::min<size_t>(il.size(), 2048), s));
+      HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, mirror,
+                                 shape_lds, d_cnt, (int)std::min<size_t>(il.size(), 2048), s));
     if (!ih.empty())
-      HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, shape_hbm,
-                                 d_cnt + 1, (int)std::min<size_t>(ih.size(), 1024), s));
+      HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, mirror,
+                                 shape_hbm, d_cnt + 1, (int)std::min<size_t>(ih.size(), 1024),
+                                 s));
     ms_kernel += tk.stop();
     HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
     if (int r = collect()) return r;
@@ -895,7 +918,7 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
     HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, BF(Vw), BF(R), 1.0, BF(Vw), BF(X), s));
     HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(Vw), BF(X), s));
   }
-  HIPCHK(launch_sort_output_b(dm, cnt, nmax, s));
+  HIPCHK(launch_sort_output_b(dm, cnt, nmax, o.sort, s));
   if (int r = download()) return r;
   S.ms_finalize = tf.stop();
   S.ms_gemm = ms_gemm;
@@ -907,14 +930,16 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
     worst = std::max(worst, st);
     if (stats) {
       je_stats& x = stats[b];
+      const double unscale = std::ldexp(1.0, -hm[i].a_exp);
       x = S;
       x.rotations = hc[i].rotations;
       x.rescans = hc[i].rescans;
-      x.final_max_score = hc[i].final_cert;
-      x.final_off = hc[i].final_off;
-      x.normF = nrm[i];
-      x.thr = hm[i].jd.thr;
+      x.final_max_score = hc[i].final_cert * unscale;
+      x.final_off = hc[i].final_off * unscale;
+      x.normF = nrm[i] * unscale;
+      x.thr = hm[i].jd.thr * unscale;
       x.sweeps32 = hm[i].f_pass_sweeps;
+      x.scale_exp = hm[i].a_exp;
       x.status = st;
     }
   }
@@ -1022,9 +1047,14 @@ void server_worker(Server* S) {
       anyv = anyv || V[i] != nullptr;
     }
     const double t_start = S->now();
-    (void)solve_batched(mem, A.data(), n.data(), lda.data(), W.data(), anyv ? V.data() : nullptr,
-                        ldv.data(), S->tol, S->pivot, S->precond, S->o, info.data(),
-                        stats.data(), st, worker_ws, &buf);
+    const int rr = solve_batched(mem, A.data(), n.data(), lda.data(), W.data(),
+                                 anyv ? V.data() : nullptr, ldv.data(), S->tol, S->pivot,
+                                 S->precond, S->o, info.data(), stats.data(), st, worker_ws,
+                                 &buf);
+    // a failure of the whole batch (allocation, device) is every member's status
+    if (rr >= JE_ERR_NOMEM)
+      for (int i = 0; i < cnt; ++i)
+        if (info[i] == JE_ERR_DEVICE) info[i] = rr;
     (void)hipStreamSynchronize(st);
     const double t_end = S->now();
     {
@@ -1064,6 +1094,12 @@ int check_args(const double* A, int n, int lda, const double* W, const double* V
   if (o.stop < JE_STOP_CERT || o.stop > JE_STOP_SCORE) return -10;
   if (o.fp32_max_sweeps < 0 || o.fp32_passes < 1 || o.fp32_passes > 2) return -10;
   if (o.split_gemm != 0 && o.split_gemm != 1) return -10;
+  if (o.sort != 0 && o.sort != 1) return -10;
+  if (o.update_mode < 0 || o.update_mode > 2) return -10;
+  if (o.tune != 0 && o.tune != 1) return -10;
+  if (o.graph != 0 && o.graph != 1) return -10;
+  if (o.profile != 0 && o.profile != 1) return -10;
+  if (o.fp32_block != 0 && o.fp32_block != 16 && o.fp32_block != 32) return -10;
   return 0;
 }
 
@@ -1083,6 +1119,12 @@ void je_opts_default(je_opts* o) {
   o->pivot_log = nullptr;
   o->pivot_log_cap = 0;
   o->split_gemm = 0;
+  o->sort = 1;
+  o->update_mode = 0;
+  o->tune = 1;
+  o->graph = 0;
+  o->profile = 0;
+  o->fp32_block = 0;
 }
 
 int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
@@ -1136,10 +1178,10 @@ int jacobi_svd(const double* B, int m, int n, int ldb, double* S, double* U, int
                  (hipStream_t)stream);
 }
 
-int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const int* lda,
-                        double* const* W, double* const* V, const int* ldv, double tol, int pivot,
-                        int precond, const je_opts* opts, int* info, je_stats* stats,
-                        je_stream stream) {
+int jacobi_eigh_batched_host(int batch, const double* const* A, const int* n, const int* lda,
+                             double* const* W, double* const* V, const int* ldv, double tol,
+                             int pivot, int precond, const je_opts* opts, int* info,
+                             je_stats* stats, je_stream stream) {
   if (batch < 0) return -1;
   if (batch > 0 && (!A || !n || !lda || !W || !info)) return -2;
   je_opts o;
@@ -1148,9 +1190,10 @@ int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const i
   o.pivot_log = nullptr;
   // argument checks first: a bad problem rejects the whole call before any work
   for (int b = 0; b < batch; ++b) {
+    // argument k of the single call is argument k + 1 here
     int a = check_args(A[b], n[b], lda[b], W[b], V ? V[b] : nullptr, ldv ? ldv[b] : n[b], tol,
                        pivot, precond, o);
-    if (a) { info[b] = a; return a; }
+    if (a) { info[b] = a - 1; return a - 1; }
     if (n[b] > JE_MAX_N) { info[b] = JE_ERR_TOO_LARGE; return JE_ERR_TOO_LARGE; }
   }
   int worst = JE_OK;
@@ -1167,6 +1210,40 @@ int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const i
   int r = solve_batched(mem, A, n, lda, W, V, ldv, tol, pivot, precond, o, info, stats,
                         (hipStream_t)stream);
   return std::max(worst, r);  // errors (>= 3) rank above warnings (1, 2)
+}
+
+int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const int* lda,
+                        double* const* W, double* const* V, double tol, int pivot,
+                        int precond, const je_opts* opts, int* info, je_stream stream) {
+  if (batch < 0) return -1;
+  if (batch == 0) return JE_OK;
+  if (!A) return -2;
+  if (!n) return -3;
+  if (!lda) return -4;
+  if (!W) return -5;
+  if (!info) return -11;
+  hipStream_t s = (hipStream_t)stream;
+  // the batch's description is read to the host: the workspace of each member is carved
+  // by its size
+  std::vector<const double*> hA(batch);
+  std::vector<double*> hW(batch), hV(V ? batch : 0);
+  std::vector<int> hn(batch), hlda(batch), hinfo(batch, 0);
+  HIPCHK(hipMemcpyAsync(hA.data(), A, sizeof(double*) * batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hW.data(), W, sizeof(double*) * batch, hipMemcpyDeviceToHost, s));
+  if (V) HIPCHK(hipMemcpyAsync(hV.data(), V, sizeof(double*) * batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hn.data(), n, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hlda.data(), lda, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int r = jacobi_eigh_batched_host(batch, hA.data(), hn.data(), hlda.data(), hW.data(),
+                                   V ? hV.data() : nullptr, nullptr, tol, pivot, precond, opts,
+                                   hinfo.data(), nullptr, stream);
+  // argument numbers of the host form past V are one higher (its ldv)
+  if (r < -7) r += 1;
+  for (int& x : hinfo)
+    if (x < -7) x += 1;
+  HIPCHK(hipMemcpyAsync(info, hinfo.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return r;
 }
 
 size_t jacobi_workspace_size(int n, int precond) {

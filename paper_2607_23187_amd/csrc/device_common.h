@@ -170,12 +170,17 @@ __device__ __forceinline__ int wave_argmax_lane(double score, int key) {
   return w;
 }
 
-// Wave-uniform upper bound of max(v) (the float rounding of the maximum, widened by
-// 2^-22 relative); -1 when every lane passes a negative value.
-__device__ __forceinline__ double wave_max_ub(double v) {
-  const int m = wave_max_i(key32(v));
+// Upper bound of every score whose key32 is <= m: the next float above the float key (the
+// conversion rounds to nearest, so the float is within half an ulp of the score, in the
+// normal and the subnormal range alike); +inf stays +inf; -1 when m is "no candidate".
+__device__ __forceinline__ double key_ub(int m) {
   if (m < 0) return -1.0;
-  return (double)__int_as_float(m) * (1.0 + 0x1p-22);
+  return m >= 0x7f800000 ? (double)__int_as_float(0x7f800000) : (double)__int_as_float(m + 1);
+}
+
+// Wave-uniform upper bound of max(v); -1 when every lane passes a negative value.
+__device__ __forceinline__ double wave_max_ub(double v) {
+  return key_ub(wave_max_i(key32(v)));
 }
 
 // Wave-uniform maximum of doubles (exact).

@@ -18,8 +18,6 @@
 //   V      is not touched by the Jacobi kernel: every rotation is appended to a log
 //          (p, q, c, s) and applied to the rows of V by a separate, fully parallel kernel.
 #include <hip/hip_runtime.h>
-#include <stdlib.h>
-
 #include <algorithm>
 
 #include "device_common.h"
@@ -95,6 +93,7 @@ __global__ void k_collect_b(const BMat* __restrict__ mats, int count, BInfo* __r
   BInfo x;
   x.normF = b.scal[0];
   x.rnorm = b.scal[1];
+  x.maxabs = b.scal[4];
   x.nonfinite = b.flag[0];
   x.pad = 0;
   x.ctl = *b.jd.ctl;
@@ -237,6 +236,106 @@ hipError_t launch_offnorm(const double* A, int n, int ld, double* partial, doubl
                           hipStream_t s) {
   hipLaunchKernelGGL(k_rowsq_off, dim3((n + 3) / 4), dim3(256), 0, s, A, n, ld, partial);
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partial, n, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ range of A
+// max |a_ij| (per-row maxima, then one block), and an exact scaling by a power of two.
+__global__ __launch_bounds__(256) void k_rowmax(const double* __restrict__ A, int n, int ld,
+                                                double* __restrict__ partial) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double m = 0.0;
+  for (int l = lane; l < n; l += 64) m = fmax(m, fabs(A[(size_t)row * ld + l]));
+  m = wave_max_d(m);
+  if (lane == 0) partial[row] = m;
+}
+
+__global__ __launch_bounds__(256) void k_max_rows(const double* __restrict__ partial, int n,
+                                                  double* out) {
+  __shared__ double w[4];
+  double m = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) m = fmax(m, partial[k]);
+  m = wave_max_d(m);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = fmax(fmax(w[0], w[1]), fmax(w[2], w[3]));
+}
+
+hipError_t launch_maxabs(const double* A, int n, int ld, double* partial, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_rowmax, dim3((n + 3) / 4), dim3(256), 0, s, A, n, ld, partial);
+  hipLaunchKernelGGL(k_max_rows, dim3(1), dim3(256), 0, s, partial, n, out);
+  return hipGetLastError();
+}
+
+// A <- 2^e A and diag <- 2^e diag (exact: no entry leaves the normal range for the scalings
+// the host chooses).
+__global__ void k_scale(double* __restrict__ A, int n, int ld, double* __restrict__ diag,
+                        int e) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
+  double v = ldexp(A[(size_t)i * ld + j], e);
+  A[(size_t)i * ld + j] = v;
+  if (i == j && diag) diag[i] = v;
+}
+
+hipError_t launch_scale(double* A, int n, int ld, double* diag, int e, hipStream_t s) {
+  size_t tot = (size_t)n * n;
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A, n, ld,
+                     diag, e);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_rowmax_b(BMat* __restrict__ mats, size_t off) {
+  BMat& b = mats[blockIdx.y];
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= b.n) return;
+  const double* A = bm_mat(b, off);
+  double m = 0.0;
+  for (int l = lane; l < b.n; l += 64) m = fmax(m, fabs(A[(size_t)row * b.ld + l]));
+  m = wave_max_d(m);
+  if (lane == 0) b.rowsq[row] = m;
+}
+
+__global__ __launch_bounds__(256) void k_max_rows_b(BMat* __restrict__ mats, int slot) {
+  BMat& b = mats[blockIdx.x];
+  __shared__ double w[4];
+  double m = 0.0;
+  for (int k = threadIdx.x; k < b.n; k += 256) m = fmax(m, b.rowsq[k]);
+  m = wave_max_d(m);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) b.scal[slot] = fmax(fmax(w[0], w[1]), fmax(w[2], w[3]));
+}
+
+hipError_t launch_maxabs_b(BMat* m, int count, int nmax, size_t off, int out_slot,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_rowmax_b, dim3((nmax + 3) / 4, count), dim3(256), 0, s, m, off);
+  hipLaunchKernelGGL(k_max_rows_b, dim3(count), dim3(256), 0, s, m, out_slot);
+  return hipGetLastError();
+}
+
+// members with a_exp != 0: the matrix at `off` and the diagonal scaled by 2^a_exp
+__global__ void k_scale_b(BMat* __restrict__ mats, size_t off) {
+  BMat& b = mats[blockIdx.y];
+  if (b.a_exp == 0) return;
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)b.n * b.n) return;
+  int i = (int)(idx / b.n), j = (int)(idx - (size_t)i * b.n);
+  double* A = bm_mat(b, off);
+  double v = ldexp(A[(size_t)i * b.ld + j], b.a_exp);
+  A[(size_t)i * b.ld + j] = v;
+  if (i == j) b.diag[i] = v;
+}
+
+hipError_t launch_scale_b(BMat* m, int count, int nmax, size_t off, hipStream_t s) {
+  size_t tot = (size_t)nmax * nmax;
+  hipLaunchKernelGGL(k_scale_b, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0, s, m,
+                     off);
   return hipGetLastError();
 }
 
@@ -439,7 +538,7 @@ __device__ __forceinline__ void wave_best3(Cand& a, int ka, Cand& b, int kb, Can
   auto ub_of = [](int m) {
     const int r = max(max(__builtin_amdgcn_readlane(m, 0), __builtin_amdgcn_readlane(m, 16)),
                       max(__builtin_amdgcn_readlane(m, 32), __builtin_amdgcn_readlane(m, 48)));
-    return r < 0 ? -1.0 : (double)__int_as_float(r) * (1.0 + 0x1p-22);
+    return key_ub(r);
   };
   const double ub = ub_of(mb), uc = ub_of(mc);
   a = read_cand(a, la, false);
@@ -498,8 +597,8 @@ __device__ __forceinline__ void reduce_groups3(const Cand* g0, const Cand* g1, c
   r0 = read_cand(x, win[0], false);
   r1 = read_cand(x, win[1], false);
   r2 = read_cand(x, win[2], false);
-  r1.u = mu1 < 0 ? -1.0 : (double)__int_as_float(mu1) * (1.0 + 0x1p-22);
-  r2.u = mu2 < 0 ? -1.0 : (double)__int_as_float(mu2) * (1.0 + 0x1p-22);
+  r1.u = key_ub(mu1);
+  r2.u = key_ub(mu2);
 }
 
 // Cross-wave argmax of slot k over the NW waves: every lane scans the same NW entries
@@ -952,6 +1051,8 @@ bool jacobi_fits_lds(int n) {
 
 template <int NT, int RM, bool GAP, bool LDSA, bool MIR>
 static hipError_t launch_one(const JDesc& d, long long log_base, hipStream_t s) {
+  // thread tid owns rows tid + i NT, i < RM: every row of the matrix needs an owner
+  if ((long long)NT * RM < d.n) return hipErrorInvalidValue;
   size_t sh = lds_bytes(d.n, LDSA);
   auto fn = k_jacobi<NT, RM, GAP, LDSA, MIR>;
   if (sh > 65536) {
@@ -961,25 +1062,6 @@ static hipError_t launch_one(const JDesc& d, long long log_base, hipStream_t s) 
   }
   hipLaunchKernelGGL(fn, dim3(1), dim3(NT), sh, s, d, log_base);
   return hipGetLastError();
-}
-
-// HBM-resident matrices are updated in mirror mode by default (rows and columns p, q stored,
-// every load a contiguous row segment); JE_MIRROR=0 selects the timestamp mode (rows only,
-// the newer copy of each entry chosen by per-row write timestamps).  Both give the same
-// arithmetic and the same pivot sequence.
-static int mirror_mode() {
-  const char* e = getenv("JE_MIRROR");
-  return (e && e[0] == '0') ? 0 : 1;
-}
-
-// The persistent batched launch defaults to the timestamp mode (JE_MIRROR=1 selects mirror
-// mode): with hundreds of matrices in flight the mirrored column stores, each dirtying a
-// cache line for 8 bytes, make HBM writes the larger cost (2048-matrix batch: 42 GB written
-// against 17 GB of algorithmic row traffic; kernel 61 -> 50 ms without them), while one
-// matrix alone is faster in mirror mode (5.11 vs 5.25 us per rotation at n = 1024).
-static int queue_mirror_mode() {
-  const char* e = getenv("JE_MIRROR");
-  return (e && e[0] == '1') ? 1 : 0;
 }
 
 // Threads per workgroup for the HBM-resident kernel: 512 (two waves per SIMD, 256 VGPRs
@@ -995,23 +1077,28 @@ static hipError_t launch_global(const JDesc& d, long long log_base, hipStream_t 
   return launch_one<1024, 8, GAP, false, MIR>(d, log_base, s);
 }
 
+// HBM-resident matrices: mirror mode (rows and columns p, q stored, every load a contiguous
+// row segment) or timestamp mode (rows only, the newer copy of each entry chosen by per-row
+// write timestamps).  Both give the same arithmetic and the same pivot sequence.
 template <bool GAP>
-static hipError_t launch_jacobi_t(const JDesc& d, long long log_base, bool lds, hipStream_t s) {
+static hipError_t launch_jacobi_t(const JDesc& d, long long log_base, bool lds, bool mirror,
+                                  hipStream_t s) {
   const int n = d.n;
   if (lds) {
     if (n <= 64) return launch_one<64, 1, GAP, true, true>(d, log_base, s);
     return launch_one<64, 2, GAP, true, true>(d, log_base, s);
   }
-  if (mirror_mode()) return launch_global<GAP, true>(d, log_base, s);
+  if (mirror) return launch_global<GAP, true>(d, log_base, s);
   return launch_global<GAP, false>(d, log_base, s);
 }
 
 template <int NT, int RM, bool GAP, bool LDSA>
-static hipError_t launch_queue_one(BMat* m, const int* idx, int count, int nmax, int* counter,
-                                   int grid, hipStream_t s) {
+static hipError_t launch_queue_one(BMat* m, const int* idx, int count, int nmax, bool mirror,
+                                   int* counter, int grid, hipStream_t s) {
+  if ((long long)NT * RM < nmax) return hipErrorInvalidValue;
   size_t sh = lds_bytes(nmax, LDSA);
-  auto fn = (LDSA || queue_mirror_mode()) ? k_jacobi_queue<NT, RM, GAP, LDSA, true>
-                                          : k_jacobi_queue<NT, RM, GAP, LDSA, false>;
+  auto fn = (LDSA || mirror) ? k_jacobi_queue<NT, RM, GAP, LDSA, true>
+                             : k_jacobi_queue<NT, RM, GAP, LDSA, false>;
   if (sh > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
@@ -1022,37 +1109,49 @@ static hipError_t launch_queue_one(BMat* m, const int* idx, int count, int nmax,
 }
 
 // Workgroup shapes of the batched Jacobi: LDS-resident matrices (n <= 128) with one or two
-// waves, HBM-resident ones with 256 or 512 threads; rows per thread = ceil(nmax / threads).
+// waves, HBM-resident ones with 256 or 512 threads (1024 above n = 4096); rows per thread
+// = ceil(nmax / threads).
 template <bool GAP>
 static hipError_t launch_queue_t(BMat* m, const int* idx, int count, int nmax, bool lds,
-                                 int threads, int* counter, int grid, hipStream_t s) {
+                                 bool mirror, int threads, int* counter, int grid,
+                                 hipStream_t s) {
   if (lds) {
     if (threads == 128 && nmax <= 128)
-      return launch_queue_one<128, 1, GAP, true>(m, idx, count, nmax, counter, grid, s);
-    if (nmax <= 64) return launch_queue_one<64, 1, GAP, true>(m, idx, count, nmax, counter, grid, s);
-    return launch_queue_one<64, 2, GAP, true>(m, idx, count, nmax, counter, grid, s);
+      return launch_queue_one<128, 1, GAP, true>(m, idx, count, nmax, mirror, counter, grid, s);
+    if (nmax <= 64)
+      return launch_queue_one<64, 1, GAP, true>(m, idx, count, nmax, mirror, counter, grid, s);
+    return launch_queue_one<64, 2, GAP, true>(m, idx, count, nmax, mirror, counter, grid, s);
   }
   if (threads == 256) {
-    if (nmax <= 256) return launch_queue_one<256, 1, GAP, false>(m, idx, count, nmax, counter, grid, s);
-    if (nmax <= 512) return launch_queue_one<256, 2, GAP, false>(m, idx, count, nmax, counter, grid, s);
+    if (nmax <= 256)
+      return launch_queue_one<256, 1, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+    if (nmax <= 512)
+      return launch_queue_one<256, 2, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
   }
-  if (nmax <= 512) return launch_queue_one<512, 1, GAP, false>(m, idx, count, nmax, counter, grid, s);
-  if (nmax <= 1024) return launch_queue_one<512, 2, GAP, false>(m, idx, count, nmax, counter, grid, s);
-  if (nmax <= 2048) return launch_queue_one<512, 4, GAP, false>(m, idx, count, nmax, counter, grid, s);
-  return launch_queue_one<512, 8, GAP, false>(m, idx, count, nmax, counter, grid, s);
+  if (nmax <= 512)
+    return launch_queue_one<512, 1, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+  if (nmax <= 1024)
+    return launch_queue_one<512, 2, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+  if (nmax <= 2048)
+    return launch_queue_one<512, 4, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+  if (nmax <= 4096)
+    return launch_queue_one<512, 8, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+  return launch_queue_one<1024, 8, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
 }
 
 hipError_t launch_jacobi_queue(BMat* m, const int* idx, int count, int nmax, int pivot,
-                               bool lds_mode, int threads, int* counter, int grid,
+                               bool lds_mode, bool mirror, int threads, int* counter, int grid,
                                hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (pivot == 1) return launch_queue_t<true>(m, idx, count, nmax, lds_mode, threads, counter, grid, s);
-  return launch_queue_t<false>(m, idx, count, nmax, lds_mode, threads, counter, grid, s);
+  if (pivot == 1)
+    return launch_queue_t<true>(m, idx, count, nmax, lds_mode, mirror, threads, counter, grid, s);
+  return launch_queue_t<false>(m, idx, count, nmax, lds_mode, mirror, threads, counter, grid, s);
 }
 
-hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, hipStream_t s) {
-  if (d.pivot == 1) return launch_jacobi_t<true>(d, log_base, lds_mode, s);
-  return launch_jacobi_t<false>(d, log_base, lds_mode, s);
+hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, bool mirror,
+                         hipStream_t s) {
+  if (d.pivot == 1) return launch_jacobi_t<true>(d, log_base, lds_mode, mirror, s);
+  return launch_jacobi_t<false>(d, log_base, lds_mode, mirror, s);
 }
 
 // ------------------------------------------------------------------ J5: apply the log to V
@@ -1214,21 +1313,27 @@ hipError_t launch_set_identity(double* V, int n, int ldv, hipStream_t s) {
 
 // ------------------------------------------------------------------ J7: sort and output
 // rank[k] = #{l : d_l < d_k} + #{l < k : d_l == d_k}  (ascending, stable)
+// (sort == 0: rank[k] = k, the diagonal order.)  W[rank[k]] = 2^w_exp d_k (exact).
 __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ diag, int n,
-                                              int* __restrict__ rank, double* __restrict__ W) {
+                                              int* __restrict__ rank, double* __restrict__ W,
+                                              int sort, int w_exp) {
   extern __shared__ double sd[];
-  for (int l = threadIdx.x; l < n; l += 256) sd[l] = diag[l];
+  if (sort)
+    for (int l = threadIdx.x; l < n; l += 256) sd[l] = diag[l];
   __syncthreads();
   int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
-  double v = sd[k];
-  int r = 0;
-  for (int l = 0; l < n; ++l) {
-    double u = sd[l];
-    r += (u < v) || (u == v && l < k);
+  double v = sort ? sd[k] : diag[k];
+  int r = k;
+  if (sort) {
+    r = 0;
+    for (int l = 0; l < n; ++l) {
+      double u = sd[l];
+      r += (u < v) || (u == v && l < k);
+    }
   }
   rank[k] = r;
-  W[r] = v;
+  W[r] = w_exp ? ldexp(v, w_exp) : v;
 }
 
 // Vout[i + rank[k] * ldvo] = Vw[i][k]   (32 x 32 tiles through LDS)
@@ -1249,23 +1354,28 @@ __global__ __launch_bounds__(256) void k_permute_out(const double* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(256) void k_rank_b(BMat* __restrict__ mats) {
+__global__ __launch_bounds__(256) void k_rank_b(BMat* __restrict__ mats, int sort) {
   extern __shared__ double sd[];
   BMat& b = mats[blockIdx.y];
   const int n = b.n;
   if ((int)blockIdx.x * 256 >= n) return;
-  for (int l = threadIdx.x; l < n; l += 256) sd[l] = b.diag[l];
+  if (sort)
+    for (int l = threadIdx.x; l < n; l += 256) sd[l] = b.diag[l];
   __syncthreads();
   int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
-  double v = sd[k];
-  int r = 0;
-  for (int l = 0; l < n; ++l) {
-    double u = sd[l];
-    r += (u < v) || (u == v && l < k);
+  double v = sort ? sd[k] : b.diag[k];
+  int r = k;
+  if (sort) {
+    r = 0;
+    for (int l = 0; l < n; ++l) {
+      double u = sd[l];
+      r += (u < v) || (u == v && l < k);
+    }
   }
   b.rank[k] = r;
-  b.Wout[r] = v;
+  // the member's input was scaled by 2^a_exp
+  b.Wout[r] = b.a_exp ? ldexp(v, -b.a_exp) : v;
 }
 
 __global__ __launch_bounds__(256) void k_permute_out_b(BMat* __restrict__ mats) {
@@ -1286,28 +1396,30 @@ __global__ __launch_bounds__(256) void k_permute_out_b(BMat* __restrict__ mats) 
   }
 }
 
-hipError_t launch_sort_output_b(BMat* m, int count, int nmax, hipStream_t s) {
+hipError_t launch_sort_output_b(BMat* m, int count, int nmax, int sort, hipStream_t s) {
   size_t sh = (size_t)nmax * 8;
   if (sh > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_rank_b,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_rank_b, dim3((nmax + 255) / 256, count), dim3(256), sh, s, m);
+  hipLaunchKernelGGL(k_rank_b, dim3((nmax + 255) / 256, count), dim3(256), sh, s, m, sort);
   int nb = (nmax + kTile - 1) / kTile;
   hipLaunchKernelGGL(k_permute_out_b, dim3(nb, nb, count), dim3(256), 0, s, m);
   return hipGetLastError();
 }
 
 hipError_t launch_sort_output(const double* diag, int n, const double* Vw, int ldw, double* W,
-                              double* Vout, int ldvo, int* rank, hipStream_t s) {
+                              double* Vout, int ldvo, int* rank, int sort, int w_exp,
+                              hipStream_t s) {
   size_t sh = (size_t)n * 8;
   if (sh > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_rank,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_rank, dim3((n + 255) / 256), dim3(256), sh, s, diag, n, rank, W);
+  hipLaunchKernelGGL(k_rank, dim3((n + 255) / 256), dim3(256), sh, s, diag, n, rank, W, sort,
+                     w_exp);
   if (Vout) {
     int nb = (n + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_permute_out, dim3(nb, nb), dim3(256), 0, s, Vw, n, ldw, rank, Vout,

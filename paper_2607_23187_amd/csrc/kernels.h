@@ -58,14 +58,25 @@ hipError_t launch_init_rows(const JDesc& d, hipStream_t s);
 hipError_t launch_get_diag(const double* A, int n, int ld, double* diag, hipStream_t s);
 // Runs the pivoted Jacobi until the stop rule holds, the cap is reached or the log is
 // full (then ctl->done stays 0 and the launch can be repeated after the log is drained).
-hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, hipStream_t s);
+// lds_mode: A held in LDS (jacobi_fits_lds); otherwise mirror selects the HBM update mode
+// (rows and columns p, q stored) over the timestamp mode (rows only).
+hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, bool mirror,
+                         hipStream_t s);
 bool jacobi_fits_lds(int n);
 // V[i][:] <- V[i][:] * G_1 ... G_m for every row (rotations of `log`, in order).
 hipError_t launch_apply_log(double* V, int n, int ldv, const RotEntry* log, long long m,
                             hipStream_t s);
 hipError_t launch_set_identity(double* V, int n, int ldv, hipStream_t s);
+// W[rank[k]] = 2^w_exp diag[k], Vout[:, rank[k]] = column k of Vw; rank ascending and
+// stable when sort != 0, else rank[k] = k.
 hipError_t launch_sort_output(const double* diag, int n, const double* Vw, int ldw, double* W,
-                              double* Vout, int ldvo, int* perm, hipStream_t s);
+                              double* Vout, int ldvo, int* perm, int sort, int w_exp,
+                              hipStream_t s);
+// out[0] = max |a_ij|
+hipError_t launch_maxabs(const double* A, int n, int ld, double* partial, double* out,
+                         hipStream_t s);
+// A <- 2^e A, diag <- 2^e diag (diag may be null)
+hipError_t launch_scale(double* A, int n, int ld, double* diag, int e, hipStream_t s);
 hipError_t launch_copy_pivots(const RotEntry* log, long long m, int* out, hipStream_t s);
 
 // FP64 GEMM on MFMA: C = alpha * op(A) * B + beta * Cin (all row-major, square n).
@@ -89,10 +100,11 @@ hipError_t launch_offnorm(const double* A, int n, int ld, double* partial, doubl
 // FP32 preconditioner.
 size_t precond_f32_bytes(int n);
 // Sweeps stop at off(A32) <= tol ||A32||_F, when a sweep leaves off(A32) >= rho times its
-// value before the sweep, or after max_sweeps.
+// value before the sweep, or after max_sweeps.  block: rows per block (16, 32; 0 = chosen
+// by n); graphs: replay the sweeps from captured HIP graphs.
 hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq,
                            void* scratch, int max_sweeps, double tol, double rho, int* sweeps,
-                           hipStream_t s);
+                           int block, bool graphs, hipStream_t s);
 
 // ------------------------------------------------------------------ batches
 // One matrix of a batch (device memory).  The batched kernels take an array of these and
@@ -117,11 +129,14 @@ struct BMat {
   int j_done;
   // Newton-Schulz: set once the member has converged; its later steps are exact no-ops
   int ns_done;
+  // the input was scaled by 2^a_exp (exact) to keep squares and FP32 values in range; the
+  // eigenvalues are scaled back
+  int a_exp;
 };
 
 // Per-matrix results gathered into one array, so the host reads a batch with one copy.
 struct BInfo {
-  double normF, rnorm;
+  double normF, rnorm, maxabs;
   int nonfinite, pad;
   JCtl ctl;
 };
@@ -143,10 +158,15 @@ hipError_t launch_init_rows_b(BMat* m, int count, int nmax, int pivot, int use_c
 // Persistent Jacobi over the matrices idx[0..count) (one workgroup per matrix at a time,
 // taken from a device counter in the given order); lds_mode as for launch_jacobi.
 hipError_t launch_jacobi_queue(BMat* m, const int* idx, int count, int nmax, int pivot,
-                               bool lds_mode, int threads, int* counter, int grid,
+                               bool lds_mode, bool mirror, int threads, int* counter, int grid,
                                hipStream_t s);
 hipError_t launch_apply_log_b(BMat* m, int count, int nmax, hipStream_t s);
-hipError_t launch_sort_output_b(BMat* m, int count, int nmax, hipStream_t s);
+hipError_t launch_sort_output_b(BMat* m, int count, int nmax, int sort, hipStream_t s);
+// scal[out_slot] = max |a_ij| of the matrix at `off`
+hipError_t launch_maxabs_b(BMat* m, int count, int nmax, size_t off, int out_slot,
+                           hipStream_t s);
+// members with a_exp != 0: matrix at `off` and diag scaled by 2^a_exp
+hipError_t launch_scale_b(BMat* m, int count, int nmax, size_t off, hipStream_t s);
 // ns_mask: members with ns_done get C = 0 (no product), resp. no identity added
 hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
                           size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s,

@@ -15,8 +15,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdio>
-#include <cstdlib>
 #include <vector>
 
 #include "device_common.h"
@@ -787,10 +785,9 @@ __global__ void k_gather_q(const float* __restrict__ V, int n, int ldv, double* 
 // (n <= 64) and above n = 2048, where the per-round passes over A and V dominate and fewer
 // rounds pay; 16 in between, where the subproblem solves dominate and a 32 x 32 inner round
 // is cheaper (measured at n = 1024: 32.8 vs 36.4 ms; at n = 4096: 423 vs 297 ms).
-// JE_F32_BLOCK=16 or 32 overrides the choice.
-static int block_rows(int n) {
-  const char* e = std::getenv("JE_F32_BLOCK");
-  if (e && (std::atoi(e) == 16 || std::atoi(e) == 32)) return std::atoi(e);
+// `request` 16 or 32 overrides the choice (0: automatic).
+static int block_rows(int n, int request) {
+  if (request == 16 || request == 32) return request;
   return (n <= 64 || n > 2048) ? 32 : 16;
 }
 
@@ -810,34 +807,14 @@ size_t precond_f32_bytes(int n) {
   return std::max(blocked_bytes<16>(n), blocked_bytes<32>(n));
 }
 
-// Graph replay of the sweeps (JE_F32_GRAPH=1).  Off by default: on MI355X it measures the
+// Graph replay of the sweeps (`graph` argument) is off by default: on MI355X it measures the
 // same as direct launches (n = 1024: 31.9 vs 31.0 ms for the FP32 stage; n = 4096: 274 vs
 // 273 ms) -- the cost between dependent launches is on the device, not in the host calls.
-static bool graphs_enabled() {
-  const char* e = std::getenv("JE_F32_GRAPH");
-  return e && e[0] == '1';
-}
-
-// JE_F32_TRACE=1: off(A32)/||A32||_F after every sweep of a single solve, on stderr.
-static bool f32_trace() {
-  static const bool on = std::getenv("JE_F32_TRACE") != nullptr;
-  return on;
-}
-
-// Fused rounds (the A update of a round launched with the next round's solves); JE_F32_FUSED=0
-// launches every A update on its own.
-static bool fused_enabled() {
-  static const bool on = [] {
-    const char* e = std::getenv("JE_F32_FUSED");
-    return !(e && e[0] == '0');
-  }();
-  return on;
-}
 
 template <int PB>
 static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int ldq,
                               void* scratch, int max_sweeps, double tol, double rho, int* sweeps,
-                              hipStream_t s) {
+                              bool graphs, hipStream_t s) {
   constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT;
   const int np = (n + PM - 1) / PM * PM, nb = np / PB, nb2 = nb / 2, rounds = nb - 1;
   char* p = (char*)scratch;
@@ -917,7 +894,7 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
   // carries the previous round's A update, and the sweep ends with that update for its
   // last round.  A sweep swaps the buffers nb - 2 times (even), so every sweep starts from
   // the same buffer.
-  const bool fused = fused_enabled() && nb >= 4;
+  const bool fused = nb >= 4;
   const int na = nb2 * (nb2 - 1) / 2;
   auto sweep_launches = [&](hipStream_t st) {
     for (int r = 0; r < rounds; ++r, ++g) {
@@ -950,7 +927,7 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
   // From the second sweep on, a sweep's launches depend only on the parity of its first
   // round (rounds per sweep is odd): each parity's sequence is captured once into a graph
   // (on a private stream) and replayed when graphs are enabled.
-  const bool use_graph = graphs_enabled() && nb2 > 1;
+  const bool use_graph = graphs && nb2 > 1;
   hipStream_t cs = nullptr;
   hipGraphExec_t ex[2] = {nullptr, nullptr};
   auto cleanup = [&]() {
@@ -997,9 +974,6 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
     if ((e = off_norm()) != hipSuccess) { cleanup(); return e; }
     off = h[0];
     nrm = h[1];
-    if (f32_trace())
-      std::fprintf(stderr, "JE_F32_TRACE n=%d tol=%g rho=%g sweep=%d off/norm=%.3e ratio=%.3f\n", n,
-                   tol, rho, sw, off / nrm, off / prev);
     if (nb == 2 || off >= rho * prev) break;
   }
   cleanup();
@@ -1346,10 +1320,12 @@ hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int*
 }
 
 hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq, void* scratch,
-                           int max_sweeps, double tol, double rho, int* sweeps, hipStream_t s) {
-  if (block_rows(n) == 16)
-    return run_blocked<16>(Asym, n, ld, Q, ldq, scratch, max_sweeps, tol, rho, sweeps, s);
-  return run_blocked<32>(Asym, n, ld, Q, ldq, scratch, max_sweeps, tol, rho, sweeps, s);
+                           int max_sweeps, double tol, double rho, int* sweeps, int block,
+                           bool graphs, hipStream_t s) {
+  if (block_rows(n, block) == 16)
+    return run_blocked<16>(Asym, n, ld, Q, ldq, scratch, max_sweeps, tol, rho, sweeps, graphs,
+                           s);
+  return run_blocked<32>(Asym, n, ld, Q, ldq, scratch, max_sweeps, tol, rho, sweeps, graphs, s);
 }
 
 }  // namespace je

@@ -34,7 +34,10 @@ class Opts(ctypes.Structure):
                 ("fp32_max_sweeps", ctypes.c_int), ("fp32_passes", ctypes.c_int),
                 ("max_rotations", ctypes.c_longlong),
                 ("abs_thr", ctypes.c_double), ("pivot_log", ctypes.c_void_p),
-                ("pivot_log_cap", ctypes.c_longlong), ("split_gemm", ctypes.c_int)]
+                ("pivot_log_cap", ctypes.c_longlong), ("split_gemm", ctypes.c_int),
+                ("sort", ctypes.c_int), ("update_mode", ctypes.c_int), ("tune", ctypes.c_int),
+                ("graph", ctypes.c_int), ("profile", ctypes.c_int),
+                ("fp32_block", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -44,14 +47,18 @@ class Stats(ctypes.Structure):
                 ("sweeps32", ctypes.c_int), ("status", ctypes.c_int),
                 ("ms_precond", ctypes.c_float), ("ms_gemm", ctypes.c_float),
                 ("ms_jacobi", ctypes.c_float), ("ms_finalize", ctypes.c_float),
-                ("ms_jacobi_kernel", ctypes.c_float), ("a_hat_off", ctypes.c_double)]
+                ("ms_jacobi_kernel", ctypes.c_float), ("a_hat_off", ctypes.c_double),
+                ("prof_ns", ctypes.c_double * 6), ("ms_apply_log", ctypes.c_float),
+                ("scale_exp", ctypes.c_int)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["prof_ns"] = list(self.prof_ns)
+        return d
 
 
 EXPORTS = ["je_opts_default", "jacobi_eigh", "jacobi_eigh_ex", "jacobi_eigh_batched",
-           "jacobi_svd",
+           "jacobi_eigh_batched_host", "jacobi_svd",
            "jacobi_workspace_size", "jacobi_strerror", "jacobi_release",
            "jacobi_server_create", "jacobi_server_submit", "jacobi_server_poll",
            "jacobi_server_pending", "jacobi_server_clock", "jacobi_server_destroy"]
@@ -83,11 +90,15 @@ def load(path: str = LIB_PATH):
     L.jacobi_eigh_ex.argtypes = [vp, ip, ip, vp, vp, ip, dp, ip, ip, ctypes.POINTER(Opts),
                                  ctypes.POINTER(Stats), vp]
     L.jacobi_eigh_ex.restype = ctypes.c_int
-    L.jacobi_eigh_batched.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(ip),
-                                      ctypes.POINTER(ip), ctypes.POINTER(vp), ctypes.POINTER(vp),
-                                      ctypes.POINTER(ip), dp, ip, ip, ctypes.POINTER(Opts),
-                                      ctypes.POINTER(ip), ctypes.POINTER(Stats), vp]
+    L.jacobi_eigh_batched.argtypes = [ip, vp, vp, vp, vp, vp, dp, ip, ip,
+                                      ctypes.POINTER(Opts), vp, vp]
     L.jacobi_eigh_batched.restype = ctypes.c_int
+    L.jacobi_eigh_batched_host.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(ip),
+                                           ctypes.POINTER(ip), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), ctypes.POINTER(ip), dp, ip, ip,
+                                           ctypes.POINTER(Opts), ctypes.POINTER(ip),
+                                           ctypes.POINTER(Stats), vp]
+    L.jacobi_eigh_batched_host.restype = ctypes.c_int
     L.jacobi_svd.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, dp, ip, ip,
                              ctypes.POINTER(Opts), ctypes.POINTER(Stats), vp]
     L.jacobi_svd.restype = ctypes.c_int
@@ -141,10 +152,34 @@ def _check_device_tensor(a: torch.Tensor):
         raise ValueError("A must be square")
 
 
+_UPDATE_MODES = {"auto": 0, "mirror": 1, "timestamp": 2, 0: 0, 1: 1, 2: 2}
+
+
+def _opts(stop="cert", polish_v=True, fp32_max_sweeps=20, fp32_passes=2, split_gemm=False,
+          max_rotations=0, abs_thr=0.0, sort=True, update_mode="auto", tune=True, graph=False,
+          profile=False, fp32_block=0) -> Opts:
+    o = default_opts()
+    o.stop = _STOPS[stop]
+    o.polish_v = 1 if polish_v else 0
+    o.fp32_max_sweeps = int(fp32_max_sweeps)
+    o.fp32_passes = int(fp32_passes)
+    o.split_gemm = int(split_gemm)
+    o.max_rotations = int(max_rotations)
+    o.abs_thr = float(abs_thr)
+    o.sort = 1 if sort else 0
+    o.update_mode = _UPDATE_MODES[update_mode]
+    o.tune = 1 if tune else 0
+    o.graph = 1 if graph else 0
+    o.profile = 1 if profile else 0
+    o.fp32_block = int(fp32_block)
+    return o
+
+
 def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop="cert",
          want_v: bool = True, abs_thr: float = 0.0, max_rotations: int = 0,
          polish_v: bool = True, fp32_max_sweeps: int = 20, fp32_passes: int = 2,
-         pivot_log_cap: int = 0, split_gemm: bool = False,
+         pivot_log_cap: int = 0, split_gemm: bool = False, sort: bool = True,
+         update_mode="auto", graph: bool = False, profile: bool = False, fp32_block: int = 0,
          stream: torch.cuda.Stream | None = None, check: bool = True) -> Result:
     """Eigen-decomposition of the symmetric float64 CUDA tensor ``a``.
 
@@ -157,14 +192,8 @@ def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop=
     a = a.contiguous()
     w = torch.empty(n, dtype=torch.float64, device=a.device)
     vt = torch.empty((n, n), dtype=torch.float64, device=a.device) if want_v else None
-    o = default_opts()
-    o.stop = _STOPS[stop]
-    o.polish_v = 1 if polish_v else 0
-    o.fp32_max_sweeps = int(fp32_max_sweeps)
-    o.fp32_passes = int(fp32_passes)
-    o.split_gemm = 1 if split_gemm else 0
-    o.max_rotations = int(max_rotations)
-    o.abs_thr = float(abs_thr)
+    o = _opts(stop, polish_v, fp32_max_sweeps, fp32_passes, split_gemm, max_rotations, abs_thr,
+              sort, update_mode, True, graph, profile, fp32_block)
     plog = None
     if pivot_log_cap > 0:
         plog = torch.full((pivot_log_cap, 2), -1, dtype=torch.int32, device=a.device)
@@ -237,8 +266,11 @@ def svd(b: torch.Tensor, tol: float = 2.0 ** -53, pivot="gap", precond="none",
 
 def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", precond="fp32",
                  stop="cert", want_v: bool = True, max_rotations: int = 0,
+                 polish_v: bool = True, abs_thr: float = 0.0, sort: bool = True,
+                 update_mode="auto", tune: bool = True, fp32_passes: int = 2,
                  stream: torch.cuda.Stream | None = None):
-    """Batch of independent problems of possibly different sizes."""
+    """Batch of independent problems of possibly different sizes (host-array form, with
+    per-problem statistics)."""
     L = load()
     b = len(mats)
     for m in mats:
@@ -254,20 +286,50 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
     ns = IA(*[m.shape[0] for m in mats])
     info = IA()
     stats = (Stats * b)()
-    o = default_opts()
-    o.stop = _STOPS[stop]
-    o.max_rotations = int(max_rotations)
+    o = _opts(stop, polish_v, 20, fp32_passes, False, max_rotations, abs_thr, sort,
+              update_mode, tune)
     s = stream if stream is not None else torch.cuda.current_stream()
-    status = L.jacobi_eigh_batched(b, a_p, ns, ns, w_p, v_p, ns, float(tol), _PIVOTS[pivot],
-                                   _PRECONDS[precond], ctypes.byref(o), info, stats,
-                                   ctypes.c_void_p(s.cuda_stream))
+    status = L.jacobi_eigh_batched_host(b, a_p, ns, ns, w_p, v_p, ns, float(tol),
+                                        _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o),
+                                        info, stats, ctypes.c_void_p(s.cuda_stream))
     if status < 0:
-        raise RuntimeError(f"jacobi_eigh_batched: argument {-status} invalid")
+        raise RuntimeError(f"jacobi_eigh_batched_host: argument {-status} invalid")
     out = []
     for i in range(b):
         out.append(Result(ws[i], vs[i].t() if vs is not None else None, int(info[i]),
                           stats[i].as_dict(), None))
     return status, out
+
+
+def eigh_batched_device(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap",
+                        precond="fp32", stop="cert", want_v: bool = True,
+                        max_rotations: int = 0, stream: torch.cuda.Stream | None = None):
+    """The same through the device-array form (jacobi_eigh_batched): pointer, size and
+    status arrays live in device memory.  Returns (status, [(w, v, info)])."""
+    L = load()
+    b = len(mats)
+    for m in mats:
+        _check_device_tensor(m)
+    mats = [m.contiguous() for m in mats]
+    dev = mats[0].device
+    ws = [torch.empty(m.shape[0], dtype=torch.float64, device=dev) for m in mats]
+    vs = [torch.empty_like(m) for m in mats] if want_v else None
+    a_p = torch.tensor([m.data_ptr() for m in mats], dtype=torch.int64, device=dev)
+    w_p = torch.tensor([x.data_ptr() for x in ws], dtype=torch.int64, device=dev)
+    v_p = (torch.tensor([x.data_ptr() for x in vs], dtype=torch.int64, device=dev)
+           if vs is not None else None)
+    ns = torch.tensor([m.shape[0] for m in mats], dtype=torch.int32, device=dev)
+    info = torch.full((b,), -99, dtype=torch.int32, device=dev)
+    o = _opts(stop, True, 20, 2, False, max_rotations)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    status = L.jacobi_eigh_batched(b, a_p.data_ptr(), ns.data_ptr(), ns.data_ptr(),
+                                   w_p.data_ptr(), v_p.data_ptr() if v_p is not None else None,
+                                   float(tol), _PIVOTS[pivot], _PRECONDS[precond],
+                                   ctypes.byref(o), info.data_ptr(),
+                                   ctypes.c_void_p(s.cuda_stream))
+    infos = info.cpu().tolist()
+    return status, [(ws[i], vs[i].t() if vs is not None else None, infos[i]) for i in range(b)]
 
 
 class Server:

@@ -34,6 +34,7 @@ def test_defaults_and_strings():
     o = J.default_opts()
     assert (o.stop, o.polish_v, o.fp32_max_sweeps, o.fp32_passes, o.max_rotations, o.abs_thr,
             o.split_gemm) == (0, 1, 20, 2, 0, 0.0, 0)
+    assert (o.sort, o.update_mode, o.tune, o.graph, o.profile, o.fp32_block) == (1, 0, 1, 0, 0, 0)
     assert J.strerror(0) == "ok"
     assert "NaN" in J.strerror(J.ERR_NONFINITE)
     assert J.strerror(-3) == "invalid argument"
@@ -58,17 +59,54 @@ def test_argument_errors_follow_lapack_info_convention():
     assert _ex(fake, 4, 4, fake, None, 4, float("nan")) == -7
     assert _ex(fake, 4, 4, fake, None, 4, 1e-12, pivot=7) == -8
     assert _ex(fake, 4, 4, fake, None, 4, 1e-12, precond=5) == -9
-    o = J.default_opts()
-    o.stop = 9
-    assert _ex(fake, 4, 4, fake, None, 4, 1e-12, opts=o) == -10
+    for field, bad in (("stop", 9), ("sort", 2), ("update_mode", 3), ("tune", -1),
+                       ("graph", 2), ("profile", 5), ("fp32_block", 24), ("fp32_passes", 3)):
+        o = J.default_opts()
+        setattr(o, field, bad)
+        assert _ex(fake, 4, 4, fake, None, 4, 1e-12, opts=o) == -10, field
     # n = 0 is a no-op that needs no device
     assert _ex(fake, 0, 1, fake, None, 1, 1e-12) == 0
     # too large
     assert _ex(fake, J.MAX_N + 1, J.MAX_N + 1, fake, None, J.MAX_N + 1, 1e-12) == J.ERR_TOO_LARGE
     L = J.load()
-    IA = ctypes.c_int * 1
-    assert L.jacobi_eigh_batched(-1, None, None, None, None, None, None, 1e-12, 1, 1, None,
-                                 None, None, None) == -1
+    assert L.jacobi_eigh_batched(-1, None, None, None, None, None, 1e-12, 1, 1, None,
+                                 None, None) == -1
+    assert L.jacobi_eigh_batched(0, None, None, None, None, None, 1e-12, 1, 1, None,
+                                 None, None) == 0
+    assert L.jacobi_eigh_batched(2, None, fake, fake, fake, None, 1e-12, 1, 1, None,
+                                 fake, None) == -2
+    assert L.jacobi_eigh_batched(2, fake, fake, fake, fake, None, 1e-12, 1, 1, None,
+                                 None, None) == -11
+    assert L.jacobi_eigh_batched_host(-1, None, None, None, None, None, None, 1e-12, 1, 1,
+                                      None, None, None, None) == -1
+
+
+def test_batched_host_form_argument_numbers():
+    """The host-array batched form numbers its arguments A = 2 ... opts = 11 and rejects the
+    whole batch before any device work."""
+    L = J.load()
+    VP, IA = ctypes.c_void_p * 2, ctypes.c_int * 2
+    fake = 0x1000
+    a, w = VP(fake, fake), VP(fake, fake)
+    n, lda, info = IA(4, 4), IA(4, 4), IA(0, 0)
+
+    def call(a=a, n=n, lda=lda, w=w, v=None, ldv=None, tol=1e-12, pivot=1, precond=1, opts=None):
+        return L.jacobi_eigh_batched_host(2, a, n, lda, w, v, ldv, tol, pivot, precond,
+                                          ctypes.byref(opts) if opts is not None else None,
+                                          info, None, None)
+
+    assert call(a=VP(fake, None)) == -2 and info[1] == -2
+    assert call(n=IA(4, -3)) == -3
+    assert call(lda=IA(4, 2)) == -4
+    assert call(w=VP(None, fake)) == -5
+    assert call(v=VP(fake, fake), ldv=IA(4, 3)) == -7
+    assert call(tol=-1.0) == -8
+    assert call(pivot=5) == -9
+    assert call(precond=4) == -10
+    o = J.default_opts()
+    o.update_mode = 7
+    assert call(opts=o) == -11
+    assert call(n=IA(4, J.MAX_N + 1), lda=IA(4, J.MAX_N + 1)) == J.ERR_TOO_LARGE
 
 
 def test_server_rejects_bad_arguments():

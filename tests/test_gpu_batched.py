@@ -119,15 +119,13 @@ def test_batched_nonfinite_member():
     assert status == J.ERR_NONFINITE
 
 
-def test_tuned_shapes_do_not_change_results(monkeypatch):
+def test_tuned_shapes_do_not_change_results():
     """The workgroup shapes picked by the size-class tuner change no bit of the results."""
     probs = problems([40, 100, 128, 150, 300, 500], 7900)
     tol = min(tol_for(a, lam) for a, lam in probs)
     mats = [torch.from_numpy(a).cuda() for a, _ in probs]
-    monkeypatch.setenv("JE_TUNE", "0")
-    _, r0 = J.eigh_batched(mats, tol=tol, pivot="gap", precond="fp32")
-    monkeypatch.setenv("JE_TUNE", "1")
-    _, r1 = J.eigh_batched(mats, tol=tol, pivot="gap", precond="fp32")
+    _, r0 = J.eigh_batched(mats, tol=tol, pivot="gap", precond="fp32", tune=False)
+    _, r1 = J.eigh_batched(mats, tol=tol, pivot="gap", precond="fp32", tune=True)
     for x, y in zip(r0, r1):
         assert x.stats["rotations"] == y.stats["rotations"]
         assert torch.equal(x.w, y.w)
@@ -135,18 +133,16 @@ def test_tuned_shapes_do_not_change_results(monkeypatch):
 
 
 @pytest.mark.parametrize("pivot", ["greedy", "gap"])
-def test_batched_timestamp_and_mirror_modes_agree(pivot, monkeypatch):
+def test_batched_timestamp_and_mirror_modes_agree(pivot):
     """The persistent batched launch keeps A current either by mirrored column stores
-    (JE_MIRROR=1) or by per-row write timestamps (the default): same arithmetic, so the same
+    (update_mode mirror) or by per-row write timestamps (the default): same arithmetic, so the same
     rotation counts and bits, including across log drains (without the preconditioner the
     520-row matrix needs more rotations than one log holds)."""
     probs = problems([129, 200, 300, 520], 8100)
     tol = min(tol_for(a, lam) for a, lam in probs)
     mats = [torch.from_numpy(a).cuda() for a, _ in probs]
     say("batched modes", pivot)
-    monkeypatch.setenv("JE_MIRROR", "1")
-    _, rm = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="none")
-    monkeypatch.delenv("JE_MIRROR")
+    _, rm = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="none", update_mode="mirror")
     _, rt = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="none")
     for x, y in zip(rm, rt):
         assert x.status == y.status == J.OK

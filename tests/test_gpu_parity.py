@@ -60,11 +60,11 @@ def test_worked_example_on_gpu():
         assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a)))
 
 
-def _parity_case(a, pivot, stop, thr, capmul=40):
+def _parity_case(a, pivot, stop, thr, capmul=40, update_mode="auto"):
     n = a.shape[0]
     cap = capmul * n * n + 64
     r = J.eigh(gpu(a), precond="none", pivot=pivot, stop=stop, abs_thr=thr,
-               pivot_log_cap=cap, polish_v=True)
+               pivot_log_cap=cap, polish_v=True, update_mode=update_mode)
     so = {"cert": O.STOP_CERT, "off": O.STOP_OFF, "score": O.STOP_SCORE}[stop]
     ref = O.jacobi(a, pivot=pivot, stop=so, thr=thr, scan=1, want_vj=False)
     return r, ref
@@ -111,15 +111,14 @@ def test_pivot_sequence_identical_preconditioned(n, pivot):
 
 @pytest.mark.parametrize("n", [129, 300, 520])
 @pytest.mark.parametrize("pivot", [J.GREEDY, J.GAP])
-def test_pivot_sequence_identical_timestamp_mode(n, pivot, monkeypatch):
+def test_pivot_sequence_identical_timestamp_mode(n, pivot):
     """The HBM-resident kernel's other storage mode (rows only, per-row write timestamps
     pick the newer copy of each entry) gives the same pivots and eigenvalues."""
     say("timestamp-mode parity", n, pivot)
-    monkeypatch.setenv("JE_MIRROR", "0")
     p = I.clustered(n, seed=3500 + n, size=8, offset=1e-10)
     ah = oracle_a_hat(p)
     thr = cert_thr(ah, np.max(np.abs(p.lam)), n)
-    r, ref = _parity_case(ah, pivot, "cert", thr)
+    r, ref = _parity_case(ah, pivot, "cert", thr, update_mode="timestamp")
     assert r.status == J.OK
     assert r.stats["rotations"] == ref.rotations
     assert np.array_equal(r.pivots.cpu().numpy(), ref.pivots)
@@ -253,18 +252,16 @@ def test_repeatable_bitwise():
 
 
 @pytest.mark.parametrize("n", [300, 1024])
-def test_fp32_sweep_graph_replay_equals_direct(n, monkeypatch):
+def test_fp32_sweep_graph_replay_equals_direct(n):
     """The FP32 sweeps replayed from captured graphs (with the stop test's own kernels and
     host synchronisations between replays) give the same bits as direct launches."""
     say("graph replay", n)
     p = I.config_c2(n=n)
     a = gpu(p.a)
     tol = 10 * n * U * np.max(np.abs(p.lam)) / np.linalg.norm(p.a)
-    monkeypatch.setenv("JE_F32_GRAPH", "0")
-    r0 = J.eigh(a, tol=tol, pivot="gap", precond="fp32")
-    monkeypatch.setenv("JE_F32_GRAPH", "1")
-    r1 = J.eigh(a, tol=tol, pivot="gap", precond="fp32")
-    r2 = J.eigh(a, tol=tol, pivot="gap", precond="fp32")
+    r0 = J.eigh(a, tol=tol, pivot="gap", precond="fp32", graph=False)
+    r1 = J.eigh(a, tol=tol, pivot="gap", precond="fp32", graph=True)
+    r2 = J.eigh(a, tol=tol, pivot="gap", precond="fp32", graph=True)
     assert r0.stats["sweeps32"] >= 4  # at least two replays of each parity's graph
     for r in (r1, r2):
         assert r.stats["rotations"] == r0.stats["rotations"]
