@@ -165,6 +165,23 @@ int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ld
                    int pivot, int precond, const je_opts* opts, je_stats* stats,
                    je_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): jacobi_eigh_ex with the same arguments,
+ * results and statistics (the timings stay 0), whose workspace is a fixed array of
+ * JE_NOALLOC_BYTES in device memory that the library holds on each device it runs on until
+ * the process ends, instead of the allocated workspace pool.  It calls no device allocation
+ * routine and creates no events or graphs (opts->graph is ignored).  n <= JE_NOALLOC_MAX_N,
+ * else JE_ERR_TOO_LARGE before any device work.  Every call on a device shares that
+ * device's array and leaves its contents there: calls on one device must not overlap (calls
+ * of one process are serialised internally and return when done; two processes each hold
+ * their own array).  The rotation log holds 2^16 entries, so longer solves drain it more
+ * often (same results). */
+#define JE_NOALLOC_MAX_N 512
+#define JE_NOALLOC_BYTES (24u << 20)
+int jacobi_eigh_noalloc(const double* A, int n, int lda, double* W, double* V, int ldv,
+                        double tol, int pivot, int precond, const je_opts* opts,
+                        je_stats* stats, je_stream stream);
+
 /* `batch` independent problems of (possibly different) sizes solved together: the same
  * phases as jacobi_eigh_ex, each launch covering the whole batch, the FP64 phase as
  * persistent launches whose workgroups take the next matrix from a device queue.  Every

@@ -175,12 +175,16 @@ WS ws_carve(void* base, int n, int precond, long long log_cap) {
     }                                   \
   } while (0)
 
+// Elapsed time on a stream between construction and stop() (HIP events).  Timers are
+// switched off per thread for the entry point that must not create runtime objects.
+thread_local bool t_timers_off = false;
+
 struct Timer {
   hipEvent_t a, b;
   hipStream_t s;
   bool ok;
   explicit Timer(hipStream_t st) : s(st) {
-    ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    ok = !t_timers_off && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
     if (ok) (void)hipEventRecord(a, s);
   }
   float stop() {
@@ -262,20 +266,18 @@ int precond_q(const double* Asym, int n, int ld, double*& X, double*& Xo, double
   return JE_OK;
 }
 
+// One solve in the workspace at `base` (ws_bytes(n, precond, cap) bytes, device memory).
 int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, double tol,
-              int pivot, int precond, const je_opts& o, je_stats* st, hipStream_t s) {
+              int pivot, int precond, const je_opts& o, je_stats* st, hipStream_t s,
+              void* base, long long cap) {
   const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
-  const long long cap = log_cap_for(n, maxrot);
-  int err = JE_OK;
-  void* base = pool_get(ws_bytes(n, precond, cap), &err);
-  if (!base) return err;
   WS w = ws_carve(base, n, precond, cap);
   const int ld = ld_of(n);
   je_stats S{};
 
   // ---- 1. symmetric copy, finiteness, range, ||A||_F
   Timer tp(s);
-  HIPCHK(hipMemsetAsync(w.flag, 0, 4, s));
+  HIPCHK(launch_zero_words(w.flag, 1, s));
   HIPCHK(launch_symcopy(Au, n, lda, w.Asym, ld, w.diag, nullptr, w.flag, s));
   HIPCHK(launch_maxabs(w.Asym, n, ld, w.rowsq, w.scal + 4, s));
   int flag = 0;
@@ -345,11 +347,11 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   d.log = w.log; d.log_cap = cap; d.ctl = w.ctl;
   d.thr = thr; d.maxrot = maxrot; d.pivot = pivot; d.stop = o.stop;
   if (precond) HIPCHK(launch_get_diag(Ajac, n, ld, w.diag, s));
-  HIPCHK(hipMemsetAsync(w.ctl, 0, sizeof(JCtl), s));
+  HIPCHK(launch_zero_words(w.ctl, sizeof(JCtl) / 4, s));
   // opts.profile: per-phase timers of the Jacobi kernel
   const bool profile = o.profile != 0;
   if (profile) {
-    HIPCHK(hipMemsetAsync(w.prof, 0, 64, s));
+    HIPCHK(launch_zero_words(w.prof, 16, s));
     d.prof = w.prof;
   }
   HIPCHK(launch_init_rows(d, s));
@@ -1103,6 +1105,35 @@ int check_args(const double* A, int n, int lda, const double* W, const double* V
   return 0;
 }
 
+// ------------------------------------------------------------------ no-allocation solves
+// Workspace of jacobi_eigh_noalloc: a file-scope device array (one copy per device, held
+// until the process ends).  Its size covers ws_bytes(JE_NOALLOC_MAX_N, precond = 1,
+// kNoAllocLogCap); the entry point checks every call against it.
+constexpr long long kNoAllocLogCap = 1ll << 16;
+constexpr size_t kNoAllocBytes = JE_NOALLOC_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on each device, taken once with that device current (in host
+// code the array's name is only a stand-in for the symbol).
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+void* scratch_address(int* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { *err = JE_ERR_DEVICE; return nullptr; }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    *err = JE_ERR_DEVICE;
+    return nullptr;
+  }
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1154,7 +1185,52 @@ int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ld
     if (stats) stats->normF = std::fabs(v);
     return JE_OK;
   }
-  return solve_one(A, n, lda, W, V, ldv, tol, pivot, precond, o, stats, s);
+  const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
+  const long long cap = log_cap_for(n, maxrot);
+  int err = JE_OK;
+  void* base = pool_get(ws_bytes(n, precond, cap), &err);
+  if (!base) return err;
+  return solve_one(A, n, lda, W, V, ldv, tol, pivot, precond, o, stats, s, base, cap);
+}
+
+int jacobi_eigh_noalloc(const double* A, int n, int lda, double* W, double* V, int ldv,
+                        double tol, int pivot, int precond, const je_opts* opts,
+                        je_stats* stats, je_stream stream) {
+  je_opts o;
+  if (opts) o = *opts;
+  else je_opts_default(&o);
+  int a = check_args(A, n, lda, W, V, ldv, tol, pivot, precond, o);
+  if (a) return a;
+  if (n > JE_NOALLOC_MAX_N) return JE_ERR_TOO_LARGE;
+  o.graph = 0;  // graph instantiation would create runtime objects
+  hipStream_t s = (hipStream_t)stream;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n == 0) return JE_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (n == 1) {
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, A, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!std::isfinite(v)) return JE_ERR_NONFINITE;
+    HIPCHK(hipMemcpyAsync(W, A, 8, hipMemcpyDeviceToDevice, s));
+    if (V) {
+      static const double one = 1.0;
+      HIPCHK(hipMemcpyAsync(V, &one, 8, hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) stats->normF = std::fabs(v);
+    return JE_OK;
+  }
+  const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
+  const long long cap = log_cap_for(n, std::min(maxrot, kNoAllocLogCap));
+  if (ws_bytes(n, precond, cap) > kNoAllocBytes) return JE_ERR_TOO_LARGE;
+  int err = JE_OK;
+  void* base = scratch_address(&err);
+  if (!base) return err;
+  t_timers_off = true;
+  const int r = solve_one(A, n, lda, W, V, ldv, tol, pivot, precond, o, stats, s, base, cap);
+  t_timers_off = false;
+  return r;
 }
 
 int jacobi_eigh(const double* A, int n, int lda, double* W, double* V, double tol, int pivot,

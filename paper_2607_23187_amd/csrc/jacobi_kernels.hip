@@ -239,6 +239,20 @@ hipError_t launch_offnorm(const double* A, int n, int ld, double* partial, doubl
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ zero fill
+// A fill kernel rather than a runtime memset, so that the call sequence holds kernels and
+// copies only.
+__global__ void k_zero_words(int* __restrict__ p, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+hipError_t launch_zero_words(void* p, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((count + 255) / 256), dim3(256), 0, s, (int*)p, count);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ range of A
 // max |a_ij| (per-row maxima, then one block), and an exact scaling by a power of two.
 __global__ __launch_bounds__(256) void k_rowmax(const double* __restrict__ A, int n, int ld,

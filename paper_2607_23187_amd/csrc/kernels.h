@@ -72,6 +72,8 @@ hipError_t launch_set_identity(double* V, int n, int ldv, hipStream_t s);
 hipError_t launch_sort_output(const double* diag, int n, const double* Vw, int ldw, double* W,
                               double* Vout, int ldvo, int* perm, int sort, int w_exp,
                               hipStream_t s);
+// count 4-byte words at p set to zero
+hipError_t launch_zero_words(void* p, int count, hipStream_t s);
 // out[0] = max |a_ij|
 hipError_t launch_maxabs(const double* A, int n, int ld, double* partial, double* out,
                          hipStream_t s);

@@ -20,6 +20,7 @@ PRECOND_NONE, PRECOND_FP32 = 0, 1
 STOP_CERT, STOP_OFF, STOP_SCORE = 0, 1, 2
 OK, WARN_MAXROT, WARN_STALL, ERR_NONFINITE, ERR_NOMEM, ERR_DEVICE, ERR_TOO_LARGE = range(7)
 MAX_N = 8192
+NOALLOC_MAX_N = 512
 
 _PIVOTS = {"greedy": GREEDY, "gap": GAP, "relative": RELATIVE, GREEDY: GREEDY, GAP: GAP,
            RELATIVE: RELATIVE}
@@ -58,7 +59,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["je_opts_default", "jacobi_eigh", "jacobi_eigh_ex", "jacobi_eigh_batched",
-           "jacobi_eigh_batched_host", "jacobi_svd",
+           "jacobi_eigh_batched_host", "jacobi_eigh_noalloc", "jacobi_svd",
            "jacobi_workspace_size", "jacobi_strerror", "jacobi_release",
            "jacobi_server_create", "jacobi_server_submit", "jacobi_server_poll",
            "jacobi_server_pending", "jacobi_server_clock", "jacobi_server_destroy"]
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH):
     L.jacobi_eigh_ex.argtypes = [vp, ip, ip, vp, vp, ip, dp, ip, ip, ctypes.POINTER(Opts),
                                  ctypes.POINTER(Stats), vp]
     L.jacobi_eigh_ex.restype = ctypes.c_int
+    L.jacobi_eigh_noalloc.argtypes = L.jacobi_eigh_ex.argtypes
+    L.jacobi_eigh_noalloc.restype = ctypes.c_int
     L.jacobi_eigh_batched.argtypes = [ip, vp, vp, vp, vp, vp, dp, ip, ip,
                                       ctypes.POINTER(Opts), vp, vp]
     L.jacobi_eigh_batched.restype = ctypes.c_int
@@ -180,11 +183,14 @@ def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop=
          polish_v: bool = True, fp32_max_sweeps: int = 20, fp32_passes: int = 2,
          pivot_log_cap: int = 0, split_gemm: bool = False, sort: bool = True,
          update_mode="auto", graph: bool = False, profile: bool = False, fp32_block: int = 0,
-         stream: torch.cuda.Stream | None = None, check: bool = True) -> Result:
+         stream: torch.cuda.Stream | None = None, check: bool = True,
+         noalloc: bool = False) -> Result:
     """Eigen-decomposition of the symmetric float64 CUDA tensor ``a``.
 
     The library reads the upper triangle of ``a`` in column-major terms (``a[j, i]`` for
     i <= j of the row-major tensor); for a symmetric tensor this is the whole matrix.
+    ``noalloc`` calls jacobi_eigh_noalloc (the library's fixed device workspace; the output
+    tensors are still allocated here by torch).
     """
     _check_device_tensor(a)
     L = load()
@@ -202,12 +208,13 @@ def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop=
     st = Stats()
     s = stream if stream is not None else torch.cuda.current_stream(a.device)
     with torch.cuda.device(a.device):
-        status = L.jacobi_eigh_ex(a.data_ptr(), n, max(1, n), w.data_ptr(),
-                                  vt.data_ptr() if vt is not None else None, max(1, n), float(tol),
-                                  _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o),
-                                  ctypes.byref(st), ctypes.c_void_p(s.cuda_stream))
+        fn = L.jacobi_eigh_noalloc if noalloc else L.jacobi_eigh_ex
+        status = fn(a.data_ptr(), n, max(1, n), w.data_ptr(),
+                    vt.data_ptr() if vt is not None else None, max(1, n), float(tol),
+                    _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o), ctypes.byref(st),
+                    ctypes.c_void_p(s.cuda_stream))
     if check and (status < 0 or status >= ERR_NONFINITE):
-        raise RuntimeError(f"jacobi_eigh_ex failed: {status} ({strerror(status)})")
+        raise RuntimeError(f"jacobi_eigh failed: {status} ({strerror(status)})")
     if plog is not None:
         plog = plog[: min(st.rotations, pivot_log_cap)]
     return Result(w, vt.t() if vt is not None else None, status, st.as_dict(), plog)
