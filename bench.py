@@ -29,6 +29,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2607_23187_amd", "csrc", "jacobi_kernels.
 PMC_FILE = os.path.join(ROOT, "profiles", "jacobi_kernel_c2_pmc.json")
 QUEUE_PMC_FILE = os.path.join(ROOT, "profiles", "jacobi_queue_c4_pmc.json")
 COUNTS_FILE = os.path.join(ROOT, "tests", "golden", "c2_oracle_counts.json")
+CPU_FULL_FILE = os.path.join(ROOT, "profiles", "oracle_c2_full_solve.json")
 
 
 def log(*a):
@@ -56,14 +57,42 @@ def pct(xs, q):
     return xs[k]
 
 
-def solve(J, a, tol, pivot, precond, passes=2):
+def solve(J, a, tol, pivot, precond, passes=2, polish=True, max_rotations=0):
     import torch
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = J.eigh(a, tol=tol, pivot=pivot, precond=precond, stop="cert", fp32_passes=passes)
+    r = J.eigh(a, tol=tol, pivot=pivot, precond=precond, stop="cert", fp32_passes=passes,
+               polish_v=polish, max_rotations=max_rotations)
     torch.cuda.synchronize()
     return r, (time.perf_counter() - t0) * 1e3
+
+
+def true_error_crossing(J, a, tol, lam, n, total):
+    """Smallest rotation count k (by bisection over the rotation cap) after which the sorted
+    diagonal is within tau = 10 n u ||A||_2 of the construction spectrum, beside the count
+    the Theorem 1 certificate needs."""
+    import numpy as np
+
+    lam2 = float(np.max(np.abs(lam)))
+    tau = 10 * n * U * lam2
+
+    def ok(k):
+        r, _ = solve(J, a, tol, "gap", "fp32", max_rotations=max(1, k))
+        return float(np.max(np.abs(r.w.cpu().numpy() - lam))) <= tau
+
+    lo, hi = 0, total
+    if ok(1):
+        hi = 1
+    else:
+        lo = 1
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if ok(mid):
+                hi = mid
+            else:
+                lo = mid
+    return {"true_error_le_tau": hi, "certificate": total, "tau_over_n_u_norm2": 10.0}
 
 
 def accuracy(r, lam, n):
@@ -84,37 +113,53 @@ def accuracy(r, lam, n):
             "fp64_accurate": bool(ok)}
 
 
+def pmc_traffic(path, key, value):
+    """HBM bytes per launch of the measured kernels, from the FETCH_SIZE and WRITE_SIZE
+    counters stored in profiles/ (each scaled by what the counter reads for a copy kernel
+    of known size), when they were taken on the current kernel source and workload; else
+    None (the kernels changed since)."""
+    try:
+        pm = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if pm.get("kernel_source_sha256_16") != kernel_hash() or pm.get(key) != value:
+        return None
+    return pm.get("hbm_bytes_per_launch")
+
+
 def roofline(stats, n):
+    """Roofline of the FP64 Jacobi phase of one solve (rows J1-J6 and J5): every rotation
+    reads and writes rows p, q of A and columns p, q of V, 64 n algorithmic bytes
+    (Sec. 3.2: O(n) work per rotation).  Time: the persistent pivoted Jacobi kernel plus the
+    kernel that applies the rotation log to V, from HIP events recorded by the library on
+    the launch stream (je_stats.ms_jacobi_kernel, ms_apply_log)."""
     rot = stats["rotations"]
-    ms = stats["ms_jacobi_kernel"]
-    bytes_per_rot = 32.0 * n  # rows p and q of A: read 2n + write 2n FP64 values
-    achieved = bytes_per_rot * rot / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    traffic = None
-    if os.path.exists(PMC_FILE):
-        try:
-            pm = json.load(open(PMC_FILE))
-            if pm.get("kernel_source_sha256_16") == kernel_hash() and pm.get("n") == n:
-                traffic = pm.get("hbm_bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    tk = stats["ms_jacobi_kernel"]
+    ta = stats["ms_apply_log"]
+    per_rot = 64.0 * n
+    t = tk + ta
+    achieved = per_rot * rot / (t * 1e-3) / 1e9 if t > 0 else 0.0
+    half = 32.0 * n
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_jacobi (persistent pivoted Jacobi, one workgroup)",
-            "algorithmic_bytes_per_rotation": bytes_per_rot, "rotations_per_launch": rot,
-            "kernel_ms": ms, "us_per_rotation": ms * 1e3 / max(1, rot)}
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": pmc_traffic(PMC_FILE, "n", n),
+            "kernel": "k_jacobi + k_apply_log (the FP64 Jacobi phase of one solve)",
+            "algorithmic_bytes_per_rotation": per_rot, "rotations_per_launch": rot,
+            "kernel_ms": t, "us_per_rotation": t * 1e3 / max(1, rot),
+            "kernels": {
+                "k_jacobi": {"ms": tk, "bytes_per_rotation": half,
+                             "achieved_GBs": half * rot / (tk * 1e-3) / 1e9 if tk > 0 else 0.0,
+                             "us_per_rotation": tk * 1e3 / max(1, rot),
+                             "what": "rows p, q of A read and written"},
+                "k_apply_log": {"ms": ta, "bytes_per_rotation": half,
+                                "achieved_GBs": half * rot / (ta * 1e-3) / 1e9 if ta > 0 else 0.0,
+                                "what": "columns p, q of V read and written"}}}
 
 
 def queue_traffic(batch):
-    """HBM bytes of the batched solve's persistent Jacobi launches, from the FETCH_SIZE and
-    WRITE_SIZE counters in profiles/ (scaled by the reference copy), when they were taken
-    on the current kernel source and batch; else None."""
-    try:
-        pm = json.load(open(QUEUE_PMC_FILE))
-    except (OSError, ValueError):
-        return None
-    if pm.get("kernel_source_sha256_16") != kernel_hash() or pm.get("batch") != batch:
-        return None
-    return pm.get("hbm_bytes_per_batched_solve")
+    """HBM bytes of the batched solve's FP64 Jacobi phase (persistent launches and log
+    drains), from the counters in profiles/ when they match the current source and batch."""
+    return pmc_traffic(QUEUE_PMC_FILE, "batch", batch)
 
 
 def cpu_baseline(a_np, n):
@@ -146,21 +191,72 @@ def cpu_baseline(a_np, n):
         t_rot = (time.perf_counter() - t) / max(1, r.rotations)
     passes = 2
     est = counts["sweeps32"] * t_sweep + passes * t_dense + counts["rotations"] * t_rot
-    return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one FP32 sweep ({t_sweep:.2f} s), one QR + Q^T A Q ({t_dense:.2f} s) "
-                       f"and {r.rotations} FP64 rotations ({t_rot * 1e6:.1f} us each) of the "
-                       f"oracle on this matrix, scaled by its own counts "
-                       f"({counts['sweeps32']} sweeps, {counts['rotations']} rotations, "
-                       f"{passes} passes) to one solve = {est:.1f} s"),
-            "seconds_per_solve": est}
+    out = {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": (f"one FP32 sweep ({t_sweep:.2f} s), one QR + Q^T A Q ({t_dense:.2f} s) "
+                      f"and {r.rotations} FP64 rotations ({t_rot * 1e6:.1f} us each) of the "
+                      f"oracle on this matrix, scaled by its own counts "
+                      f"({counts['sweeps32']} sweeps, {counts['rotations']} rotations, "
+                      f"{passes} passes) to one solve = {est:.1f} s"),
+           "seconds_per_solve": est, "host": host_cpu()}
+    # one whole oracle solve of this matrix, timed on the same kind of host by
+    # `bench.py --workload cpu-full` (stored summary)
+    try:
+        full = json.load(open(CPU_FULL_FILE))
+        out["measured_full_solve"] = {k: full[k] for k in ("seconds", "cores", "host",
+                                                           "rotations", "sweeps32", "command")}
+    except (OSError, ValueError, KeyError):
+        out["measured_full_solve"] = None
+    return out
 
 
-def bench_batch(args):
+def host_cpu() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
+def bench_cpu_full(args):
+    """One whole oracle solve of the n = 1024 benchmark matrix on one host core (the FP32
+    sweeps report their progress on stderr); prints a JSON summary."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    from paper_2607_23187_amd import inputs as I
+
+    O.build(force=False)
+    prob = I.config_c2(n=args.n)
+    n = prob.a.shape[0]
+    lam2 = float(np.max(np.abs(prob.lam)))
+    tol = 10 * n * U * lam2 / float(np.linalg.norm(prob.a))
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        r = O.eigh(prob.a, tol=tol, pivot=O.GAP, precond="fp32", stop=O.STOP_CERT,
+                   verbose=True)
+        dt = time.perf_counter() - t
+    err = float(np.max(np.abs(r.w - prob.lam)))
+    print(json.dumps({"workload": f"oracle: one whole solve of the n={n} benchmark matrix "
+                                  "(FP32 preconditioner, 2 passes, gap pivots, Theorem 1 stop)",
+                      "seconds": dt, "cores": 1, "host": host_cpu(),
+                      "rotations": r.rotations, "sweeps32": r.sweeps32,
+                      "eig_err_over_n_u_norm2": err / (n * U * lam2),
+                      "command": "python bench.py --workload cpu-full"}), flush=True)
+
+
+def run_batch(args):
     """Batched workload: 2048 independent matrices, n log-uniform in [32, 512], spectrum
     clustered (clusters of 4-16, spread 1e-10..1e-6) or uniform on [1, 2] with probability
     1/2; every matrix FP32-preconditioned with gap pivots to the Theorem 1 certificate at
     tau = 10 n u ||A||_2 (tol = min over the batch).  The batched call (one launch sequence
-    for the whole batch, persistent FP64 Jacobi launches) against one call per matrix."""
+    for the whole batch, persistent FP64 Jacobi launches) against one call per matrix.
+    Returns a dict of the measurements."""
     import numpy as np
     import torch
 
@@ -170,7 +266,7 @@ def bench_batch(args):
     J.load()
     t = time.perf_counter()
     probs = I.config_c4(count=args.batch)
-    log(f"generated {len(probs)} matrices in {time.perf_counter() - t:.1f} s")
+    log(f"batched: generated {len(probs)} matrices in {time.perf_counter() - t:.1f} s")
     mats = [torch.from_numpy(p.a).to("cuda:0") for p in probs]
     tol = min(10 * p.a.shape[0] * U * float(np.max(np.abs(p.lam))) / float(np.linalg.norm(p.a))
               for p in probs)
@@ -185,7 +281,7 @@ def bench_batch(args):
         st, res = J.eigh_batched(mats, tol=tol, pivot="gap", precond=args.precond)
         torch.cuda.synchronize()
         log(f"profile run: copy 268435456 B; batched solve status {st}")
-        return
+        return None
 
     def run_batched():
         torch.cuda.synchronize()
@@ -194,16 +290,17 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return st, res, time.perf_counter() - t0
 
-    for i in range(args.warmup):
+    for i in range(max(1, args.batch_warmup)):
         st, res, dt = run_batched()
-        log(f"warmup {i}: {dt * 1e3:.1f} ms, status {st}")
+        log(f"batched warmup {i}: {dt * 1e3:.1f} ms, status {st}")
     lat = []
-    for i in range(args.steps):
+    for i in range(args.batch_steps):
         st, res, dt = run_batched()
         lat.append(dt)
-        log(f"step {i}: {dt * 1e3:.1f} ms")
+        log(f"batched step {i}: {dt * 1e3:.1f} ms")
     ok = 0
     worst = 0.0
+    worst_orth = 0.0
     for p, r in zip(probs, res):
         n = p.a.shape[0]
         lam2 = float(np.max(np.abs(p.lam)))
@@ -213,19 +310,35 @@ def bench_batch(args):
         g -= torch.eye(n, dtype=g.dtype, device=g.device)
         orth = float(torch.linalg.norm(g).item()) / (n * U)
         worst = max(worst, err)
+        worst_orth = max(worst_orth, orth)
         ok += int(r.status == J.OK and err <= 10 and orth <= 10)
     s0 = res[0].stats
     rot = np.array([r.stats["rotations"] for r in res], dtype=np.float64)
-    kern_ms = s0["ms_jacobi_kernel"]
-    algo = float(np.sum(rot * 32.0 * sizes))
-    out_b = {"seconds": float(np.median(lat)), "solves_per_s": len(probs) / float(np.median(lat)),
-             "p50_ms": pct([x * 1e3 for x in lat], 50), "p99_ms": pct([x * 1e3 for x in lat], 99),
-             "phase_ms": {k: s0[k] for k in ("ms_precond", "ms_gemm", "ms_jacobi", "ms_finalize",
-                                              "ms_jacobi_kernel")},
-             "rotations_total": int(rot.sum()), "fp64_accurate": ok, "worst_err_over_n_u_norm2": worst}
-    # one call per matrix, same stream
-    dt1, singles = float("nan"), 0
+    tk, ta = s0["ms_jacobi_kernel"], s0["ms_apply_log"]
+    algo = float(np.sum(rot * 64.0 * sizes))   # rows p, q of A and columns p, q of V
+    med = float(np.median(lat))
+    out = {"batch": len(probs), "seconds": med, "solves_per_s": len(probs) / med,
+           "fp64_accurate_solves_per_s": len(probs) / med if ok == len(probs) else 0.0,
+           "p50_ms": pct([x * 1e3 for x in lat], 50), "p99_ms": pct([x * 1e3 for x in lat], 99),
+           "steps": args.batch_steps,
+           "phase_ms": {k: s0[k] for k in ("ms_precond", "ms_gemm", "ms_jacobi", "ms_finalize",
+                                            "ms_jacobi_kernel", "ms_apply_log")},
+           "rotations_total": int(rot.sum()), "fp64_accurate": f"{ok}/{len(probs)}",
+           "worst_err_over_n_u_norm2": worst, "worst_orth_over_n_u": worst_orth,
+           "roofline": {"bound": "hbm",
+                        "achieved": algo / ((tk + ta) * 1e-3) / 1e9 if tk + ta > 0 else 0.0,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": (algo / ((tk + ta) * 1e-3) / 1e9) / HBM_PEAK_GBS
+                        if tk + ta > 0 else 0.0,
+                        "traffic": queue_traffic(len(probs)),
+                        "kernel": "k_jacobi_queue + k_apply_log_b (FP64 Jacobi phase of the batch)",
+                        "algorithmic_bytes": algo, "kernel_ms": tk + ta,
+                        "k_jacobi_queue": {"ms": tk, "achieved_GBs": algo / 2 / (tk * 1e-3) / 1e9
+                                           if tk > 0 else 0.0},
+                        "k_apply_log_b": {"ms": ta, "achieved_GBs": algo / 2 / (ta * 1e-3) / 1e9
+                                          if ta > 0 else 0.0}}}
     if not args.no_compare:
+        singles = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for m in mats:
@@ -233,26 +346,32 @@ def bench_batch(args):
             singles += int(r.status == J.OK)
         torch.cuda.synchronize()
         dt1 = time.perf_counter() - t0
-        log(f"one call per matrix: {dt1 * 1e3:.1f} ms")
+        log(f"batched: one call per matrix {dt1 * 1e3:.1f} ms")
+        out["one_call_per_matrix"] = {"seconds": dt1, "solves_per_s": len(probs) / dt1,
+                                      "ok": singles}
+        out["batched_speedup"] = dt1 / med
+    return out
+
+
+def bench_batch(args):
+    import numpy as np  # noqa: F401
+
+    from paper_2607_23187_amd import inputs as I
+
+    b = run_batch(args)
+    if b is None:
+        return
     out = {
-        "metric": "FP64-accurate eigensolves/s (batched)", "value": out_b["solves_per_s"] if ok == len(probs) else 0.0,
-        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": out_b["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "metric": "FP64-accurate eigensolves/s (batched)", "value": b["fp64_accurate_solves_per_s"],
+        "unit": "solves/s", "n_gpus": 1, "steps": args.batch_steps, "warmup": args.batch_warmup,
+        "ms_per_step": b["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": (f"{len(probs)} independent FP64 symmetric matrices, n log-uniform in "
-                                "[32,512], spectra clustered (4-16, spread 1e-10..1e-6) or U[1,2] "
-                                f"with p=1/2; precond {args.precond}, gap pivots, Theorem 1 stop"),
-                   "batch": len(probs), "precond": args.precond, "seed": I.SEED_C4},
-        "batched": out_b,
-        "one_call_per_matrix": (None if args.no_compare else
-                                {"seconds": dt1, "solves_per_s": len(probs) / dt1, "ok": singles}),
-        "batched_speedup": None if args.no_compare else dt1 / out_b["seconds"],
-        "roofline": {"bound": "hbm", "achieved": algo / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (algo / (kern_ms * 1e-3) / 1e9) / HBM_PEAK_GBS if kern_ms > 0 else 0.0,
-                     "traffic": queue_traffic(len(probs)),
-                     "kernel": "k_jacobi_queue (persistent, one workgroup per matrix)",
-                     "algorithmic_bytes": algo, "kernel_ms": kern_ms},
+        "config": {"workload": (f"{b['batch']} independent FP64 symmetric matrices, n log-uniform "
+                                "in [32,512], spectra clustered (4-16, spread 1e-10..1e-6) or "
+                                f"U[1,2] with p=1/2; precond {args.precond}, gap pivots, "
+                                "Theorem 1 stop"),
+                   "batch": b["batch"], "precond": args.precond, "seed": I.SEED_C4},
+        "batched": b, "roofline": b["roofline"],
     }
     print(json.dumps(out), flush=True)
 
@@ -381,10 +500,14 @@ def bench_sec41(args):
 
 
 def bench_precision(args):
+    print(json.dumps(run_precision(args)), flush=True)
+
+
+def run_precision(args):
     """Precision variant of the contraction (n = 4096, clusters of 8 with offsets 1e-10):
-    Q^T A Q from FP64 MFMA products against three-slice BF16 products with FP32
-    accumulation; off(A_hat), eigenvalue error against the construction spectrum and the
-    time split between the contraction and the FP64 Jacobi phase, for both."""
+    Q^T A Q from FP64 MFMA products against split BF16 products with FP32 accumulation;
+    off(A_hat), eigenvalue error against the construction spectrum and the time split
+    between the contraction and the FP64 Jacobi phase, for both."""
     import numpy as np
     import torch
 
@@ -424,9 +547,9 @@ def bench_precision(args):
                      "fp64_accurate": bool(err <= 10 * n * U * lam2),
                      "status": J.strerror(r.status)}
         log(f"{name}: {ms:.1f} ms, contraction {s['ms_gemm']:.2f} ms, error {err:.3e}")
-    print(json.dumps({"workload": f"n={n} FP64 symmetric, clusters of 8 (offsets 1e-10), "
-                                  "FP32 preconditioner, gap pivots, Theorem 1 stop",
-                      "n": n, "variants": out}), flush=True)
+    return {"workload": f"n={n} FP64 symmetric, clusters of 8 (offsets 1e-10), "
+                        "FP32 preconditioner, gap pivots, Theorem 1 stop",
+            "n": n, "variants": out}
 
 
 def bench_svd(args):
@@ -511,7 +634,7 @@ def main():
     ap.add_argument("--n-precision", type=int, default=4096)
     ap.add_argument("--n-sec41", type=int, default=1000)
     ap.add_argument("--workload", choices=("single", "batch", "serve", "precision", "svd",
-                                           "sec41"),
+                                           "sec41", "cpu-full"),
                     default="single",
                     help="single: the n=1024 headline workload; batch: 2048 uneven matrices; "
                          "serve: a Poisson request stream through the library's server")
@@ -522,6 +645,12 @@ def main():
     ap.add_argument("--rho", type=float, default=0.8)
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-warmup", type=int, default=1)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="default line without the batched workload")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="default line without the n=4096 precision workload")
     ap.add_argument("--precond", choices=("fp32", "none"), default="fp32")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -544,6 +673,9 @@ def main():
         return
     if args.workload == "sec41":
         bench_sec41(args)
+        return
+    if args.workload == "cpu-full":
+        bench_cpu_full(args)
         return
 
     import numpy as np
@@ -629,7 +761,18 @@ def main():
         cmp["gap_speedup_vs_greedy"] = cmp["greedy"]["ms"] / out["p50_ms"]
         cmp["gap_speedup_vs_plain_jacobi"] = cmp["plain_jacobi"]["ms"] / out["p50_ms"]
         out["compare"] = cmp
+    # Sec. 2.1 / 8(d) report items: orthogonality before the polish, and the rotation at
+    # which the true error first meets tau (bisection on the rotation cap: the sorted
+    # diagonal after k rotations is checked against the construction spectrum)
+    rp, _ = solve(J, a, tol, "gap", "fp32", polish=False)
+    out["accuracy"]["orth_over_n_u_before_polish"] = accuracy(rp, prob.lam, n)["orth_over_n_u"]
+    out["rotations_to_true_error"] = true_error_crossing(J, a, tol, prob.lam, n,
+                                                         int(last["rotations"]))
     out["roofline"] = roofline(last, n)
+    if not args.no_batch:
+        out["batched"] = run_batch(args)
+    if not args.no_precision:
+        out["precision"] = run_precision(args)
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(prob.a, n)

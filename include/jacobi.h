@@ -124,6 +124,10 @@ typedef struct je_opts {
   int profile;               /* 1: phase timers of the FP64 Jacobi kernel into        */
                              /* je_stats.prof_ns (slows the kernel slightly)     (0)  */
   int fp32_block;            /* rows per block of the FP32 stage: 0 by n, 16 or 32 (0) */
+  int jacobi_wgs;            /* FP64 phase of one problem: 0 automatic (several       */
+                             /* workgroups from n = 1024), 1 one workgroup, 2 several*/
+                             /* workgroups when the matrix lives in HBM; same results */
+                             /* (0); batches always use one workgroup per matrix      */
 } je_opts;
 
 /* Statistics of one solve (host struct, filled before return). */
@@ -149,6 +153,7 @@ typedef struct je_stats {
                              /* the rotation parameters and the row updates          */
   float ms_apply_log;        /* applying the rotation log to V (HIP events on stream) */
   int scale_exp;             /* the input was scaled by 2^scale_exp (0: not scaled)   */
+  int jacobi_wgs;            /* workgroups of the FP64 Jacobi kernel                  */
 } je_stats;
 
 void je_opts_default(je_opts* opts);

@@ -82,7 +82,7 @@ def lib():
                                ctypes.c_longlong, ctypes.POINTER(_Stats)]
         L.orc_jacobi_f32.restype = ctypes.c_int
         L.orc_jacobi_f32.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_double,
-                                       ctypes.c_double]
+                                       ctypes.c_double, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -156,7 +156,7 @@ F32_TOL2, F32_RHO2 = 2.0 ** -30, 0.5
 
 
 def jacobi_f32(a: np.ndarray, max_sweeps: int = 20, tol: float = F32_TOL1,
-               rho: float = F32_RHO1):
+               rho: float = F32_RHO1, verbose: bool = False):
     """Cyclic FP32 Jacobi: returns (A32_final, V32, sweeps).  Pairs whose a_pq and
     a_pp - a_qq are both at FP32 rounding level of the diagonal are skipped; sweeps stop at
     off <= tol ||A32||_F, when a sweep leaves off >= rho times its previous value, or after
@@ -166,7 +166,7 @@ def jacobi_f32(a: np.ndarray, max_sweeps: int = 20, tol: float = F32_TOL1,
     v32 = np.empty((n, n), dtype=np.float32)
     fp = ctypes.POINTER(ctypes.c_float)
     sweeps = lib().orc_jacobi_f32(a32.ctypes.data_as(fp), n, v32.ctypes.data_as(fp),
-                                  max_sweeps, tol, rho)
+                                  max_sweeps, tol, rho, 1 if verbose else 0)
     return a32, v32, sweeps
 
 
@@ -219,8 +219,9 @@ def threshold(stop: int, tol: float, n: int, normF: float) -> float:
 def eigh(a: np.ndarray, tol: float, pivot: int = GAP, precond: str = "fp32",
          stop: int = STOP_CERT, abs_thr: float | None = None, want_v: bool = True,
          maxrot: int | None = None, scan: int = 1, sweeps32: int = 20,
-         polish_v: bool = True, passes: int = 2) -> EighResult:
-    """Whole preconditioned solve: returns ascending eigenvalues and eigenvectors."""
+         polish_v: bool = True, passes: int = 2, verbose: bool = False) -> EighResult:
+    """Whole preconditioned solve: returns ascending eigenvalues and eigenvectors.
+    ``verbose`` prints the progress of the FP32 sweeps on stderr."""
     a = symmetric_from_upper(a)
     n = a.shape[0]
     if not np.all(np.isfinite(a)):
@@ -232,12 +233,14 @@ def eigh(a: np.ndarray, tol: float, pivot: int = GAP, precond: str = "fp32",
     sw = 0
     if precond == "fp32" and n > 1:
         _, v32, sw = jacobi_f32(a, max_sweeps=sweeps32,
-                                 tol=F32_TOL1 if passes == 1 else F32_TOL1_REFINED)
+                                 tol=F32_TOL1 if passes == 1 else F32_TOL1_REFINED,
+                                 verbose=verbose)
         q = householder_q(v32.astype(np.float64))
         for _ in range(passes - 1):
             a1 = q.T @ (a @ q)
             a1 = 0.5 * (a1 + a1.T)
-            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32, tol=F32_TOL2, rho=F32_RHO2)
+            _, v2, sw2 = jacobi_f32(a1, max_sweeps=sweeps32, tol=F32_TOL2, rho=F32_RHO2,
+                                    verbose=verbose)
             sw += sw2
             q = householder_q(q @ v2.astype(np.float64))
         a_hat = q.T @ (a @ q)

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -359,7 +360,9 @@ static bool f32_noise_pair(float app, float aqq, float apq) {
   return std::fabs(app - aqq) <= nz && std::fabs(apq) <= nz;
 }
 
-int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol, double rho) {
+// verbose != 0: one line per sweep on stderr (progress of long runs).
+int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol, double rho,
+                   int verbose) {
   std::fill(V32, V32 + (size_t)n * n, 0.0f);
   for (int i = 0; i < n; ++i) V32[(size_t)i * n + i] = 1.0f;
   auto off_and_norm = [&](double* off, double* nrm) {
@@ -410,6 +413,7 @@ int orc_jacobi_f32(float* A32, int n, float* V32, int max_sweeps, double tol, do
     ++sweeps;
     double prev = off;
     off_and_norm(&off, &nrm);
+    if (verbose) std::fprintf(stderr, "oracle fp32 sweep %d: off/norm %.3e\n", sweeps, off / nrm);
     if (off >= rho * prev) break;
   }
   return sweeps;

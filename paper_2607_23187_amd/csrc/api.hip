@@ -80,6 +80,11 @@ constexpr double kF32Rho2 = 0.5;
 // pass skips, and the sweep that would show the stall is saved).
 constexpr double kF32Tol2 = 0x1p-30;
 
+// Smallest n whose FP64 Jacobi phase runs on several workgroups by default (MI355X, per
+// rotation, one workgroup against several: n = 512 3.75 / 4.63 us, 1024 5.02 / 4.74,
+// 2048 7.23 / 5.29, 4096 11.47 / 6.04).
+constexpr int kMultiWgMinN = 1024;
+
 // Range of the entries solved as given: outside it the input is scaled by a power of two
 // (exact) so that squares in FP64 and the FP32 copy of the preconditioner stay in range.
 constexpr double kRangeLo = 0x1p-60, kRangeHi = 0x1p60;
@@ -101,6 +106,7 @@ struct WS {
   JCtl* ctl;
   RotEntry* log;
   void* f32;
+  void* mw;       // control block and exchange area of the multi-workgroup Jacobi kernel
   long long log_cap;
 };
 
@@ -119,6 +125,7 @@ size_t ws_bytes(int n, int precond, long long log_cap) {
   b += al(64);                    // phase timers
   b += al((size_t)log_cap * sizeof(RotEntry));
   if (precond) b += al(precond_f32_bytes(n));
+  b += al(mw_bytes(n));
   return b;
 }
 
@@ -163,6 +170,7 @@ WS ws_carve(void* base, int n, int precond, long long log_cap) {
   w.prof = (long long*)take(64);
   w.log = (RotEntry*)take((size_t)log_cap * sizeof(RotEntry));
   w.f32 = precond ? take(precond_f32_bytes(n)) : nullptr;
+  w.mw = take(mw_bytes(n));
   w.log_cap = log_cap;
   return w;
 }
@@ -357,16 +365,29 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   HIPCHK(launch_init_rows(d, s));
   const bool lds = jacobi_fits_lds(n);
   const bool mirror = o.update_mode != 2;  // one problem: mirror mode unless asked otherwise
+  // several workgroups for large HBM-resident problems (mirror mode, no phase timers)
+  bool multi = !lds && mirror &&
+               (o.jacobi_wgs == 2 || (o.jacobi_wgs == 0 && n >= kMultiWgMinN));
   long long base_rot = 0;
   JCtl hc{};
   float ms_apply = 0.f;
   float ms_kernel = 0.f;
   for (;;) {
     Timer tk(s);
-    HIPCHK(launch_jacobi(d, base_rot, lds, mirror, s));
+    if (multi) HIPCHK(launch_jacobi_mw(d, base_rot, w.mw, s));
+    else HIPCHK(launch_jacobi(d, base_rot, lds, mirror, s));
     ms_kernel += tk.stop();
     HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(JCtl), hipMemcpyDeviceToHost, s));
+    MwCtl mc{};
+    if (multi) HIPCHK(hipMemcpyAsync(&mc, w.mw, 16, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (multi && mc.misplaced) {
+      // the workgroups were not all resident on one XCD: the state is untouched, the
+      // one-workgroup kernel takes over
+      multi = false;
+      continue;
+    }
+    if (multi && mc.abort) return JE_ERR_DEVICE;
     long long m = hc.rotations - base_rot;
     if (o.pivot_log && base_rot < o.pivot_log_cap) {
       long long mm = std::min(m, o.pivot_log_cap - base_rot);
@@ -388,6 +409,9 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
   }
   S.ms_jacobi_kernel = ms_kernel;
   S.ms_apply_log = ms_apply;
+  int rows_per_thread = 0;
+  if (multi) mw_shape(n, &S.jacobi_wgs, &rows_per_thread);
+  else S.jacobi_wgs = 1;
   S.rotations = hc.rotations;
   S.rescans = hc.rescans;
   S.final_max_score = hc.final_cert * unscale;
@@ -880,7 +904,7 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
   }
   std::vector<JCtl> hc(cnt);
   std::vector<char> done(cnt, 0);
-  float ms_kernel = 0.f;
+  float ms_kernel = 0.f, ms_apply = 0.f;
   for (int launch = 0;; ++launch) {
     std::vector<int> il, ih;
     int nl = 0, nh = 0;
@@ -906,12 +930,15 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
                                  shape_hbm, d_cnt + 1, (int)std::min<size_t>(ih.size(), 1024),
                                  s));
     ms_kernel += tk.stop();
+    Timer ta(s);
     HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
+    ms_apply += ta.stop();
     if (int r = collect()) return r;
     for (int i = 0; i < cnt; ++i) { hc[i] = hi[i].ctl; done[i] = hc[i].done ? 1 : 0; }
   }
   S.ms_jacobi = tj.stop();
   S.ms_jacobi_kernel = ms_kernel;
+  S.ms_apply_log = ms_apply;
   // ---- 4. polish, sort, output
   Timer tf(s);
   if (V && o.polish_v) {
@@ -1102,6 +1129,7 @@ int check_args(const double* A, int n, int lda, const double* W, const double* V
   if (o.graph != 0 && o.graph != 1) return -10;
   if (o.profile != 0 && o.profile != 1) return -10;
   if (o.fp32_block != 0 && o.fp32_block != 16 && o.fp32_block != 32) return -10;
+  if (o.jacobi_wgs < 0 || o.jacobi_wgs > 2) return -10;
   return 0;
 }
 
@@ -1156,6 +1184,7 @@ void je_opts_default(je_opts* o) {
   o->graph = 0;
   o->profile = 0;
   o->fp32_block = 0;
+  o->jacobi_wgs = 0;
 }
 
 int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,

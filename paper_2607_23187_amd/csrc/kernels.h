@@ -66,6 +66,23 @@ bool jacobi_fits_lds(int n);
 // V[i][:] <- V[i][:] * G_1 ... G_m for every row (rotations of `log`, in order).
 hipError_t launch_apply_log(double* V, int n, int ldv, const RotEntry* log, long long m,
                             hipStream_t s);
+
+// Multi-workgroup form of launch_jacobi (mirror mode, A in HBM): G one-wave workgroups on
+// one XCD exchange their candidates through L2 every rotation.  `buf` holds the control
+// block and the exchange area (mw_bytes(n) bytes).  After the launch, MwCtl::misplaced = 1
+// means the kernel returned without touching the state (run launch_jacobi instead);
+// abort = 1 without it means a wait ran out mid-run (device error).
+constexpr int kMwMaxGroups = 32;
+struct MwCtl {
+  int counter;                // arrivals at the exchange barriers
+  int abort;                  // a wait ran out
+  int misplaced;              // the workgroups were not all resident on one XCD
+  int pad;
+  int xcc[kMwMaxGroups];      // XCC id of every workgroup
+};
+void mw_shape(int n, int* G, int* RM);
+size_t mw_bytes(int n);
+hipError_t launch_jacobi_mw(const JDesc& d, long long log_base, void* buf, hipStream_t s);
 hipError_t launch_set_identity(double* V, int n, int ldv, hipStream_t s);
 // W[rank[k]] = 2^w_exp diag[k], Vout[:, rank[k]] = column k of Vw; rank ascending and
 // stable when sort != 0, else rank[k] = k.

@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
                 ("pivot_log_cap", ctypes.c_longlong), ("split_gemm", ctypes.c_int),
                 ("sort", ctypes.c_int), ("update_mode", ctypes.c_int), ("tune", ctypes.c_int),
                 ("graph", ctypes.c_int), ("profile", ctypes.c_int),
-                ("fp32_block", ctypes.c_int)]
+                ("fp32_block", ctypes.c_int), ("jacobi_wgs", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -50,7 +50,7 @@ class Stats(ctypes.Structure):
                 ("ms_jacobi", ctypes.c_float), ("ms_finalize", ctypes.c_float),
                 ("ms_jacobi_kernel", ctypes.c_float), ("a_hat_off", ctypes.c_double),
                 ("prof_ns", ctypes.c_double * 6), ("ms_apply_log", ctypes.c_float),
-                ("scale_exp", ctypes.c_int)]
+                ("scale_exp", ctypes.c_int), ("jacobi_wgs", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -158,9 +158,12 @@ def _check_device_tensor(a: torch.Tensor):
 _UPDATE_MODES = {"auto": 0, "mirror": 1, "timestamp": 2, 0: 0, 1: 1, 2: 2}
 
 
+_WGS = {"auto": 0, "one": 1, "many": 2, 0: 0, 1: 1, 2: 2}
+
+
 def _opts(stop="cert", polish_v=True, fp32_max_sweeps=20, fp32_passes=2, split_gemm=False,
           max_rotations=0, abs_thr=0.0, sort=True, update_mode="auto", tune=True, graph=False,
-          profile=False, fp32_block=0) -> Opts:
+          profile=False, fp32_block=0, jacobi_wgs="auto") -> Opts:
     o = default_opts()
     o.stop = _STOPS[stop]
     o.polish_v = 1 if polish_v else 0
@@ -175,6 +178,7 @@ def _opts(stop="cert", polish_v=True, fp32_max_sweeps=20, fp32_passes=2, split_g
     o.graph = 1 if graph else 0
     o.profile = 1 if profile else 0
     o.fp32_block = int(fp32_block)
+    o.jacobi_wgs = _WGS[jacobi_wgs]
     return o
 
 
@@ -183,7 +187,7 @@ def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop=
          polish_v: bool = True, fp32_max_sweeps: int = 20, fp32_passes: int = 2,
          pivot_log_cap: int = 0, split_gemm: bool = False, sort: bool = True,
          update_mode="auto", graph: bool = False, profile: bool = False, fp32_block: int = 0,
-         stream: torch.cuda.Stream | None = None, check: bool = True,
+         jacobi_wgs="auto", stream: torch.cuda.Stream | None = None, check: bool = True,
          noalloc: bool = False) -> Result:
     """Eigen-decomposition of the symmetric float64 CUDA tensor ``a``.
 
@@ -199,7 +203,7 @@ def eigh(a: torch.Tensor, tol: float = 1e-14, pivot="gap", precond="fp32", stop=
     w = torch.empty(n, dtype=torch.float64, device=a.device)
     vt = torch.empty((n, n), dtype=torch.float64, device=a.device) if want_v else None
     o = _opts(stop, polish_v, fp32_max_sweeps, fp32_passes, split_gemm, max_rotations, abs_thr,
-              sort, update_mode, True, graph, profile, fp32_block)
+              sort, update_mode, True, graph, profile, fp32_block, jacobi_wgs)
     plog = None
     if pivot_log_cap > 0:
         plog = torch.full((pivot_log_cap, 2), -1, dtype=torch.int32, device=a.device)

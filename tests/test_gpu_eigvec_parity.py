@@ -219,3 +219,59 @@ def test_unsorted_output_keeps_diagonal_order():
     ref = O.jacobi(a, pivot=O.GAP, stop=O.STOP_CERT, thr=thr, scan=1, want_vj=True)
     assert np.array_equal(r.w.cpu().numpy(), np.diag(ref.a))
     assert np.array_equal(r.v.cpu().numpy(), ref.vj)
+
+
+@pytest.mark.parametrize("n,pivot", [(512, J.GAP), (700, J.GREEDY), (1024, J.GAP),
+                                     (2049, J.GAP), (4097, J.GREEDY)])
+def test_multi_workgroup_kernel_equals_one_workgroup(n, pivot):
+    """The FP64 phase on several workgroups (one wave each, candidates exchanged through L2
+    every rotation) performs the same arithmetic as the one-workgroup kernel: same pivots,
+    rotation count, diagonal and eigenvectors, for 1, 2 and 4 rows per thread, with row
+    rescans."""
+    cap = 3000
+    a = I.random_symmetric(n, seed=7000 + n)
+    say("multi-workgroup vs one", n, pivot)
+    kw = dict(precond="none", pivot=pivot, stop="cert", abs_thr=1e-300, max_rotations=cap,
+              pivot_log_cap=cap, polish_v=False)
+    r1 = J.eigh(gpu(a), jacobi_wgs="one", **kw)
+    rm = J.eigh(gpu(a), jacobi_wgs="many", **kw)
+    assert r1.stats["jacobi_wgs"] == 1 and rm.stats["jacobi_wgs"] > 1
+    assert r1.status == rm.status == J.WARN_MAXROT
+    assert rm.stats["rotations"] == r1.stats["rotations"] == cap
+    # (the rescan counts may differ: a stale row's cached bound is widened by one float ulp
+    # per reduction level and the two kernels group the maximum differently; a rescan only
+    # makes a row exact, so the pivots do not depend on it)
+    assert torch.equal(rm.pivots, r1.pivots)
+    assert torch.equal(rm.w, r1.w)
+    assert torch.equal(rm.v, r1.v)
+
+
+@pytest.mark.parametrize("stop", ["cert", "score", "off"])
+def test_multi_workgroup_full_solve_matches_oracle(stop):
+    """A whole FP64 phase on several workgroups against the oracle (n = 600, nearly diagonal
+    input, both pivot rules through the certificate stop with greedy's L cache): pivots,
+    rotation count and bits of W and V.  The off-norm stop sums its per-row parts in another
+    order than the oracle, so there the pivots agree up to the common length."""
+    n = 600
+    a, lam2 = nearly_diag_case(n)
+    for pivot in (J.GAP, J.GREEDY):
+        thr = cert_thr(lam2, n) if stop == "cert" else 1e-13
+        say("multi-workgroup full", stop, pivot)
+        cap = 40 * n * n
+        r = J.eigh(gpu(a), precond="none", pivot=pivot, stop=stop, abs_thr=thr, polish_v=False,
+                   pivot_log_cap=cap, jacobi_wgs="many")
+        so = {"cert": O.STOP_CERT, "off": O.STOP_OFF, "score": O.STOP_SCORE}[stop]
+        ref = O.jacobi(a, pivot=pivot, stop=so, thr=thr, scan=1, want_vj=True)
+        assert r.status == J.OK and r.stats["jacobi_wgs"] > 1
+        piv = r.pivots.cpu().numpy()
+        if stop == "off":
+            m = min(len(piv), len(ref.pivots))
+            assert abs(len(piv) - len(ref.pivots)) <= 1
+            assert np.array_equal(piv[:m], ref.pivots[:m])
+            continue
+        assert r.stats["rotations"] == ref.rotations
+        assert np.array_equal(piv, ref.pivots)
+        d = np.diag(ref.a).copy()
+        order = np.argsort(d, kind="stable")
+        assert np.array_equal(r.w.cpu().numpy(), d[order])
+        assert np.array_equal(r.v.cpu().numpy(), ref.vj[:, order])
