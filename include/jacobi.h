@@ -108,10 +108,11 @@ typedef struct je_opts {
   int* pivot_log;            /* device int32[2*pivot_log_cap]: (p, q) of every        */
                              /* rotation of the FP64 phase, 0-based, p < q; NULL = off */
   long long pivot_log_cap;
-  int split_gemm;            /* 1: form Q^T A Q from three-slice BF16 products on the  */
-                             /* matrix cores with FP32 accumulation (FP32-level      */
-                             /* accuracy of A_hat: a precision variant, not FP64-     */
-                             /* accurate eigenvalues); 0: FP64 MFMA products     (0)  */
+  int split_gemm;            /* 1: form Q^T A Q on the BF16 matrix cores from 8-bit   */
+                             /* integer slices of the row- and column-scaled         */
+                             /* operands, summed exactly in FP32 per block of 32 and */
+                             /* added into FP64 (FP64-accurate A_hat, the precision  */
+                             /* variant); 0: FP64 MFMA products                  (0)  */
   int sort;                  /* 1: W ascending, V's columns permuted to match; 0: W in  */
                              /* the order of the final diagonal                  (1)  */
   int update_mode;           /* HBM-resident FP64 phase: 0 automatic (mirror for one    */

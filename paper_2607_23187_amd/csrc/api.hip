@@ -107,10 +107,11 @@ struct WS {
   RotEntry* log;
   void* f32;
   void* mw;       // control block and exchange area of the multi-workgroup Jacobi kernel
+  void* split;    // slice planes of the split-precision contraction (opts.split_gemm)
   long long log_cap;
 };
 
-size_t ws_bytes(int n, int precond, long long log_cap) {
+size_t ws_bytes(int n, int precond, long long log_cap, int split = 0) {
   size_t ld = ld_of(n);
   size_t mat = al((size_t)n * ld * 8);
   size_t b = 0;
@@ -126,10 +127,11 @@ size_t ws_bytes(int n, int precond, long long log_cap) {
   b += al((size_t)log_cap * sizeof(RotEntry));
   if (precond) b += al(precond_f32_bytes(n));
   b += al(mw_bytes(n));
+  if (precond && split) b += al(gemm_split_bytes(n));
   return b;
 }
 
-WS ws_carve(void* base, int n, int precond, long long log_cap) {
+WS ws_carve(void* base, int n, int precond, long long log_cap, int split = 0) {
   WS w{};
   char* p = (char*)base;
   size_t ld = ld_of(n);
@@ -171,6 +173,7 @@ WS ws_carve(void* base, int n, int precond, long long log_cap) {
   w.log = (RotEntry*)take((size_t)log_cap * sizeof(RotEntry));
   w.f32 = precond ? take(precond_f32_bytes(n)) : nullptr;
   w.mw = take(mw_bytes(n));
+  w.split = (precond && split) ? take(gemm_split_bytes(n)) : nullptr;
   w.log_cap = log_cap;
   return w;
 }
@@ -279,7 +282,7 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
               int pivot, int precond, const je_opts& o, je_stats* st, hipStream_t s,
               void* base, long long cap) {
   const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
-  WS w = ws_carve(base, n, precond, cap);
+  WS w = ws_carve(base, n, precond, cap, o.split_gemm);
   const int ld = ld_of(n);
   je_stats S{};
 
@@ -325,8 +328,8 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
     Timer tg(s);
     // A_hat = X^T (A X): T = A X, A_hat = X^T T, then exact symmetry
     if (o.split_gemm) {
-      HIPCHK(launch_gemm_split(n, 0, w.Asym, ld, X, ld, w.T, ld, s));
-      HIPCHK(launch_gemm_split(n, 1, X, ld, w.T, ld, w.A, ld, s));
+      HIPCHK(launch_gemm_split(n, 0, w.Asym, ld, X, ld, w.T, ld, w.split, s));
+      HIPCHK(launch_gemm_split(n, 1, X, ld, w.T, ld, w.A, ld, w.split, s));
     } else {
       HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
       HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
@@ -1217,7 +1220,7 @@ int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ld
   const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
   const long long cap = log_cap_for(n, maxrot);
   int err = JE_OK;
-  void* base = pool_get(ws_bytes(n, precond, cap), &err);
+  void* base = pool_get(ws_bytes(n, precond, cap, o.split_gemm), &err);
   if (!base) return err;
   return solve_one(A, n, lda, W, V, ldv, tol, pivot, precond, o, stats, s, base, cap);
 }
@@ -1252,7 +1255,7 @@ int jacobi_eigh_noalloc(const double* A, int n, int lda, double* W, double* V, i
   }
   const long long maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(n);
   const long long cap = log_cap_for(n, std::min(maxrot, kNoAllocLogCap));
-  if (ws_bytes(n, precond, cap) > kNoAllocBytes) return JE_ERR_TOO_LARGE;
+  if (ws_bytes(n, precond, cap, o.split_gemm) > kNoAllocBytes) return JE_ERR_TOO_LARGE;
   int err = JE_OK;
   void* base = scratch_address(&err);
   if (!base) return err;

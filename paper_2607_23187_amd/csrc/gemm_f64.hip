@@ -214,111 +214,161 @@ hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int ld
 }
 
 // ------------------------------------------------------------------ split-precision product
-// C = op(A) * B on the BF16 matrix cores (v_mfma_f32_16x16x16_bf16).  Every FP64 operand
-// is split into three BF16 slices, v ~ s0 + s1 + s2 (each the BF16 rounding of the FP64
-// residual left by the previous ones: about 24 significant bits), and the six slice
-// products s_a * s_b with a + b <= 2 are accumulated in FP32, smallest first.  FP32
-// accumulators are added into FP64 every kSplitFlush K steps, so FP32 rounding
-// accumulates over 128 terms rather than n (compensated accumulation).  The result carries
-// FP32-level error (~2^-24 |A| |B|): the precision variant of the Q^T A Q contraction.
+// C = op(A) * B on the BF16 matrix cores (v_mfma_f32_16x16x16_bf16) with FP64 accuracy, by
+// error-free slicing:
+//   * every row i of op(A) is scaled by 2^-ea_i and every column j of B by 2^-eb_j (exact),
+//     the powers of two that bring the row's / column's largest entry below 1;
+//   * a scaled entry x (|x| < 1) is cut into kSlices integer slices of 8 bits,
+//     x = sum_s 2^(-8 (s + 1)) alpha_s, alpha_s = rint(256 r_s), r_(s+1) = 256 r_s - alpha_s
+//     (|alpha_0| <= 256, |alpha_s| <= 128 after it): every slice is an integer that BF16
+//     holds exactly, and the cut is exact in FP64 (the residual after 7 slices is below
+//     2^-57 of the row's or column's largest entry);
+//   * products of slices are integers below 2^16, exact in FP32.  For every K block of
+//     kSplitKb = 32 terms, the slice products of one level d = s + t (all of them scaled
+//     by 2^(-8 (d + 2))) are accumulated in FP32: every partial sum is an integer below
+//     2^24 (at most 7 pairs x 32 terms x 2^16), so the FP32 accumulation is exact whatever
+//     the order inside the matrix core;
+//   * each level's exact block sum is added into an FP64 accumulator with its weight
+//     2^(-8 (d + 2)), levels d = 0 .. kSlices - 1 (slice pairs with s + t >= kSlices are
+//     below 2^-64 of |op(A)| |B| and dropped), and the row and column scales are applied
+//     at the end.
+// The FP64 accumulation over n / 32 blocks rounds like an FP64 product does; everything
+// before it is exact, so the result carries FP64-level error (the accuracy the FP64 phase
+// needs from Q^T A Q, Sec. 2.1), from 28 BF16 slice products per block.
 typedef short bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int SK = 16;          // K step (one bf16 MFMA)
-constexpr int kSplitFlush = 8;  // K steps per FP32 accumulation chunk
+constexpr int kSlices = 7;     // 8-bit slices per operand entry
+constexpr int kSplitKb = 32;   // K block accumulated exactly in FP32
+constexpr int SPL = kSplitKb + 4;  // LDS row of one slice tile (bf16), 8-byte aligned
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs)
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// bf16 bits of an integer |v| <= 256 (exact)
+__device__ __forceinline__ unsigned short bf16_int(double v) {
+  return (unsigned short)(__float_as_uint((float)v) >> 16);
 }
 
-__device__ __forceinline__ double bf16_value(unsigned short h) {
-  return (double)__uint_as_float((unsigned)h << 16);
+// Exponent e with max |x| < 2^e over the row (trans = 0: row r of M, contiguous) or the
+// column (trans = 1: column r of M); 0 for a zero row.  One wave per row / column.
+__global__ __launch_bounds__(256) void k_split_exp(const double* __restrict__ M, int n, int ld,
+                                                   int trans, int* __restrict__ ex) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  double m = 0.0;
+  for (int k = lane; k < n; k += 64)
+    m = fmax(m, fabs(trans ? M[(size_t)k * ld + r] : M[(size_t)r * ld + k]));
+  m = wave_max_d(m);
+  if (lane == 0) {
+    int e = 0;
+    if (m > 0.0) {
+      (void)frexp(m, &e);  // m = f 2^e, f in [1/2, 1): m < 2^e
+    }
+    ex[r] = e;
+  }
 }
 
-__device__ __forceinline__ void split3(double v, unsigned short& s0, unsigned short& s1,
-                                       unsigned short& s2) {
-  s0 = bf16_bits((float)v);
-  const double r1 = v - bf16_value(s0);
-  s1 = bf16_bits((float)r1);
-  const double r2 = r1 - bf16_value(s1);
-  s2 = bf16_bits((float)r2);
+// Slice planes P[s][r][k] (r < np rows of op(M) or columns of M, k < kp, zero padded) of
+// the scaled entries: trans = 0: entry M[r][k]; trans = 1: entry M[k][r].  32 x 32 tiles
+// through LDS so that both the reads and the writes are coalesced.
+__global__ __launch_bounds__(256) void k_split_slices(const double* __restrict__ M, int n, int ld,
+                                                      int trans, const int* __restrict__ ex,
+                                                      unsigned short* __restrict__ P, int np,
+                                                      int kp) {
+  __shared__ double t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int r0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
+  // t[rr][kk] = entry (r0 + rr, k0 + kk) of op(M)
+  for (int i = ty; i < 32; i += 8) {
+    const int r = r0 + (trans ? tx : i), k = k0 + (trans ? i : tx);
+    double v = 0.0;
+    if (r < n && k < n) v = trans ? M[(size_t)k * ld + r] : M[(size_t)r * ld + k];
+    if (trans) t[tx][i] = v;
+    else t[i][tx] = v;
+  }
+  __syncthreads();
+  const size_t plane = (size_t)np * kp;
+  for (int i = ty; i < 32; i += 8) {
+    const int r = r0 + i, k = k0 + tx;
+    if (r >= np || k >= kp) continue;
+    double x = (r < n) ? ldexp(t[i][tx], -ex[r]) : 0.0;
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl) {
+      const double y = x * 256.0;
+      const double a = rint(y);
+      x = y - a;
+      P[sl * plane + (size_t)r * kp + k] = bf16_int(a);
+    }
+  }
 }
 
-template <int TRANSA>
-__global__ __launch_bounds__(256) void k_gemm_split(int n, const double* __restrict__ A, int lda,
-                                                    const double* __restrict__ B, int ldb,
-                                                    double* __restrict__ C, int ldc) {
-  // sA[s][i][k]: slice s of op(A)[i0 + i][k0 + k]; sB[s][j][k]: slice s of B[k0 + k][j0 + j]
-  __shared__ __align__(8) unsigned short sA[3][GB][SK + 4];
-  __shared__ __align__(8) unsigned short sB[3][GB][SK + 4];
+// One 64 x 64 tile of C from the slice planes of op(A) (PA, rows i) and B (PB, columns j).
+__global__ __launch_bounds__(256) void k_gemm_split(int n, const unsigned short* __restrict__ PA,
+                                                    const unsigned short* __restrict__ PB,
+                                                    int kp, const int* __restrict__ ea,
+                                                    const int* __restrict__ eb,
+                                                    double* __restrict__ C, int ldc, int np) {
+  __shared__ __align__(16) unsigned short sA[kSlices][GB][SPL];
+  __shared__ __align__(16) unsigned short sB[kSlices][GB][SPL];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = blockIdx.y * GB, j0 = blockIdx.x * GB;
   const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
   const int lr = lane & 15, lq = lane >> 4;
-  f4 acc[2][2];
+  const size_t plane = (size_t)np * kp;
   double acc64[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
-    }
-  int chunk = 0;
-  for (int k0 = 0; k0 < n; k0 += SK) {
-#pragma unroll
-    for (int t = 0; t < GB * SK / 256; ++t) {
-      const int e = tid + t * 256;
-      int i, k;
-      if (TRANSA) { i = e % GB; k = e / GB; }   // A[k][i]: contiguous in i
-      else { k = e % SK; i = e / SK; }          // A[i][k]: contiguous in k
-      const int gi = i0 + i, gk = k0 + k;
-      double v = 0.0;
-      if (gi < n && gk < n) v = TRANSA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
-      split3(v, sA[0][i][k], sA[1][i][k], sA[2][i][k]);
-      const int j = e % GB, kb = e / GB;
-      const int gkb = k0 + kb, gj = j0 + j;
-      const double u = (gkb < n && gj < n) ? B[(size_t)gkb * ldb + gj] : 0.0;
-      split3(u, sB[0][j][kb], sB[1][j][kb], sB[2][j][kb]);
+  for (int k0 = 0; k0 < kp; k0 += kSplitKb) {
+    // 7 slices x 64 rows x 32 k of each operand: 8-byte pieces (4 bf16), 7 per thread each
+    for (int e = tid; e < kSlices * GB * (kSplitKb / 4); e += 256) {
+      const int sl = e / (GB * (kSplitKb / 4));
+      const int rem = e - sl * (GB * (kSplitKb / 4));
+      const int r = rem / (kSplitKb / 4), c4 = (rem % (kSplitKb / 4)) * 4;
+      *reinterpret_cast<bf4*>(&sA[sl][r][c4]) =
+          *reinterpret_cast<const bf4*>(PA + sl * plane + (size_t)(i0 + r) * kp + k0 + c4);
+      *reinterpret_cast<bf4*>(&sB[sl][r][c4]) =
+          *reinterpret_cast<const bf4*>(PB + sl * plane + (size_t)(j0 + r) * kp + k0 + c4);
     }
     __syncthreads();
-    bf4 af[3][2], bfr[3][2];
+    // level d: all slice pairs s + t = d, exact FP32 sums over the block
 #pragma unroll
-    for (int sl = 0; sl < 3; ++sl)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        af[sl][t] = *reinterpret_cast<const bf4*>(&sA[sl][wi + t * 16 + lr][4 * lq]);
-        bfr[sl][t] = *reinterpret_cast<const bf4*>(&sB[sl][wj + t * 16 + lr][4 * lq]);
-      }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        f4 c = acc[a][b];
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[2][a], bfr[0][b], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[1][a], bfr[1][b], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[0][a], bfr[2][b], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[1][a], bfr[0][b], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[0][a], bfr[1][b], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[0][a], bfr[0][b], c, 0, 0, 0);
-        acc[a][b] = c;
-      }
-    __syncthreads();
-    if (++chunk == kSplitFlush) {
-      chunk = 0;
+    for (int d = kSlices - 1; d >= 0; --d) {
+      f4 acc[2][2];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[a][b][r] += (double)acc[a][b][r];
-          acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int sa = 0; sa <= d; ++sa) {
+        const int sb = d - sa;
+#pragma unroll
+        for (int kk = 0; kk < kSplitKb; kk += 16) {
+          bf4 af[2], bfr[2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            af[t] = *reinterpret_cast<const bf4*>(&sA[sa][wi + t * 16 + lr][kk + 4 * lq]);
+            bfr[t] = *reinterpret_cast<const bf4*>(&sB[sb][wj + t * 16 + lr][kk + 4 * lq]);
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bfr[b], acc[a][b], 0,
+                                                                     0, 0);
         }
+      }
+      const double wd = ldexp(1.0, -8 * (d + 2));
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[a][b][r] += wd * (double)acc[a][b][r];
     }
+    __syncthreads();
   }
   // D[i][j] of a 16 x 16 tile sits in lane j + 16 * (i / 4), register i % 4
   // (A[i][k] in lane i + 16 (k / 4), element k % 4; B[k][j] in lane j + 16 (k / 4)).
@@ -330,16 +380,35 @@ __global__ __launch_bounds__(256) void k_gemm_split(int n, const double* __restr
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + wi + a * 16 + 4 * lq + r;
         const int j = j0 + wj + b * 16 + lr;
-        if (i < n && j < n) C[(size_t)i * ldc + j] = acc64[a][b][r] + (double)acc[a][b][r];
+        if (i < n && j < n) C[(size_t)i * ldc + j] = ldexp(acc64[a][b][r], ea[i] + eb[j]);
       }
 }
 
+static int split_np(int n) { return (n + GB - 1) / GB * GB; }
+
+size_t gemm_split_bytes(int n) {
+  const size_t np = split_np(n);
+  return 2 * (size_t)kSlices * np * np * 2 + 2 * ((np * 4 + 255) & ~(size_t)255);
+}
+
 hipError_t launch_gemm_split(int n, int transA, const double* A, int lda, const double* B,
-                             int ldb, double* C, int ldc, hipStream_t s) {
-  int nb = (n + GB - 1) / GB;
-  dim3 g(nb, nb), b(256);
-  if (transA) hipLaunchKernelGGL(k_gemm_split<1>, g, b, 0, s, n, A, lda, B, ldb, C, ldc);
-  else hipLaunchKernelGGL(k_gemm_split<0>, g, b, 0, s, n, A, lda, B, ldb, C, ldc);
+                             int ldb, double* C, int ldc, void* work, hipStream_t s) {
+  const int np = split_np(n), kp = np;  // GB is a multiple of the K block
+  const size_t plane = (size_t)np * kp;
+  unsigned short* PA = (unsigned short*)work;
+  unsigned short* PB = PA + kSlices * plane;
+  int* ea = (int*)(PB + kSlices * plane);
+  int* eb = ea + ((np * 4 + 255) & ~255) / 4;
+  const int nt = (np + 31) / 32;
+  // op(A): rows of A, or columns of A when transposed; B: its columns
+  hipLaunchKernelGGL(k_split_exp, dim3((n + 3) / 4), dim3(256), 0, s, A, n, lda, transA, ea);
+  hipLaunchKernelGGL(k_split_exp, dim3((n + 3) / 4), dim3(256), 0, s, B, n, ldb, 1, eb);
+  hipLaunchKernelGGL(k_split_slices, dim3(nt, nt), dim3(256), 0, s, A, n, lda, transA, ea, PA, np,
+                     kp);
+  hipLaunchKernelGGL(k_split_slices, dim3(nt, nt), dim3(256), 0, s, B, n, ldb, 1, eb, PB, np, kp);
+  const int nb = np / GB;
+  hipLaunchKernelGGL(k_gemm_split, dim3(nb, nb), dim3(256), 0, s, n, PA, PB, kp, ea, eb, C, ldc,
+                     np);
   return hipGetLastError();
 }
 

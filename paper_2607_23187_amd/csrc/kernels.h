@@ -105,10 +105,13 @@ hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int ld
                         const double* B, int ldb, double beta, const double* Cin, int ldcin,
                         double* C, int ldc, hipStream_t s);
 hipError_t launch_add_identity(double* C, int n, int ldc, double scale, hipStream_t s);
-// C = op(A) * B from three-slice BF16 splits on the matrix cores, FP32 accumulation flushed
-// into FP64 every 128 terms: FP32-level accuracy (the precision variant of Q^T A Q).
+// C = op(A) * B on the BF16 matrix cores with FP64 accuracy: rows of op(A) and columns of
+// B scaled by powers of two and cut into 8-bit integer slices (exact in BF16), slice
+// products summed exactly in FP32 per K block of 32 and level, each level added into FP64
+// (the precision variant of Q^T A Q).  `work`: gemm_split_bytes(n) bytes of device memory.
+size_t gemm_split_bytes(int n);
 hipError_t launch_gemm_split(int n, int transA, const double* A, int lda, const double* B,
-                             int ldb, double* C, int ldc, hipStream_t s);
+                             int ldb, double* C, int ldc, void* work, hipStream_t s);
 hipError_t launch_symmetrize(double* A, int n, int ld, hipStream_t s);
 hipError_t launch_fro2(const double* A, int n, int ld, double* partial, double* out,
                        hipStream_t s);
