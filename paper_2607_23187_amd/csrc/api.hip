@@ -18,6 +18,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -646,221 +647,256 @@ void bws_carve(char* p, BMat& b, int n, int precond, long long cap) {
 
 #define BF(f) BM_FIELD(f)
 
-// Device bytes a batch of these sizes needs (workspaces + per-batch tables).
+// Device bytes of a cohort's tables for `cnt` members (beside the members' workspaces).
+size_t cohort_meta_bytes(int cnt) {
+  return 2 * al((size_t)cnt * sizeof(BMat)) + 8 * al((size_t)cnt * 4 + 4) + al(64) +
+         al((size_t)cnt * sizeof(BInfo));
+}
+
+// Device bytes a batch of these sizes needs (workspaces + tables).
 size_t batch_bytes(const std::vector<int>& sizes, int precond) {
   size_t tot = 0;
   for (int nn : sizes) tot += bws_bytes(nn, precond, kBatchLogCap);
-  const size_t cnt = sizes.size();
-  return tot + al(cnt * sizeof(BMat)) + 8 * al(cnt * 4 + 4) + al(64) + al(cnt * sizeof(BInfo));
+  return tot + cohort_meta_bytes((int)sizes.size());
 }
 
-// Device memory for one batched solve: the library's pool, or a server worker's buffer.
-using WsGet = void* (*)(size_t bytes, int* err, void* ctx);
+// One problem of a cohort: the caller's arrays, its workspace, and the caller's index.
+struct Member {
+  const double* A;
+  int n, lda;
+  double* W;
+  double* V;
+  int ldv;
+  char* ws;     // bws_bytes(n, precond, kBatchLogCap) bytes of device memory
+  int idx;      // index of the problem in the caller's arrays (or request slot)
+};
 
-void* pool_ws(size_t bytes, int* err, void*) { return pool_get(bytes, err); }
+// A set of problems solved together in bounded steps (the batched method of the library):
+// begin() checks and scales the inputs, every step() advances the whole cohort by one
+// bounded piece of work (a few FP32 rounds, one Newton-Schulz step, one persistent FP64
+// Jacobi launch of at most `step_rot` rotations per member, ...).  Members whose FP64 phase
+// has ended are finalised (polish, sort, output) at the end of the step that ended it and
+// leave the cohort; their results are appended to `left`.  Every member gives the same
+// bits whatever its cohort: all launches act on each member independently, in the same
+// order of operations.
+struct Cohort {
+  enum Phase { SETUP, F32A, NS1, REFINE, F32B, NS2, CONTRACT, JACOBI, DONE };
+  struct Left {
+    int idx;         // Member::idx
+    int status;
+    je_stats st;
+  };
 
-int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
-                  const int* lda, double* const* W, double* const* V, const int* ldv, double tol,
-                  int pivot, int precond, const je_opts& o, int* info, je_stats* stats,
-                  hipStream_t s, WsGet ws_get = pool_ws, void* ws_ctx = nullptr) {
-  int cnt = (int)mem.size();
-  if (cnt == 0) return JE_OK;
-  int nmax = 0;
-  for (int b : mem) nmax = std::max(nmax, n[b]);
-  std::vector<size_t> woff(cnt);
-  size_t tot = 0;
-  for (int i = 0; i < cnt; ++i) {
-    woff[i] = tot;
-    tot += bws_bytes(n[mem[i]], precond, kBatchLogCap);
-  }
-  const size_t meta = al((size_t)cnt * sizeof(BMat)) + 8 * al((size_t)cnt * 4 + 4) + al(64) +
-                      al((size_t)cnt * sizeof(BInfo));
-  int err = JE_OK;
-  char* base = (char*)ws_get(tot + meta, &err, ws_ctx);
-  if (!base) return err;
-  char* mp = base + tot;
-  BMat* dm = (BMat*)mp; mp += al((size_t)cnt * sizeof(BMat));
-  int* d_idx_lds = (int*)mp; mp += al((size_t)cnt * 4 + 4);
-  int* d_idx_hbm = (int*)mp; mp += al((size_t)cnt * 4 + 4);
-  int* d_work = (int*)mp; mp += 5 * al((size_t)cnt * 4 + 4);  // FP32 stage launch lists
-  int* d_cnt = (int*)mp;  // [0], [1] queue counters, [2] pending
-  mp += al(64);
-  BInfo* d_info = (BInfo*)mp;
-  std::vector<BInfo> hi(cnt);
-  auto collect = [&]() -> int {
+  // configuration
+  double tol = 0.0;
+  int pivot = 1, precond = 1;
+  je_opts o{};
+  hipStream_t s = nullptr;
+  long long step_rot = kBatchLogCap;
+  // members (arrays compacted when members leave)
+  std::vector<Member> mem;
+  std::vector<BMat> hm;
+  std::vector<BInfo> hi;
+  std::vector<double> nrm;
+  std::vector<int> nv;
+  int cnt = 0, nmax = 0;
+  // device tables
+  char* meta = nullptr;
+  BMat *dm = nullptr, *dfin = nullptr;
+  int *d_idx_lds = nullptr, *d_idx_hbm = nullptr, *d_work = nullptr, *d_cnt = nullptr;
+  BInfo* d_info = nullptr;
+  // progress
+  Phase phase = SETUP;
+  int ns_iter = 0, pass = 0;
+  size_t offX = BF(X), offXb = BF(Xb);
+  F32Batch f32;
+  bool mirror = false;
+  int shape_lds = 64, shape_hbm = 512;
+  je_stats S{};
+  float ms_kernel = 0.f, ms_apply = 0.f;
+  std::vector<Left> left;
+
+  int collect() {
     HIPCHK(launch_collect_b(dm, cnt, d_info, s));
     HIPCHK(hipMemcpyAsync(hi.data(), d_info, (size_t)cnt * sizeof(BInfo), hipMemcpyDeviceToHost,
                           s));
     HIPCHK(hipStreamSynchronize(s));
     return JE_OK;
-  };
-
-  std::vector<BMat> hm(cnt);
-  for (int i = 0; i < cnt; ++i) {
-    const int b = mem[i];
-    BMat& x = hm[i];
-    std::memset(&x, 0, sizeof(x));
-    x.Au = Ain[b]; x.n = n[b]; x.lda = lda[b];
-    x.Wout = W[b]; x.Vout = V ? V[b] : nullptr; x.ldv = ldv ? ldv[b] : n[b];
-    bws_carve(base + woff[i], x, n[b], precond, kBatchLogCap);
   }
-  auto upload = [&]() -> int {
+  int upload() {
     HIPCHK(hipMemcpyAsync(dm, hm.data(), (size_t)cnt * sizeof(BMat), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return JE_OK;
-  };
-  if (int r = upload()) return r;
-  auto download = [&]() -> int {
+  }
+  int download() {
     HIPCHK(hipMemcpyAsync(hm.data(), dm, (size_t)cnt * sizeof(BMat), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return JE_OK;
-  };
-  je_stats S{};
-  Timer tp(s);
-  // ---- 1. symmetric copies, finiteness, range, ||A||_F
-  HIPCHK(launch_reset_b(dm, cnt, s));
-  HIPCHK(launch_symcopy_b(dm, cnt, nmax, s));
-  HIPCHK(launch_maxabs_b(dm, cnt, nmax, BF(Asym), 4, s));
-  if (int r = collect()) return r;
-  // out-of-range members are solved as 2^e A (exact), their eigenvalues scaled back
-  {
-    bool any = false;
+  }
+  void refresh_sizes() {
+    nmax = 0;
+    nv.resize(cnt);
     for (int i = 0; i < cnt; ++i) {
-      hm[i].a_exp = hi[i].nonfinite ? 0 : range_exp(hi[i].maxabs);
-      any = any || hm[i].a_exp != 0;
-    }
-    if (any) {
-      if (int r = upload()) return r;
-      HIPCHK(launch_scale_b(dm, cnt, nmax, BF(Asym), s));
+      nv[i] = hm[i].n;
+      nmax = std::max(nmax, hm[i].n);
     }
   }
-  HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(Asym), 0, s));
-  if (int r = collect()) return r;
-  for (int i = 0; i < cnt; ++i)
-    if (!hi[i].nonfinite && !std::isfinite(hi[i].normF)) hi[i].nonfinite = 1;
-  // members with a non-finite entry leave the batch here (status JE_ERR_NONFINITE, outputs
-  // untouched, as for a single problem)
-  int worst = JE_OK;
-  {
-    std::vector<int> keep;
+  // Keep the members with keep[i] != 0 (device state downloaded first, tables re-uploaded).
+  int compact(const std::vector<char>& keep) {
+    if (int r = download()) return r;
+    std::vector<Member> m2;
+    std::vector<BMat> h2;
+    std::vector<BInfo> i2;
+    std::vector<double> n2;
+    for (int i = 0; i < cnt; ++i)
+      if (keep[i]) {
+        m2.push_back(mem[i]); h2.push_back(hm[i]); i2.push_back(hi[i]);
+        n2.push_back(nrm.empty() ? 0.0 : nrm[i]);
+      }
+    mem.swap(m2); hm.swap(h2); hi.swap(i2);
+    if (!nrm.empty()) nrm.swap(n2);
+    cnt = (int)mem.size();
+    refresh_sizes();
+    if (cnt == 0) { phase = DONE; return JE_OK; }
+    return upload();
+  }
+  void leave(int i, int status, const je_stats* st) {
+    Left l;
+    l.idx = mem[i].idx;
+    l.status = status;
+    if (st) l.st = *st;
+    else { std::memset(&l.st, 0, sizeof(l.st)); l.st.status = status; }
+    left.push_back(l);
+  }
+
+  // members: workspaces already assigned; meta: cohort_meta_bytes(members.size()) bytes
+  int begin(std::vector<Member> members, char* meta_, double tol_, int pivot_, int precond_,
+            const je_opts& o_, hipStream_t s_, long long step_rot_) {
+    mem = std::move(members);
+    cnt = (int)mem.size();
+    tol = tol_; pivot = pivot_; precond = precond_; o = o_; s = s_; step_rot = step_rot_;
+    meta = meta_;
+    char* mp = meta;
+    dm = (BMat*)mp; mp += al((size_t)cnt * sizeof(BMat));
+    dfin = (BMat*)mp; mp += al((size_t)cnt * sizeof(BMat));
+    d_idx_lds = (int*)mp; mp += al((size_t)cnt * 4 + 4);
+    d_idx_hbm = (int*)mp; mp += al((size_t)cnt * 4 + 4);
+    d_work = (int*)mp; mp += 5 * al((size_t)cnt * 4 + 4);  // FP32 stage launch lists
+    d_cnt = (int*)mp; mp += al(64);                        // queue counters
+    d_info = (BInfo*)mp;
+    hi.assign(cnt, BInfo{});
+    hm.assign(cnt, BMat{});
     for (int i = 0; i < cnt; ++i) {
-      if (hi[i].nonfinite) {
-        info[mem[i]] = JE_ERR_NONFINITE;
-        worst = JE_ERR_NONFINITE;
-        if (stats) { std::memset(&stats[mem[i]], 0, sizeof(je_stats)); stats[mem[i]].status = JE_ERR_NONFINITE; }
-      } else {
-        keep.push_back(i);
+      BMat& x = hm[i];
+      std::memset(&x, 0, sizeof(x));
+      x.Au = mem[i].A; x.n = mem[i].n; x.lda = mem[i].lda;
+      x.Wout = mem[i].W; x.Vout = mem[i].V; x.ldv = mem[i].ldv;
+      bws_carve(mem[i].ws, x, mem[i].n, precond, kBatchLogCap);
+    }
+    refresh_sizes();
+    if (int r = upload()) return r;
+    Timer tp(s);
+    // ---- symmetric copies, finiteness, range, ||A||_F
+    HIPCHK(launch_reset_b(dm, cnt, s));
+    HIPCHK(launch_symcopy_b(dm, cnt, nmax, s));
+    HIPCHK(launch_maxabs_b(dm, cnt, nmax, BF(Asym), 4, s));
+    if (int r = collect()) return r;
+    // out-of-range members are solved as 2^e A (exact), their eigenvalues scaled back
+    {
+      bool any = false;
+      for (int i = 0; i < cnt; ++i) {
+        hm[i].a_exp = hi[i].nonfinite ? 0 : range_exp(hi[i].maxabs);
+        any = any || hm[i].a_exp != 0;
+      }
+      if (any) {
+        if (int r = upload()) return r;
+        HIPCHK(launch_scale_b(dm, cnt, nmax, BF(Asym), s));
       }
     }
-    if ((int)keep.size() < cnt) {
-      std::vector<BMat> h2;
-      std::vector<int> m2;
-      std::vector<BInfo> i2;
-      for (int i : keep) { h2.push_back(hm[i]); m2.push_back(mem[i]); i2.push_back(hi[i]); }
-      hm.swap(h2); mem.swap(m2); hi.swap(i2);
-      cnt = (int)keep.size();
-      if (cnt == 0) return worst;
-      if (int r = upload()) return r;
+    HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(Asym), 0, s));
+    if (int r = collect()) return r;
+    // members with a non-finite entry leave here (outputs untouched, as for one problem)
+    {
+      std::vector<char> keep(cnt, 1);
+      bool drop = false;
+      for (int i = 0; i < cnt; ++i)
+        if (hi[i].nonfinite || !std::isfinite(hi[i].normF)) {
+          leave(i, JE_ERR_NONFINITE, nullptr);
+          keep[i] = 0;
+          drop = true;
+        }
+      if (drop) {
+        if (int r = compact(keep)) return r;
+        if (cnt == 0) return JE_OK;
+      }
     }
-  }
-  std::vector<double> nrm(cnt);
-  for (int i = 0; i < cnt; ++i) nrm[i] = hi[i].normF;
-  // largest first: the order of the FP64 work queue
-  std::vector<int> ord(cnt);
-  for (int i = 0; i < cnt; ++i) ord[i] = i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hm[a].n > hm[b].n; });
-  const long long maxrot_opt = o.max_rotations;
-  for (int i = 0; i < cnt; ++i) {
-    BMat& x = hm[i];
-    const int nn = x.n;
-    JDesc& d = x.jd;
-    double thr;
-    if (o.abs_thr > 0.0) thr = std::ldexp(o.abs_thr, x.a_exp);
-    else if (o.stop == JE_STOP_CERT) thr = tol * nrm[i] / (2.0 * nn * (double)(nn - 1));
-    else thr = tol * nrm[i];
-    d.A = precond ? x.A : x.Asym;
-    d.n = nn; d.ld = x.ld; d.diag = x.diag;
-    d.thr = thr;
-    d.maxrot = maxrot_opt > 0 ? maxrot_opt : default_maxrot(nn);
-    d.pivot = pivot; d.stop = o.stop;
-    d.prof = nullptr;
-    x.log_base = 0;
-    x.f_pass_sweeps = 0;
-  }
-  if (int r = upload()) return r;
-  // non-finite inputs: reported, their workspaces still processed (results discarded)
-  // ---- 2. preconditioner
-  float ms_gemm = 0.f;
-  size_t offX = BF(X), offXb = BF(Xb);
-  // Newton-Schulz on every member: a member stops stepping once it meets the single
-  // problem's rule (ns_converged); its later steps in the batch take R = 0 and leave X
-  // bit for bit, so its result does not depend on its batch-mates.
-  auto orthonormalize_b = [&]() -> int {
-    HIPCHK(launch_ns_reset_b(dm, cnt, s));
-    for (int itn = 0; itn < 6; ++itn) {
-      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s, 1));
-      HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s, 1));
-      HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(R), 1, s));
-      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, offX, BF(R), 1.0, offX, offXb, s));
-      std::swap(offX, offXb);
-      HIPCHK(launch_ns_flag_b(dm, cnt, s));
-      if (int r = collect()) return r;
-      bool all = true;
-      for (int i = 0; i < cnt; ++i) all = all && ns_converged(hi[i].rnorm, hm[i].n);
-      if (all) break;
+    nrm.resize(cnt);
+    for (int i = 0; i < cnt; ++i) nrm[i] = hi[i].normF;
+    for (int i = 0; i < cnt; ++i) {
+      BMat& x = hm[i];
+      const int nn = x.n;
+      JDesc& d = x.jd;
+      double thr;
+      if (o.abs_thr > 0.0) thr = std::ldexp(o.abs_thr, x.a_exp);
+      else if (o.stop == JE_STOP_CERT) thr = tol * nrm[i] / (2.0 * nn * (double)(nn - 1));
+      else thr = tol * nrm[i];
+      d.A = precond ? x.A : x.Asym;
+      d.n = nn; d.ld = x.ld; d.diag = x.diag;
+      d.thr = thr;
+      d.maxrot = o.max_rotations > 0 ? o.max_rotations : default_maxrot(nn);
+      d.pivot = pivot; d.stop = o.stop;
+      d.prof = nullptr;
+      // a persistent launch stops a member after step_rot rotations (log drained between)
+      d.log_cap = std::min<long long>(d.log_cap, step_rot);
+      x.log_base = 0;
+      x.f_pass_sweeps = 0;
     }
+    if (int r = upload()) return r;
+    // a batch keeps rows only (timestamp mode) unless asked otherwise: with hundreds of
+    // matrices in flight the mirrored column stores, each dirtying a cache line for 8
+    // bytes, make HBM writes the larger cost
+    mirror = o.update_mode == 1;
+    if (precond) {
+      HIPCHK(f32.begin(dm, nv.data(), cnt, nmax, d_work, BF(Asym), offX, o.fp32_max_sweeps,
+                       f32_tol1(o.fp32_passes), kF32Rho1, s));
+      phase = F32A;
+    } else {
+      HIPCHK(launch_set_identity_b(dm, cnt, nmax, BF(Vw), s));
+      phase = CONTRACT;
+    }
+    S.ms_precond += tp.stop();
     return JE_OK;
-  };
-  if (precond) {
-    std::vector<int> nv(cnt);
-    for (int i = 0; i < cnt; ++i) nv[i] = hm[i].n;
-    auto f32pass = [&](size_t src, size_t dst, double t, double r) -> int {
-      HIPCHK(run_precond_f32_b(dm, nv.data(), cnt, nmax, d_work, src, dst, o.fp32_max_sweeps, t,
-                               r, s));
-      return JE_OK;
-    };
-    if (int r = f32pass(BF(Asym), offX, f32_tol1(o.fp32_passes), kF32Rho1)) return r;
-    if (int r = orthonormalize_b()) return r;
-    for (int pass = 1; pass < o.fp32_passes; ++pass) {
-      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
-      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
-      HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
-      if (int r = f32pass(BF(A), BF(T), kF32Tol2, kF32Rho2)) return r;
-      HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, offX, BF(T), 0.0, 0, offXb, s));
-      std::swap(offX, offXb);
-      if (int r = orthonormalize_b()) return r;
-    }
-    S.ms_precond = tp.stop();
-    Timer tg(s);
-    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
-    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
-    HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
-    HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(Vw), offX, s));
-    HIPCHK(launch_get_diag_b(dm, cnt, nmax, BF(A), s));
-    ms_gemm = tg.stop();
-  } else {
-    HIPCHK(launch_set_identity_b(dm, cnt, nmax, BF(Vw), s));
-    S.ms_precond = tp.stop();
   }
-  // ---- 3. FP64 pivoted Jacobi: persistent launches until every matrix is done
-  Timer tj(s);
-  HIPCHK(launch_reset_b(dm, cnt, s));
-  const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
-  HIPCHK(launch_init_rows_b(dm, cnt, nmax, pivot, use_cert, s));
-  // a batch keeps rows only (timestamp mode) unless asked otherwise: with hundreds of
-  // matrices in flight the mirrored column stores, each dirtying a cache line for 8 bytes,
-  // make HBM writes the larger cost
-  const bool mirror = o.update_mode == 1;
-  // workgroup shape of each class: tuned once per (class, pivot, size bucket) and cached
-  int shape_lds = 64, shape_hbm = 512;
-  {
-    std::vector<int> il, ih;
+
+  // One Newton-Schulz step on every member not yet converged; *converged when all are.
+  int ns_step(bool* converged) {
+    if (ns_iter == 0) HIPCHK(launch_ns_reset_b(dm, cnt, s));
+    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s, 1));
+    HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s, 1));
+    HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(R), 1, s));
+    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, offX, BF(R), 1.0, offX, offXb, s));
+    std::swap(offX, offXb);
+    HIPCHK(launch_ns_flag_b(dm, cnt, s));
+    if (int r = collect()) return r;
+    bool all = true;
+    for (int i = 0; i < cnt; ++i) all = all && ns_converged(hi[i].rnorm, hm[i].n);
+    ++ns_iter;
+    *converged = all || ns_iter >= 6;
+    if (*converged) ns_iter = 0;
+    return JE_OK;
+  }
+
+  // Workgroup shape of each class: tuned once per (class, pivot, size bucket) and cached.
+  int tune_shapes() {
+    std::vector<int> ord(cnt), il, ih;
+    for (int i = 0; i < cnt; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hm[a].n > hm[b].n; });
     int nl = 0, nh = 0;
-    for (int k = 0; k < cnt; ++k) {
-      const int i = ord[k];
+    for (int i : ord) {
       if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
       else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
     }
+    const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
     auto tuned = [&](bool lds, const std::vector<int>& lst, int nmx, int* shape) -> int {
       if (lst.empty()) return JE_OK;
       // the default shape first; the other replaces it only if it is 5% faster
@@ -882,109 +918,249 @@ int solve_batched(std::vector<int> mem, const double* const* Ain, const int* n,
       const size_t offJ = precond ? BF(A) : BF(Asym);
       // the FP64 matrices of the whole batch are saved in T and restored after each trial
       HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(T), offJ, s));
-      float best = 1e30f;
       float t_default = 0.f;
       for (int shp : {a, b}) {
-        HIPCHK(hipMemsetAsync(d_cnt, 0, 8, s));
+        HIPCHK(launch_zero_words(d_cnt, 2, s));
         Timer tt(s);
         HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)smp.size(), nmx, pivot, lds, mirror,
                                    shp, d_cnt,
                                    (int)std::min<size_t>(smp.size(), lds ? 2048 : 1024), s));
         const float ms = tt.stop();
-        if (shp == a) { t_default = ms; best = ms; *shape = a; }
-        else if (ms < 0.95f * t_default) { best = ms; *shape = shp; }
+        if (shp == a) { t_default = ms; *shape = a; }
+        else if (ms < 0.95f * t_default) { *shape = shp; }
         HIPCHK(launch_copy_mat_b(dm, cnt, nmax, offJ, BF(T), s));
         HIPCHK(launch_get_diag_b(dm, cnt, nmax, offJ, s));
         HIPCHK(launch_reset_b(dm, cnt, s));
         HIPCHK(launch_init_rows_b(dm, cnt, nmax, pivot, use_cert, s));
       }
+      HIPCHK(hipStreamSynchronize(s));
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune[key] = *shape;
       return JE_OK;
     };
     if (int r = tuned(true, il, nl, &shape_lds)) return r;
     if (int r = tuned(false, ih, nh, &shape_hbm)) return r;
+    return JE_OK;
   }
-  std::vector<JCtl> hc(cnt);
-  std::vector<char> done(cnt, 0);
-  float ms_kernel = 0.f, ms_apply = 0.f;
-  for (int launch = 0;; ++launch) {
-    std::vector<int> il, ih;
-    int nl = 0, nh = 0;
-    for (int k = 0; k < cnt; ++k) {
-      const int i = ord[k];
-      if (done[i]) continue;
-      if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
-      else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
+
+  // Members whose FP64 phase ended: polish, sort, output (on a table of just them), report,
+  // and leave the cohort.
+  int finalize(const std::vector<char>& fin) {
+    std::vector<BMat> hf;
+    for (int i = 0; i < cnt; ++i)
+      if (fin[i]) hf.push_back(hm[i]);
+    const int nf = (int)hf.size();
+    if (nf == 0) return JE_OK;
+    int nfmax = 0;
+    for (const BMat& x : hf) nfmax = std::max(nfmax, x.n);
+    Timer tf(s);
+    HIPCHK(hipMemcpyAsync(dfin, hf.data(), (size_t)nf * sizeof(BMat), hipMemcpyHostToDevice, s));
+    bool anyv = false;
+    for (const BMat& x : hf) anyv = anyv || x.Vout != nullptr;
+    if (anyv && o.polish_v) {
+      HIPCHK(launch_dgemm_b(dfin, nf, nfmax, 1, -1.0, BF(Vw), BF(Vw), 0.0, 0, BF(R), s));
+      HIPCHK(launch_add_identity_b(dfin, nf, nfmax, BF(R), 1.0, s));
+      HIPCHK(launch_dgemm_b(dfin, nf, nfmax, 0, 0.5, BF(Vw), BF(R), 1.0, BF(Vw), BF(X), s));
+      HIPCHK(launch_copy_mat_b(dfin, nf, nfmax, BF(Vw), BF(X), s));
     }
-    if (il.empty() && ih.empty()) break;
-    if (!il.empty())
-      HIPCHK(hipMemcpyAsync(d_idx_lds, il.data(), il.size() * 4, hipMemcpyHostToDevice, s));
-    if (!ih.empty())
-      HIPCHK(hipMemcpyAsync(d_idx_hbm, ih.data(), ih.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(d_cnt, 0, 8, s));
+    HIPCHK(launch_sort_output_b(dfin, nf, nfmax, o.sort, s));
     HIPCHK(hipStreamSynchronize(s));
-    Timer tk(s);
-    if (!il.empty())
-      HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, mirror,
-                                 shape_lds, d_cnt, (int)std::min<size_t>(il.size(), 2048), s));
-    if (!ih.empty())
-      HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, mirror,
-                                 shape_hbm, d_cnt + 1, (int)std::min<size_t>(ih.size(), 1024),
-                                 s));
-    ms_kernel += tk.stop();
-    Timer ta(s);
-    HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
-    ms_apply += ta.stop();
-    if (int r = collect()) return r;
-    for (int i = 0; i < cnt; ++i) { hc[i] = hi[i].ctl; done[i] = hc[i].done ? 1 : 0; }
-  }
-  S.ms_jacobi = tj.stop();
-  S.ms_jacobi_kernel = ms_kernel;
-  S.ms_apply_log = ms_apply;
-  // ---- 4. polish, sort, output
-  Timer tf(s);
-  if (V && o.polish_v) {
-    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, BF(Vw), BF(Vw), 0.0, 0, BF(R), s));
-    HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s));
-    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, BF(Vw), BF(R), 1.0, BF(Vw), BF(X), s));
-    HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(Vw), BF(X), s));
-  }
-  HIPCHK(launch_sort_output_b(dm, cnt, nmax, o.sort, s));
-  if (int r = download()) return r;
-  S.ms_finalize = tf.stop();
-  S.ms_gemm = ms_gemm;
-  for (int i = 0; i < cnt; ++i) {
-    const int b = mem[i];
-    int st = hc[i].status == ST_MAXROT ? JE_WARN_MAXROT
-             : (hc[i].status == ST_STALL ? JE_WARN_STALL : JE_OK);
-    info[b] = st;
-    worst = std::max(worst, st);
-    if (stats) {
-      je_stats& x = stats[b];
+    const float ms_fin = tf.stop();
+    std::vector<char> keep(cnt, 1);
+    for (int i = 0; i < cnt; ++i) {
+      if (!fin[i]) continue;
+      keep[i] = 0;
+      const JCtl& c = hi[i].ctl;
+      const int st = c.status == ST_MAXROT ? JE_WARN_MAXROT
+                     : (c.status == ST_STALL ? JE_WARN_STALL : JE_OK);
+      je_stats x = S;
       const double unscale = std::ldexp(1.0, -hm[i].a_exp);
-      x = S;
-      x.rotations = hc[i].rotations;
-      x.rescans = hc[i].rescans;
-      x.final_max_score = hc[i].final_cert * unscale;
-      x.final_off = hc[i].final_off * unscale;
+      x.ms_jacobi_kernel = ms_kernel;
+      x.ms_apply_log = ms_apply;
+      x.ms_finalize = ms_fin;
+      x.rotations = c.rotations;
+      x.rescans = c.rescans;
+      x.final_max_score = c.final_cert * unscale;
+      x.final_off = c.final_off * unscale;
       x.normF = nrm[i] * unscale;
       x.thr = hm[i].jd.thr * unscale;
       x.sweeps32 = hm[i].f_pass_sweeps;
       x.scale_exp = hm[i].a_exp;
+      x.jacobi_wgs = 1;
       x.status = st;
+      leave(i, st, &x);
     }
+    return compact(keep);
+  }
+
+  // One bounded piece of work.
+  int step() {
+    switch (phase) {
+      case F32A:
+      case F32B: {
+        Timer tp(s);
+        HIPCHK(f32.advance(8));
+        if (f32.finished) {
+          if (phase == F32A) {
+            phase = NS1;
+          } else {
+            HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, offX, BF(T), 0.0, 0, offXb, s));
+            std::swap(offX, offXb);
+            phase = NS2;
+          }
+        }
+        S.ms_precond += tp.stop();
+        return JE_OK;
+      }
+      case NS1:
+      case NS2: {
+        Timer tp(s);
+        bool conv = false;
+        if (int r = ns_step(&conv)) return r;
+        if (conv) {
+          if (phase == NS1 && pass + 1 < o.fp32_passes) phase = REFINE;
+          else phase = CONTRACT;
+          if (phase == REFINE) ++pass;
+        }
+        if (phase == CONTRACT) {
+          // the contraction below is timed as ms_gemm
+          S.ms_precond += tp.stop();
+          return JE_OK;
+        }
+        S.ms_precond += tp.stop();
+        return JE_OK;
+      }
+      case REFINE: {
+        Timer tp(s);
+        HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
+        HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
+        HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
+        HIPCHK(f32.begin(dm, nv.data(), cnt, nmax, d_work, BF(A), BF(T), o.fp32_max_sweeps,
+                         kF32Tol2, kF32Rho2, s));
+        phase = F32B;
+        S.ms_precond += tp.stop();
+        return JE_OK;
+      }
+      case CONTRACT: {
+        if (precond) {
+          Timer tg(s);
+          HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
+          HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
+          HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
+          HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(Vw), offX, s));
+          HIPCHK(launch_get_diag_b(dm, cnt, nmax, BF(A), s));
+          S.ms_gemm += tg.stop();
+        }
+        Timer tj(s);
+        HIPCHK(launch_reset_b(dm, cnt, s));
+        const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
+        HIPCHK(launch_init_rows_b(dm, cnt, nmax, pivot, use_cert, s));
+        if (int r = tune_shapes()) return r;
+        phase = JACOBI;
+        S.ms_jacobi += tj.stop();
+        return JE_OK;
+      }
+      case JACOBI: {
+        Timer tj(s);
+        std::vector<int> ord(cnt);
+        for (int i = 0; i < cnt; ++i) ord[i] = i;
+        // largest first: the order of the FP64 work queue
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hm[a].n > hm[b].n; });
+        std::vector<int> il, ih;
+        int nl = 0, nh = 0;
+        for (int i : ord) {
+          if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
+          else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
+        }
+        if (!il.empty())
+          HIPCHK(hipMemcpyAsync(d_idx_lds, il.data(), il.size() * 4, hipMemcpyHostToDevice, s));
+        if (!ih.empty())
+          HIPCHK(hipMemcpyAsync(d_idx_hbm, ih.data(), ih.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_zero_words(d_cnt, 2, s));
+        HIPCHK(hipStreamSynchronize(s));  // the index vectors are host memory
+        Timer tk(s);
+        if (!il.empty())
+          HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, mirror,
+                                     shape_lds, d_cnt, (int)std::min<size_t>(il.size(), 2048),
+                                     s));
+        if (!ih.empty())
+          HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, mirror,
+                                     shape_hbm, d_cnt + 1,
+                                     (int)std::min<size_t>(ih.size(), 1024), s));
+        ms_kernel += tk.stop();
+        Timer ta(s);
+        HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
+        ms_apply += ta.stop();
+        if (int r = collect()) return r;
+        S.ms_jacobi += tj.stop();
+        std::vector<char> fin(cnt, 0);
+        bool any = false;
+        for (int i = 0; i < cnt; ++i) {
+          fin[i] = hi[i].ctl.done ? 1 : 0;
+          any = any || fin[i];
+        }
+        if (any) return finalize(fin);
+        return JE_OK;
+      }
+      default:
+        return JE_OK;
+    }
+  }
+};
+
+// All problems of a batch (n >= 2) go through one cohort: every launch covers the whole
+// batch (grids sized for the largest n, blocks past a matrix's n exit).  The FP32 stage
+// runs each matrix at its own pace; the FP64 Jacobi phase is one persistent launch per
+// workgroup shape (LDS-resident n <= 128, HBM-resident above), each workgroup taking the
+// next matrix, largest first, from a device counter.  Logs are drained for all matrices
+// between launches; unfinished matrices are relaunched.
+int solve_batched(std::vector<int> idx, const double* const* Ain, const int* n,
+                  const int* lda, double* const* W, double* const* V, const int* ldv, double tol,
+                  int pivot, int precond, const je_opts& o, int* info, je_stats* stats,
+                  hipStream_t s) {
+  const int cnt = (int)idx.size();
+  if (cnt == 0) return JE_OK;
+  std::vector<Member> mem(cnt);
+  size_t tot = 0;
+  std::vector<size_t> woff(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    woff[i] = tot;
+    tot += bws_bytes(n[idx[i]], precond, kBatchLogCap);
+  }
+  int err = JE_OK;
+  char* base = (char*)pool_get(tot + cohort_meta_bytes(cnt), &err);
+  if (!base) return err;
+  for (int i = 0; i < cnt; ++i) {
+    const int b = idx[i];
+    mem[i] = Member{Ain[b], n[b], lda[b], W[b], V ? V[b] : nullptr, ldv ? ldv[b] : n[b],
+                    base + woff[i], b};
+  }
+  Cohort c;
+  int r = c.begin(mem, base + tot, tol, pivot, precond, o, s, kBatchLogCap);
+  while (r == JE_OK && c.phase != Cohort::DONE) r = c.step();
+  if (r != JE_OK) return r;
+  int worst = JE_OK;
+  for (const Cohort::Left& l : c.left) {
+    info[l.idx] = l.status;
+    worst = std::max(worst, l.status);
+    if (stats) stats[l.idx] = l.st;
   }
   return worst;
 }
 
 // ------------------------------------------------------------------ serving
-// Requests wait in a FIFO queue.  Each worker (a host thread with its own stream and
-// device buffer) takes, when it is free, every queued request that fits its buffer, in
-// arrival order (admission by workspace footprint; a request larger than the buffer is
-// taken alone and the buffer grows), and solves them as one batch.  Requests that arrive
-// while the workers are busy join the next batch a worker forms; the workers' batches run
-// concurrently on the device.
+// Continuous batching of a request stream.  One device buffer of hbm_budget bytes (the
+// arena) holds the workspaces of every request in flight; `lanes` host threads, each with
+// its own stream, run cohorts (Cohort above) in bounded steps.  At every step boundary a
+// lane admits queued requests: the oldest one and the queued requests of its size class
+// (n <= 128, <= 512, <= 1024, larger), in arrival order, as far as their workspaces fit in
+// the arena, form a new cohort that runs beside the lane's other cohorts.  A request whose
+// workspace does not fit stays queued until memory is freed.  Members whose solve has
+// ended leave their cohort at the end of that step: their completion record is posted and
+// their workspace returned to the arena.  Cohorts of different lanes run concurrently on
+// the device; the cohorts of one lane interleave step by step.
+constexpr long long kServeStepRot = 4096;  // FP64 rotations per member per step
+
 struct SrvReq {
   const double* A;
   int n, lda;
@@ -993,6 +1169,48 @@ struct SrvReq {
   int ldv;
   long long tag;
   double t_submit;
+};
+
+// First-fit allocator over the arena (offsets in 256-byte units), adjacent free blocks
+// merged on release.
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0;
+  std::map<size_t, size_t> free_;  // offset -> size
+  void init(char* b, size_t n) {
+    base = b;
+    bytes = n & ~(size_t)255;
+    free_.clear();
+    if (bytes) free_[0] = bytes;
+  }
+  char* get(size_t n) {
+    n = al(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > n) free_[off + n] = sz - n;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void put(char* p, size_t n) {
+    n = al(n);
+    size_t off = (size_t)(p - base);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + n == next->first) {
+      n += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
 };
 
 struct Server {
@@ -1008,106 +1226,168 @@ struct Server {
   long long in_flight = 0;
   bool stop = false;
   int error = 0;
-  std::vector<std::thread> workers;
+  void* buffer = nullptr;
+  Arena arena;
+  long long mem_gen = 0;  // incremented whenever memory returns to the arena
+  std::vector<std::thread> lanes;
   std::chrono::steady_clock::time_point t0;
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 };
 
-struct WorkerBuf {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-
-void* worker_ws(size_t bytes, int* err, void* ctx) {
-  WorkerBuf* b = (WorkerBuf*)ctx;
-  if (b->bytes < bytes) {
-    if (b->ptr) { (void)hipFree(b->ptr); b->ptr = nullptr; b->bytes = 0; }
-    if (hipMalloc(&b->ptr, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      *err = JE_ERR_NOMEM;
-      return nullptr;
-    }
-    b->bytes = bytes;
-  }
-  return b->ptr;
-}
-
 int size_class(int n) { return n <= 128 ? 0 : (n <= 512 ? 1 : (n <= 1024 ? 2 : 3)); }
 
-void server_worker(Server* S) {
+// A cohort of a lane and the arena blocks it holds.
+struct LaneCohort {
+  Cohort c;
+  std::vector<SrvReq> req;          // by Member::idx
+  std::vector<char*> ws;            // workspace of each request (null once returned)
+  std::vector<size_t> ws_bytes;
+  char* meta = nullptr;
+  size_t meta_bytes = 0;
+  double t_start = 0.0;
+  int members = 0;
+};
+
+// Posts the records of the members that left `lc` since the last call and returns their
+// workspaces to the arena.  Caller holds S->mu.
+void post_left(Server* S, LaneCohort& lc, size_t& seen) {
+  const double t = S->now();
+  for (; seen < lc.c.left.size(); ++seen) {
+    const Cohort::Left& l = lc.c.left[seen];
+    const SrvReq& r = lc.req[l.idx];
+    je_done d{};
+    d.tag = r.tag;
+    d.status = l.status;
+    d.n = r.n;
+    d.batch = lc.members;
+    d.rotations = l.st.rotations;
+    d.t_submit = r.t_submit;
+    d.t_start = lc.t_start;
+    d.t_done = t;
+    S->done.push_back(d);
+    if (lc.ws[l.idx]) {
+      S->arena.put(lc.ws[l.idx], lc.ws_bytes[l.idx]);
+      lc.ws[l.idx] = nullptr;
+      ++S->mem_gen;
+    }
+    --S->in_flight;
+  }
+}
+
+void server_lane(Server* S) {
   (void)hipSetDevice(S->device);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->error = JE_ERR_DEVICE;
+    S->cv_done.notify_all();
     return;
   }
-  WorkerBuf buf;
-  int err = JE_OK;
-  (void)worker_ws(S->budget, &err, &buf);
+  std::vector<std::unique_ptr<LaneCohort>> cohorts;
+  std::vector<size_t> seen;
+  long long gen_seen = -1;  // arena generation of this lane's last failed admission
   for (;;) {
-    std::vector<SrvReq> take;
+    // ---- admission at the step boundary
+    std::unique_ptr<LaneCohort> nc;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
-      if (S->queue.empty()) break;  // stop requested and nothing left
-      // the oldest request opens the batch; queued requests of its size class join in
-      // arrival order while the batch fits the buffer (a batch lasts as long as its largest
-      // member, so small problems do not wait behind large ones)
-      std::vector<int> sizes;
-      const int cls = size_class(S->queue.front().n);
-      for (auto it = S->queue.begin(); it != S->queue.end();) {
-        if (size_class(it->n) != cls) { ++it; continue; }
-        sizes.push_back(it->n);
-        if (!take.empty() && batch_bytes(sizes, S->precond) > S->budget) break;
-        take.push_back(*it);
-        it = S->queue.erase(it);
+      // an idle lane sleeps until there is a request it has not yet failed to place
+      if (cohorts.empty())
+        S->cv_work.wait(lk, [&] {
+          return S->stop || (!S->queue.empty() && S->mem_gen != gen_seen);
+        });
+      if (cohorts.empty() && S->queue.empty() && S->stop) break;
+      if (cohorts.empty() && S->mem_gen == gen_seen) continue;  // stop requested, memory held
+      if (!S->queue.empty()) {
+        const int cls = size_class(S->queue.front().n);
+        std::vector<SrvReq> take;
+        std::vector<char*> ws;
+        std::vector<size_t> wb;
+        for (auto it = S->queue.begin(); it != S->queue.end();) {
+          if (size_class(it->n) != cls) { ++it; continue; }
+          const size_t b = bws_bytes(it->n, S->precond, kBatchLogCap);
+          char* p = S->arena.get(b);
+          if (!p) break;  // admission by footprint: the rest waits for memory
+          take.push_back(*it);
+          ws.push_back(p);
+          wb.push_back(b);
+          it = S->queue.erase(it);
+        }
+        char* meta = nullptr;
+        const size_t mb = take.empty() ? 0 : cohort_meta_bytes((int)take.size());
+        if (!take.empty()) meta = S->arena.get(mb);
+        if (!take.empty() && !meta) {
+          // no room for the tables: give the requests back, in order
+          for (size_t i = 0; i < take.size(); ++i) S->arena.put(ws[i], wb[i]);
+          for (size_t i = take.size(); i-- > 0;) S->queue.push_front(take[i]);
+          take.clear();
+        }
+        if (take.empty()) gen_seen = S->mem_gen;
+        if (!take.empty()) {
+          nc.reset(new LaneCohort());
+          nc->req = take;
+          nc->ws = ws;
+          nc->ws_bytes = wb;
+          nc->meta = meta;
+          nc->meta_bytes = mb;
+          nc->members = (int)take.size();
+          S->in_flight += (long long)take.size();
+        }
       }
-      S->in_flight += (long long)take.size();
     }
-    const int cnt = (int)take.size();
-    std::vector<const double*> A(cnt);
-    std::vector<double*> W(cnt), V(cnt);
-    std::vector<int> n(cnt), lda(cnt), ldv(cnt), info(cnt, JE_ERR_DEVICE), mem(cnt);
-    std::vector<je_stats> stats(cnt);
-    bool anyv = false;
-    for (int i = 0; i < cnt; ++i) {
-      A[i] = take[i].A; W[i] = take[i].W; V[i] = take[i].V; n[i] = take[i].n;
-      lda[i] = take[i].lda; ldv[i] = take[i].ldv; mem[i] = i;
-      anyv = anyv || V[i] != nullptr;
+    if (nc) {
+      std::vector<Member> mem(nc->req.size());
+      for (size_t i = 0; i < nc->req.size(); ++i) {
+        const SrvReq& r = nc->req[i];
+        mem[i] = Member{r.A, r.n, r.lda, r.W, r.V, r.ldv, nc->ws[i], (int)i};
+      }
+      nc->t_start = S->now();
+      int r = nc->c.begin(mem, nc->meta, S->tol, S->pivot, S->precond, S->o, st, kServeStepRot);
+      if (r != JE_OK) {
+        // the whole cohort failed: every member gets the error
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (size_t i = 0; i < nc->req.size(); ++i)
+          nc->c.left.push_back(Cohort::Left{(int)i, r, je_stats{}});
+        nc->c.phase = Cohort::DONE;
+      }
+      cohorts.push_back(std::move(nc));
+      seen.push_back(0);
     }
-    const double t_start = S->now();
-    const int rr = solve_batched(mem, A.data(), n.data(), lda.data(), W.data(),
-                                 anyv ? V.data() : nullptr, ldv.data(), S->tol, S->pivot,
-                                 S->precond, S->o, info.data(), stats.data(), st, worker_ws,
-                                 &buf);
-    // a failure of the whole batch (allocation, device) is every member's status
-    if (rr >= JE_ERR_NOMEM)
-      for (int i = 0; i < cnt; ++i)
-        if (info[i] == JE_ERR_DEVICE) info[i] = rr;
-    (void)hipStreamSynchronize(st);
-    const double t_end = S->now();
+    // ---- one step of every cohort of this lane
+    for (size_t k = 0; k < cohorts.size(); ++k) {
+      LaneCohort& lc = *cohorts[k];
+      if (lc.c.phase != Cohort::DONE) {
+        const int r = lc.c.step();
+        if (r != JE_OK) {
+          // a device error ends the cohort: its remaining members get the status
+          for (int i = 0; i < lc.c.cnt; ++i) lc.c.leave(i, r, nullptr);
+          lc.c.cnt = 0;
+          lc.c.phase = Cohort::DONE;
+        }
+      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      post_left(S, lc, seen[k]);
+    }
+    // ---- finished cohorts return their tables
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      for (int i = 0; i < cnt; ++i) {
-        je_done d{};
-        d.tag = take[i].tag;
-        d.status = info[i];
-        d.n = take[i].n;
-        d.batch = cnt;
-        d.rotations = stats[i].rotations;
-        d.t_submit = take[i].t_submit;
-        d.t_start = t_start;
-        d.t_done = t_end;
-        S->done.push_back(d);
+      for (size_t k = 0; k < cohorts.size();) {
+        if (cohorts[k]->c.phase == Cohort::DONE) {
+          S->arena.put(cohorts[k]->meta, cohorts[k]->meta_bytes);
+          ++S->mem_gen;
+          cohorts.erase(cohorts.begin() + k);
+          seen.erase(seen.begin() + k);
+        } else {
+          ++k;
+        }
       }
-      S->in_flight -= cnt;
     }
     S->cv_done.notify_all();
+    S->cv_work.notify_all();  // memory may have been freed for queued requests
   }
-  if (buf.ptr) (void)hipFree(buf.ptr);
+  (void)hipStreamSynchronize(st);
   (void)hipStreamDestroy(st);
 }
 
@@ -1383,12 +1663,20 @@ je_server* jacobi_server_create(int workers, size_t hbm_budget, double tol, int 
   if (!(tol > 0.0) && !(o.abs_thr > 0.0)) return nullptr;
   if (pivot != JE_PIVOT_GREEDY && pivot != JE_PIVOT_GAP) return nullptr;
   if (precond != JE_PRECOND_NONE && precond != JE_PRECOND_FP32) return nullptr;
+  if (check_args((const double*)1, 2, 2, (const double*)1, nullptr, 2, tol, pivot, precond, o))
+    return nullptr;
   Server* S = new Server();
   if (hipGetDevice(&S->device) != hipSuccess) { delete S; return nullptr; }
   S->tol = tol; S->pivot = pivot; S->precond = precond; S->o = o;
   S->budget = std::max<size_t>(hbm_budget, (size_t)1 << 20);
+  if (hipMalloc(&S->buffer, S->budget) != hipSuccess) {
+    (void)hipGetLastError();
+    delete S;
+    return nullptr;
+  }
+  S->arena.init((char*)S->buffer, S->budget);
   S->t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < workers; ++i) S->workers.emplace_back(server_worker, S);
+  for (int i = 0; i < workers; ++i) S->lanes.emplace_back(server_lane, S);
   return reinterpret_cast<je_server*>(S);
 }
 
@@ -1399,6 +1687,11 @@ int jacobi_server_submit(je_server* srv, const double* A, int n, int lda, double
   int a = check_args(A, n, lda, W, V, ldv, S->tol, S->pivot, S->precond, S->o);
   if (a) return a - 1;  // argument k of the single call is argument k + 1 here
   if (n > JE_MAX_N) return JE_ERR_TOO_LARGE;
+  // a request that could never be admitted: its workspace and a one-member cohort's tables
+  // exceed the whole budget
+  if (n >= 2 && al(bws_bytes(n, S->precond, kBatchLogCap)) + al(cohort_meta_bytes(1)) >
+                    S->arena.bytes)
+    return JE_ERR_NOMEM;
   if (n < 2) {
     // trivial problems complete at once, through the single-problem call
     int r = jacobi_eigh_ex(A, n, lda, W, V, ldv, S->tol, S->pivot, S->precond, &S->o, nullptr,
@@ -1456,7 +1749,8 @@ void jacobi_server_destroy(je_server* srv) {
     S->stop = true;
   }
   S->cv_work.notify_all();
-  for (auto& t : S->workers) t.join();
+  for (auto& t : S->lanes) t.join();
+  if (S->buffer) (void)hipFree(S->buffer);
   delete S;
 }
 

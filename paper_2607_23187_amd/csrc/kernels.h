@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace je {
 
 enum { STOP_CERT = 0, STOP_OFF = 1, STOP_SCORE = 2 };
@@ -209,6 +211,31 @@ int precond_f32_block_b();  // block rows PB of the batched FP32 stage
 hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int* dwork,
                              size_t off, size_t qoff, int max_sweeps, double tol, double rho,
                              hipStream_t s);
+
+// The same stage in bounded pieces: begin() starts it, every advance(k) performs up to k
+// steps (a step = the next round of every matrix not yet done); `finished` is set, and the
+// FP64 eigenvector matrices gathered, once every matrix is done.  nvec must stay valid.
+struct F32Batch {
+  BMat* m = nullptr;
+  const int* nvec = nullptr;
+  int count = 0, nmax = 0;
+  int* dwork = nullptr;
+  size_t qoff = 0;
+  int max_sweeps = 0;
+  double tol = 0.0, rho = 0.0;
+  hipStream_t s = nullptr;
+  long long step = 0, max_steps = 0;
+  bool finished = false;
+  std::vector<int> done, act, ps, pa, pv;
+  int tps = 0, tpa = 0, tpv = 0, na = 0, max_rounds = 1;
+  hipError_t begin(BMat* m, const int* nvec, int count, int nmax, int* dwork, size_t off,
+                   size_t qoff, int max_sweeps, double tol, double rho, hipStream_t s);
+  hipError_t advance(int steps);
+
+ private:
+  hipError_t rebuild();
+  hipError_t poll();
+};
 
 // ------------------------------------------------------------------ one-sided SVD
 constexpr int kSvdMaxN = 8192;

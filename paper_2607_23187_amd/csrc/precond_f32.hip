@@ -1251,72 +1251,95 @@ size_t precond_f32_bytes_b(int n) {
   return (b + 255) & ~(size_t)255;
 }
 
-hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int* dwork,
-                             size_t off, size_t qoff, int max_sweeps, double tol, double rho,
-                             hipStream_t s) {
-  constexpr int NT = Blk<BPB>::NT, PM = Blk<BPB>::PM;
-  hipLaunchKernelGGL(k_f32_start_b, dim3(count), dim3(256), 0, s, m, off, tol);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // device work area: done flags, active list, three prefix arrays
-  int* d_done = dwork;
+hipError_t F32Batch::rebuild() {
+  constexpr int PM = Blk<BPB>::PM;
   int* d_act = dwork + count;
   int* d_ps = dwork + 2 * count;
   int* d_pa = dwork + 3 * count;
   int* d_pv = dwork + 4 * count;
-  std::vector<int> done(count, 0), act, ps, pa, pv;
-  int tps = 0, tpa = 0, tpv = 0, na = 0, max_rounds = 1;
-  // launch lists of the matrices not yet done (rebuilt at every poll)
-  auto rebuild = [&]() -> hipError_t {
-    act.clear(); ps.clear(); pa.clear(); pv.clear();
-    tps = tpa = tpv = 0;
-    max_rounds = 1;
-    for (int i = 0; i < count; ++i) {
-      if (done[i]) continue;
-      const int np = (nvec[i] + PM - 1) / PM * PM, nb = np / BPB, nb2 = nb / 2;
-      const int nvt = (nvec[i] + PM - 1) / PM;
-      act.push_back(i); ps.push_back(tps); pa.push_back(tpa); pv.push_back(tpv);
-      tps += nb2; tpa += nb2 * (nb2 - 1) / 2; tpv += nvt * nb2;
-      max_rounds = std::max(max_rounds, nb - 1);
-    }
-    na = (int)act.size();
-    if (na == 0) return hipSuccess;
-    hipError_t r;
-    if ((r = hipMemcpyAsync(d_act, act.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
-    if ((r = hipMemcpyAsync(d_ps, ps.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
-    if ((r = hipMemcpyAsync(d_pa, pa.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
-    if ((r = hipMemcpyAsync(d_pv, pv.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
-    return hipStreamSynchronize(s);  // the host vectors are reused by the next rebuild
-  };
-  auto poll = [&]() -> hipError_t {
-    hipLaunchKernelGGL(k_f32_done_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count, d_done);
-    hipError_t r = hipMemcpyAsync(done.data(), d_done, count * 4, hipMemcpyDeviceToHost, s);
-    if (r == hipSuccess) r = hipStreamSynchronize(s);
-    return r;
-  };
+  act.clear(); ps.clear(); pa.clear(); pv.clear();
+  tps = tpa = tpv = 0;
+  max_rounds = 1;
+  for (int i = 0; i < count; ++i) {
+    if (done[i]) continue;
+    const int np = (nvec[i] + PM - 1) / PM * PM, nb = np / BPB, nb2 = nb / 2;
+    const int nvt = (nvec[i] + PM - 1) / PM;
+    act.push_back(i); ps.push_back(tps); pa.push_back(tpa); pv.push_back(tpv);
+    tps += nb2; tpa += nb2 * (nb2 - 1) / 2; tpv += nvt * nb2;
+    max_rounds = std::max(max_rounds, nb - 1);
+  }
+  na = (int)act.size();
+  if (na == 0) return hipSuccess;
+  hipError_t r;
+  if ((r = hipMemcpyAsync(d_act, act.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+  if ((r = hipMemcpyAsync(d_ps, ps.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+  if ((r = hipMemcpyAsync(d_pa, pa.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+  if ((r = hipMemcpyAsync(d_pv, pv.data(), na * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+  return hipStreamSynchronize(s);  // the host vectors are reused by the next rebuild
+}
+
+hipError_t F32Batch::poll() {
+  hipLaunchKernelGGL(k_f32_done_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count, dwork);
+  hipError_t r = hipMemcpyAsync(done.data(), dwork, count * 4, hipMemcpyDeviceToHost, s);
+  if (r == hipSuccess) r = hipStreamSynchronize(s);
+  return r;
+}
+
+hipError_t F32Batch::begin(BMat* m_, const int* nvec_, int count_, int nmax_, int* dwork_,
+                           size_t off, size_t qoff_, int max_sweeps_, double tol_, double rho_,
+                           hipStream_t s_) {
+  m = m_; nvec = nvec_; count = count_; nmax = nmax_; dwork = dwork_; qoff = qoff_;
+  max_sweeps = max_sweeps_; tol = tol_; rho = rho_; s = s_;
+  step = 0;
+  finished = false;
+  done.assign(count, 0);
+  hipLaunchKernelGGL(k_f32_start_b, dim3(count), dim3(256), 0, s, m, off, tol);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if ((e = poll()) != hipSuccess) return e;
   if ((e = rebuild()) != hipSuccess) return e;
   // every matrix ends within max_sweeps sweeps of at most max_rounds rounds
-  const long long max_steps = (long long)max_sweeps * max_rounds;
+  max_steps = (long long)max_sweeps * max_rounds;
+  return hipSuccess;
+}
+
+hipError_t F32Batch::advance(int steps) {
+  constexpr int NT = Blk<BPB>::NT;
   const int poll_every = 8;
-  for (long long step = 0; step < max_steps && na > 0; ++step) {
-    hipLaunchKernelGGL(k_round_solve_b, dim3(tps), dim3(NT), 0, s, m, d_act, d_ps, na,
-                       max_sweeps, (float)(tol * tol), (float)(rho * rho));
+  hipError_t e;
+  for (int k = 0; k < steps && step < max_steps && na > 0; ++k, ++step) {
+    hipLaunchKernelGGL(k_round_solve_b, dim3(tps), dim3(NT), 0, s, m, dwork + count,
+                       dwork + 2 * count, na, max_sweeps, (float)(tol * tol), (float)(rho * rho));
     if (tpa > 0)
-      hipLaunchKernelGGL(k_round_apply_a_b, dim3(tpa), dim3(NT), 0, s, m, d_act, d_pa, na);
-    hipLaunchKernelGGL(k_round_apply_v_b, dim3(tpv), dim3(NT), 0, s, m, d_act, d_pv, na);
-    hipLaunchKernelGGL(k_f32_control_b, dim3((na + 63) / 64), dim3(64), 0, s, m, d_act, na,
-                       max_sweeps, tol, rho);
+      hipLaunchKernelGGL(k_round_apply_a_b, dim3(tpa), dim3(NT), 0, s, m, dwork + count,
+                         dwork + 3 * count, na);
+    hipLaunchKernelGGL(k_round_apply_v_b, dim3(tpv), dim3(NT), 0, s, m, dwork + count,
+                       dwork + 4 * count, na);
+    hipLaunchKernelGGL(k_f32_control_b, dim3((na + 63) / 64), dim3(64), 0, s, m, dwork + count,
+                       na, max_sweeps, tol, rho);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((step + 1) % poll_every == 0) {
       if ((e = poll()) != hipSuccess) return e;
       if ((e = rebuild()) != hipSuccess) return e;
     }
   }
-  size_t tot = (size_t)nmax * nmax;
-  hipLaunchKernelGGL(k_f32_gather_b, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0, s,
-                     m, qoff);
-  return hipGetLastError();
+  if (step >= max_steps || na == 0) {
+    size_t tot = (size_t)nmax * nmax;
+    hipLaunchKernelGGL(k_f32_gather_b, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0,
+                       s, m, qoff);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    finished = true;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int* dwork,
+                             size_t off, size_t qoff, int max_sweeps, double tol, double rho,
+                             hipStream_t s) {
+  F32Batch f;
+  hipError_t e = f.begin(m, nvec, count, nmax, dwork, off, qoff, max_sweeps, tol, rho, s);
+  while (e == hipSuccess && !f.finished) e = f.advance(1 << 30);
+  return e;
 }
 
 hipError_t run_precond_f32(const double* Asym, int n, int ld, double* Q, int ldq, void* scratch,

@@ -346,13 +346,14 @@ def eigh_batched_device(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap
 class Server:
     """Request server of the library (jacobi_server_*): submit(A, tag) queues a problem,
     poll() returns completion records.  Keeps each request's tensors alive until its record
-    has been polled; the solve itself runs in the library's worker threads."""
+    has been polled; the solve itself runs in the library's lane threads (continuous
+    batching within an HBM budget)."""
 
     def __init__(self, workers: int = 2, hbm_budget: int = 1 << 30, tol: float = 1e-14,
-                 pivot="gap", precond="fp32", stop="cert", want_v: bool = True):
+                 pivot="gap", precond="fp32", stop="cert", want_v: bool = True,
+                 polish_v: bool = True):
         L = load()
-        o = default_opts()
-        o.stop = _STOPS[stop]
+        o = _opts(stop, polish_v)
         self._want_v = want_v
         self._h = L.jacobi_server_create(int(workers), int(hbm_budget), float(tol),
                                          _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o))
