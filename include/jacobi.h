@@ -261,38 +261,46 @@ const char* jacobi_strerror(int status);
 void jacobi_release(void);
 
 /* ---------------------------------------------------------------- serving
- * A request server for streams of independent problems of different sizes (the served
- * workload of the batched method; each problem is solved exactly as by jacobi_eigh_ex with
- * the server's tol, pivot, precond and opts, and gives the same bits as a solve of its own).
- * `workers` host threads (1..16), each with its own HIP stream on the device current at
- * creation and its own device buffer of `hbm_budget` bytes, take queued requests: a free
- * worker opens a batch with the oldest request and adds, in arrival order, the queued
- * requests of the same size class (n <= 128, <= 512, <= 1024, larger) while their
- * workspaces fit its buffer (always at least one; a larger request grows the buffer), and
- * solves them as one batch.  Batches of different workers run concurrently on the device.
+ * A request server for streams of independent problems of different sizes, with continuous
+ * batching.  Each problem is solved by the batched method (jacobi_eigh_batched) with the
+ * server's tol, pivot, precond and opts, and gives the same bits as in a batch of its own.
+ * One device buffer of `hbm_budget` bytes, allocated at creation, holds the workspaces of
+ * all requests in flight.  `workers` lanes (host threads, 1..16, each with its own HIP
+ * stream on the device current at creation) run cohorts in bounded steps (a few FP32
+ * rounds, one Newton-Schulz step, a few thousand FP64 rotations per member, ...).  At
+ * every step boundary a lane admits queued requests of the size classes it serves
+ * (n <= 128, <= 512, <= 1024, larger: with 4 or more lanes lane l serves class l mod 4,
+ * with fewer, class c goes to lane c mod workers), in arrival order and as far as their
+ * workspaces fit in the buffer, as a new cohort beside the (at most one) other it is
+ * running; a request that does not fit, or whose lane runs two cohorts, waits and joins the
+ * lane's next cohort.  A problem whose solve has ended
+ * leaves its cohort at once: its completion record is posted and its memory returned.
+ * Cohorts of different lanes run concurrently on the device.
  *
  * Ownership: A, W and V of a request are the caller's device memory and must stay valid
  * (A unmodified) until the request's completion record has been polled.  The server owns
- * its threads, streams and buffers; jacobi_server_destroy waits for queued requests. */
+ * its threads, streams and buffer; jacobi_server_destroy waits for queued requests. */
 typedef struct je_server je_server;
 
 typedef struct {
   long long tag;        /* the caller's tag from jacobi_server_submit                    */
   int status;           /* as jacobi_eigh_ex                                              */
   int n;
-  int batch;            /* requests solved in the same batch                             */
+  int batch;            /* requests admitted in the same cohort                          */
   int pad;
   long long rotations;
   double t_submit;      /* seconds on the server's clock (jacobi_server_clock)           */
-  double t_start;       /* the batch's start                                              */
-  double t_done;        /* the batch's end: results are in W, V                           */
+  double t_start;       /* admission of its cohort                                        */
+  double t_done;        /* the request left its cohort: results are in W, V               */
 } je_done;
 
 /* NULL on an invalid argument or device error. */
 je_server* jacobi_server_create(int workers, size_t hbm_budget, double tol, int pivot,
                                 int precond, const je_opts* opts);
 /* Queues one problem (arguments as jacobi_eigh_ex, numbered from 2).  Returns 0, a
- * negative argument index, JE_ERR_TOO_LARGE, or a device error seen by a worker. */
+ * negative argument index, JE_ERR_TOO_LARGE, JE_ERR_NOMEM when the problem's workspace
+ * exceeds the whole hbm_budget (it could never be admitted), or a device error seen by a
+ * lane. */
 int jacobi_server_submit(je_server* srv, const double* A, int n, int lda, double* W, double* V,
                          int ldv, long long tag);
 /* Moves up to `max` completion records to `out` (host array) and returns their number;

@@ -1152,14 +1152,19 @@ int solve_batched(std::vector<int> idx, const double* const* Ain, const int* n,
 // Continuous batching of a request stream.  One device buffer of hbm_budget bytes (the
 // arena) holds the workspaces of every request in flight; `lanes` host threads, each with
 // its own stream, run cohorts (Cohort above) in bounded steps.  At every step boundary a
-// lane admits queued requests: the oldest one and the queued requests of its size class
-// (n <= 128, <= 512, <= 1024, larger), in arrival order, as far as their workspaces fit in
-// the arena, form a new cohort that runs beside the lane's other cohorts.  A request whose
+// lane admits queued requests: the oldest one of the size classes it serves (n <= 128,
+// <= 512, <= 1024, larger; see lane_serves) and the queued requests of that class, in
+// arrival order, as far as their workspaces fit in the arena, form a new cohort that runs
+// beside the lane's other cohorts (at most kLaneCohorts at once).  A request whose
 // workspace does not fit stays queued until memory is freed.  Members whose solve has
 // ended leave their cohort at the end of that step: their completion record is posted and
 // their workspace returned to the arena.  Cohorts of different lanes run concurrently on
 // the device; the cohorts of one lane interleave step by step.
 constexpr long long kServeStepRot = 4096;  // FP64 rotations per member per step
+// Cohorts a lane runs at once: a request that arrives while its lane is at this limit
+// waits and joins the next cohort, so cohorts grow with the load (a cohort of k large
+// matrices costs about as long as one of a single large matrix).
+constexpr int kLaneCohorts = 2;
 
 struct SrvReq {
   const double* A;
@@ -1229,6 +1234,7 @@ struct Server {
   void* buffer = nullptr;
   Arena arena;
   long long mem_gen = 0;  // incremented whenever memory returns to the arena
+  int lanes_n = 1;
   std::vector<std::thread> lanes;
   std::chrono::steady_clock::time_point t0;
   double now() const {
@@ -1237,6 +1243,13 @@ struct Server {
 };
 
 int size_class(int n) { return n <= 128 ? 0 : (n <= 512 ? 1 : (n <= 1024 ? 2 : 3)); }
+
+// Lanes are affine to size classes, so that the long steps of large problems never delay
+// the steps of small ones: with L >= 4 lanes lane l serves class l mod 4, with fewer lanes
+// class c goes to lane c mod L.
+bool lane_serves(int lane, int lanes, int cls) {
+  return lanes >= 4 ? (lane % 4 == cls) : (cls % lanes == lane);
+}
 
 // A cohort of a lane and the arena blocks it holds.
 struct LaneCohort {
@@ -1276,7 +1289,7 @@ void post_left(Server* S, LaneCohort& lc, size_t& seen) {
   }
 }
 
-void server_lane(Server* S) {
+void server_lane(Server* S, int lane) {
   (void)hipSetDevice(S->device);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -1294,14 +1307,18 @@ void server_lane(Server* S) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       // an idle lane sleeps until there is a request it has not yet failed to place
+      const int lanes = (int)S->lanes_n;
+      auto mine = [&]() -> const SrvReq* {
+        for (const SrvReq& r : S->queue)
+          if (lane_serves(lane, lanes, size_class(r.n))) return &r;
+        return nullptr;
+      };
       if (cohorts.empty())
-        S->cv_work.wait(lk, [&] {
-          return S->stop || (!S->queue.empty() && S->mem_gen != gen_seen);
-        });
-      if (cohorts.empty() && S->queue.empty() && S->stop) break;
+        S->cv_work.wait(lk, [&] { return S->stop || (mine() && S->mem_gen != gen_seen); });
+      if (cohorts.empty() && !mine() && S->stop) break;
       if (cohorts.empty() && S->mem_gen == gen_seen) continue;  // stop requested, memory held
-      if (!S->queue.empty()) {
-        const int cls = size_class(S->queue.front().n);
+      if (const SrvReq* first = (cohorts.size() < (size_t)kLaneCohorts) ? mine() : nullptr) {
+        const int cls = size_class(first->n);
         std::vector<SrvReq> take;
         std::vector<char*> ws;
         std::vector<size_t> wb;
@@ -1676,7 +1693,8 @@ je_server* jacobi_server_create(int workers, size_t hbm_budget, double tol, int 
   }
   S->arena.init((char*)S->buffer, S->budget);
   S->t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < workers; ++i) S->lanes.emplace_back(server_lane, S);
+  S->lanes_n = workers;
+  for (int i = 0; i < workers; ++i) S->lanes.emplace_back(server_lane, S, i);
   return reinterpret_cast<je_server*>(S);
 }
 
@@ -1709,7 +1727,7 @@ int jacobi_server_submit(je_server* srv, const double* A, int n, int lda, double
     if (S->error) return S->error;
     S->queue.push_back(SrvReq{A, n, lda, W, V, ldv, tag, S->now()});
   }
-  S->cv_work.notify_one();
+  S->cv_work.notify_all();  // the lane serving this size class may be any of them
   return JE_OK;
 }
 

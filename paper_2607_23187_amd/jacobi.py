@@ -367,7 +367,10 @@ class Server:
         n = a.shape[0]
         w = torch.empty(n, dtype=torch.float64, device=a.device)
         v = torch.empty_like(a) if self._want_v else None
-        torch.cuda.synchronize()  # A is written by the caller's stream; workers use their own
+        # A is written by the caller's stream and read by the server's lanes on their own
+        # streams: wait for the caller's stream only (a device-wide synchronisation would
+        # also wait for the solves in flight)
+        torch.cuda.current_stream(a.device).synchronize()
         r = load().jacobi_server_submit(self._h, ctypes.c_void_p(a.data_ptr()), n, max(1, n),
                                         ctypes.c_void_p(w.data_ptr()),
                                         ctypes.c_void_p(v.data_ptr()) if v is not None else None,
