@@ -326,6 +326,41 @@ def test_fp32_preconditioner_quality():
     assert off.max() <= 64 * np.sqrt(n) * u32 * nrm2
 
 
+def test_fp32_skip_rule_matches_what_fp32_can_resolve():
+    """The FP32 stage leaves a pair to the FP64 phase when FP32 cannot determine its
+    rotation: the angle of the 2 x 2 block is 1/2 atan2(2 a_pq, a_pp - a_qq), and in FP32
+    the difference of two diagonal entries near 1 carries an error of up to one ulp of 1
+    (2^-23).  Pairs whose off-diagonal entry and diagonal difference are half the rule's
+    level (2^-22 (|a_pp| + |a_qq|)) have FP32 angles decided by that rounding (errors of a
+    sizeable fraction of a radian), and the oracle must skip them; pairs 64 times above it
+    have FP32 angles accurate to a few hundredths of a radian, and the oracle must rotate
+    them.  A threshold moved by a large factor either way fails one half."""
+    rng = np.random.Generator(np.random.PCG64(4242))
+
+    def angle(app, aqq, apq):
+        return 0.5 * np.arctan2(2.0 * apq, app - aqq)
+
+    for f, must_skip in ((0.5, True), (64.0, False)):
+        worst = 0.0
+        for _ in range(200):
+            lev = f * 2.0 ** -22 * 2.0
+            d = lev * rng.uniform(0.1, 0.9) * rng.choice([-1.0, 1.0])
+            apq = lev * rng.uniform(0.1, 0.9) * rng.choice([-1.0, 1.0])
+            app, aqq = 1.0 + 0.5 * d + rng.uniform(-1, 1) * 2.0 ** -40, 1.0 - 0.5 * d
+            a = np.array([[app, apq], [apq, aqq]])
+            a32 = a.astype(np.float32)
+            d32 = np.float32(a32[0, 0]) - np.float32(a32[1, 1])
+            th32 = 0.5 * np.arctan2(2.0 * float(a32[0, 1]), float(d32))
+            worst = max(worst, abs(th32 - angle(app, aqq, apq)))
+            _, v32, _ = O.jacobi_f32(a, max_sweeps=1, tol=0.0)
+            skipped = np.array_equal(v32, np.eye(2, dtype=np.float32))
+            assert skipped == must_skip, (f, d, apq)
+        if must_skip:
+            assert worst > 0.2      # FP32 cannot resolve these angles
+        else:
+            assert worst < 0.05     # it resolves these
+
+
 # ------------------------------------------------------------------ Sec. 4.1 behaviour
 def test_sec41_gap_beats_greedy_on_tight_cluster():
     """Sec. 4.1: with alpha = 1 the gap-aware pivots need far fewer rotations than greedy
