@@ -503,6 +503,43 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_phases(args):
+    """Per-rotation time of the FP64 Jacobi phase on one workgroup and on several, with the
+    phase timers of opts.profile, for the n = 1024 recipe at n = 512, 1024, 2048 and the
+    n = 4096 recipe (C3)."""
+    import numpy as np
+    import torch
+
+    from paper_2607_23187_amd import inputs as I
+    from paper_2607_23187_amd import jacobi as J
+
+    J.load()
+    out = {}
+    probs = [("c2_n512", I.config_c2(n=512)), ("c2_n1024", I.config_c2()),
+             ("c2_n2048", I.config_c2(n=2048)), ("c3_n4096", I.config_c3())]
+    names = {"one": ["wave reductions", "barrier", "cross-wave", "rescans", "parameters",
+                     "update"],
+             "many": ["local reductions", "publish + store acks", "barrier", "slot read + "
+                      "reduction", "parameters + row loads", "update"]}
+    for name, prob in probs:
+        n = prob.a.shape[0]
+        a = torch.from_numpy(prob.a).to("cuda:0")
+        tol = 10 * n * U * float(np.max(np.abs(prob.lam))) / float(np.linalg.norm(prob.a))
+        for wgs in ("one", "many"):
+            J.eigh(a, tol=tol, jacobi_wgs=wgs)
+            r = J.eigh(a, tol=tol, jacobi_wgs=wgs)
+            rp = J.eigh(a, tol=tol, jacobi_wgs=wgs, profile=True)
+            st = r.stats
+            key = f"{name} {wgs}"
+            out[key] = {"n": n, "workgroups": st["jacobi_wgs"], "rotations": st["rotations"],
+                        "kernel_ms": st["ms_jacobi_kernel"],
+                        "us_per_rotation": st["ms_jacobi_kernel"] * 1e3 / st["rotations"],
+                        "phase_ns_per_rotation": dict(zip(names[wgs], rp.stats["prof_ns"]))}
+            log(f"{key}: {out[key]['us_per_rotation']:.2f} us/rotation")
+    print(json.dumps({"workload": "FP64 Jacobi phase per rotation, one workgroup vs several",
+                      "runs": out}), flush=True)
+
+
 def bench_sec41(args):
     """Sec. 4.1 on the GPU: n = 1000, eigenvalues 1 + exp(-alpha k) (a cluster near 1 for
     alpha = 1) next to 2 + (k - 1)/(h - 1), k = 1..h, alpha in {1, 0.01}; gap-aware against
@@ -686,7 +723,7 @@ def main():
     ap.add_argument("--n-precision", type=int, default=4096)
     ap.add_argument("--n-sec41", type=int, default=1000)
     ap.add_argument("--workload", choices=("single", "batch", "serve", "precision", "svd",
-                                           "sec41", "cpu-full"),
+                                           "sec41", "cpu-full", "phases"),
                     default="single",
                     help="single: the n=1024 headline workload; batch: 2048 uneven matrices; "
                          "serve: a Poisson request stream through the library's server")
@@ -730,6 +767,9 @@ def main():
         return
     if args.workload == "cpu-full":
         bench_cpu_full(args)
+        return
+    if args.workload == "phases":
+        bench_phases(args)
         return
 
     import numpy as np
