@@ -126,7 +126,7 @@ typedef struct je_opts {
                              /* je_stats.prof_ns (slows the kernel slightly)     (0)  */
   int fp32_block;            /* rows per block of the FP32 stage: 0 by n, 16 or 32 (0) */
   int jacobi_wgs;            /* FP64 phase of one problem: 0 automatic (several       */
-                             /* workgroups from n = 1024), 1 one workgroup, 2 several*/
+                             /* workgroups from n = 768), 1 one workgroup, 2 several */
                              /* workgroups when the matrix lives in HBM; same results */
                              /* (0); batches always use one workgroup per matrix      */
 } je_opts;

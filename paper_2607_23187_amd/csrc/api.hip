@@ -82,9 +82,9 @@ constexpr double kF32Rho2 = 0.5;
 constexpr double kF32Tol2 = 0x1p-30;
 
 // Smallest n whose FP64 Jacobi phase runs on several workgroups by default (MI355X, per
-// rotation, one workgroup against several: n = 512 3.75 / 4.63 us, 1024 5.02 / 4.74,
-// 2048 7.23 / 5.29, 4096 11.47 / 6.04).
-constexpr int kMultiWgMinN = 1024;
+// rotation, one workgroup against several: n = 512 3.77 / 4.10 us, 1024 5.02 / 4.29,
+// 2048 7.23 / 4.77, 4096 11.52 / 5.37; the two cross near n = 670).
+constexpr int kMultiWgMinN = 768;
 
 // Range of the entries solved as given: outside it the input is scaled by a power of two
 // (exact) so that squares in FP64 and the FP32 copy of the preconditioner stay in range.

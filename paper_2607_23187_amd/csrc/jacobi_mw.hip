@@ -17,9 +17,9 @@
 //
 // Placement and memory ordering: workgroups are dispatched to the XCDs round-robin, so the
 // grid is 8 G and only workgroups with blockIdx % 8 == 0 work; they share XCD 0 and its
-// L2.  All accesses to A and to the exchange area are relaxed agent-scope atomics (they
-// bypass the per-CU cache and meet in L2), and a wave waits for its stores to be
-// acknowledged before it arrives at a barrier.  A start barrier checks every workgroup's
+// L2.  Loads of A and of the exchange area are relaxed agent-scope atomics (they miss the
+// per-CU cache and read L2), stores are workgroup-scope (acknowledged by that L2), and a
+// wave waits for its stores to be acknowledged before it arrives at a barrier.  A start barrier checks every workgroup's
 // XCC id: if they do not share one XCD (or a start wait runs out) the kernel returns
 // without touching the state and the host runs the one-workgroup kernel instead.  Every
 // wait is bounded; a wait that runs out sets an abort flag that ends all workgroups.
@@ -42,10 +42,14 @@ __device__ __forceinline__ double ld_ag(const double* p) {
   return __longlong_as_double((long long)v);
 }
 
+// Stores need only reach the L2 that every workgroup of the launch shares (they all run on
+// one XCD, checked at the start): workgroup-scope stores are acknowledged there, without
+// the write-through of device-scope ones (measured 0.81 against 1.08 us per exchange round
+// for 16 workgroups).  Readers use agent-scope loads, which miss their own CU's cache.
 __device__ __forceinline__ void st_ag(double* p, double v) {
   __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
                      (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+                     __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ int ld_ag_i(int* p) {
@@ -60,7 +64,9 @@ __device__ __forceinline__ void st_ag_i(int* p, int v) {
 // False when the wait ran out or another workgroup gave up (the abort flag is then set).
 __device__ __forceinline__ bool mw_sync(MwCtl* mc, int G, int round) {
   int ok = 1;
-  // this wave's stores (its slot and its part of A) have been acknowledged by L2
+  // this wave's stores (its slot and its part of A) have been acknowledged by L2; the
+  // compiler fences keep every memory access of the round on its side of the barrier
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(&mc->counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -74,6 +80,7 @@ __device__ __forceinline__ bool mw_sync(MwCtl* mc, int G, int round) {
       }
     }
   }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   return __builtin_amdgcn_readfirstlane(ok) != 0;
 }
 
