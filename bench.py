@@ -287,10 +287,10 @@ def run_batch(args):
         log(f"profile run: copy 268435456 B; batched solve status {st}")
         return None
 
-    def run_batched():
+    def run_batched(graph=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, res = J.eigh_batched(mats, tol=tol, pivot="gap", precond=args.precond)
+        st, res = J.eigh_batched(mats, tol=tol, pivot="gap", precond=args.precond, graph=graph)
         torch.cuda.synchronize()
         return st, res, time.perf_counter() - t0
 
@@ -341,6 +341,20 @@ def run_batch(args):
                                            if tk > 0 else 0.0},
                         "k_apply_log_b": {"ms": ta, "achieved_GBs": algo / 2 / (ta * 1e-3) / 1e9
                                           if ta > 0 else 0.0}}}
+    # the same solve with the repeated step sequences replayed from captured graphs
+    glat = []
+    for i in range(max(1, args.batch_warmup) + args.batch_steps):
+        gst, gres, dt = run_batched(graph=True)
+        if i >= max(1, args.batch_warmup):
+            glat.append(dt)
+        log(f"batched graph replay {i}: {dt * 1e3:.1f} ms, status {gst}")
+    same = all(torch.equal(a.w, b.w) and torch.equal(a.v, b.v) and
+               a.stats["rotations"] == b.stats["rotations"] for a, b in zip(res, gres))
+    gmed = float(np.median(glat))
+    out["graph_replay"] = {"seconds": gmed, "solves_per_s": len(probs) / gmed,
+                           "p50_ms": pct([x * 1e3 for x in glat], 50),
+                           "direct_over_graph": med / gmed, "same_bits_as_direct": bool(same)}
+    del gres
     if not args.no_compare:
         singles = 0
         torch.cuda.synchronize()

@@ -121,7 +121,11 @@ typedef struct je_opts {
                              /* results                                          (0)  */
   int tune;                  /* batched: time the workgroup shapes of each size class  */
                              /* once per process and keep the faster (same results)(1)*/
-  int graph;                 /* 1: FP32 sweeps replayed from captured HIP graphs   (0)  */
+  int graph;                 /* 1: replay from captured HIP graphs: the FP32 sweeps (0)  */
+                             /* of one problem; for batches and served requests the  */
+                             /* FP32 rounds between two polls, a Newton-Schulz step, */
+                             /* the persistent FP64 launches and the log drain (same */
+                             /* results as direct launches)                          */
   int profile;               /* 1: phase timers of the FP64 Jacobi kernel into        */
                              /* je_stats.prof_ns (slows the kernel slightly)     (0)  */
   int fp32_block;            /* rows per block of the FP32 stage: 0 by n, 16 or 32 (0) */

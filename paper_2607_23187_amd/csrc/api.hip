@@ -660,6 +660,28 @@ size_t batch_bytes(const std::vector<int>& sizes, int precond) {
   return tot + cohort_meta_bytes((int)sizes.size());
 }
 
+// The launches `body` makes on stream s, captured into an executable graph (no memset or
+// copy nodes: buffers are cleared by kernels).
+template <class F>
+hipError_t capture_graph(hipStream_t s, hipGraphExec_t* gx, F body) {
+  hipGraph_t g = nullptr;
+  *gx = nullptr;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t ec = body();
+  const hipError_t ee = hipStreamEndCapture(s, &g);
+  if (ec == hipSuccess) ec = ee;
+  if (ec == hipSuccess) ec = hipGraphInstantiate(gx, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (ec != hipSuccess) *gx = nullptr;
+  return ec;
+}
+
+inline void drop_graph(hipGraphExec_t& gx) {
+  if (gx) (void)hipGraphExecDestroy(gx);
+  gx = nullptr;
+}
+
 // One problem of a cohort: the caller's arrays, its workspace, and the caller's index.
 struct Member {
   const double* A;
@@ -715,6 +737,45 @@ struct Cohort {
   je_stats S{};
   float ms_kernel = 0.f, ms_apply = 0.f;
   std::vector<Left> left;
+  // graph replay (opts.graph): a Newton-Schulz step (one graph per buffer parity), the
+  // persistent FP64 launches and the log drain of a step, captured for the current
+  // membership (gen counts the changes of membership) and replayed until it changes
+  int gen = 0, graph_gen = -1;
+  hipGraphExec_t g_ns[2] = {nullptr, nullptr}, g_jq = nullptr, g_ja = nullptr;
+  // graphs are captured on a stream of their own (the caller's may be the null stream,
+  // which cannot be captured) and launched on the caller's
+  hipStream_t cap = nullptr;
+
+  Cohort() = default;
+  Cohort(const Cohort&) = delete;
+  Cohort& operator=(const Cohort&) = delete;
+  ~Cohort() {
+    drop_graphs();
+    f32.release();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  int capture_stream() {
+    if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    return JE_OK;
+  }
+  // the launches `body` makes (on the member stream s) captured into *gx
+  template <class F>
+  int capture(hipGraphExec_t* gx, F body) {
+    if (int r = capture_stream()) return r;
+    hipStream_t run = s;
+    s = cap;
+    const hipError_t e = capture_graph(cap, gx, body);
+    s = run;
+    HIPCHK(e);
+    return JE_OK;
+  }
+  void drop_graphs() {
+    drop_graph(g_ns[0]); drop_graph(g_ns[1]); drop_graph(g_jq); drop_graph(g_ja);
+  }
+  // graphs of an older membership are dropped
+  void graphs_current() {
+    if (graph_gen != gen) { drop_graphs(); graph_gen = gen; }
+  }
 
   int collect() {
     HIPCHK(launch_collect_b(dm, cnt, d_info, s));
@@ -756,6 +817,7 @@ struct Cohort {
     mem.swap(m2); hm.swap(h2); hi.swap(i2);
     if (!nrm.empty()) nrm.swap(n2);
     cnt = (int)mem.size();
+    ++gen;
     refresh_sizes();
     if (cnt == 0) { phase = DONE; return JE_OK; }
     return upload();
@@ -857,8 +919,10 @@ struct Cohort {
     // bytes, make HBM writes the larger cost
     mirror = o.update_mode == 1;
     if (precond) {
+      if (o.graph)
+        if (int r = capture_stream()) return r;
       HIPCHK(f32.begin(dm, nv.data(), cnt, nmax, d_work, BF(Asym), offX, o.fp32_max_sweeps,
-                       f32_tol1(o.fp32_passes), kF32Rho1, s));
+                       f32_tol1(o.fp32_passes), kF32Rho1, s, o.graph != 0, cap));
       phase = F32A;
     } else {
       HIPCHK(launch_set_identity_b(dm, cnt, nmax, BF(Vw), s));
@@ -869,15 +933,30 @@ struct Cohort {
   }
 
   // One Newton-Schulz step on every member not yet converged; *converged when all are.
+  hipError_t ns_launches() {
+    hipError_t e;
+    if ((e = launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s, 1))) return e;
+    if ((e = launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s, 1))) return e;
+    if ((e = launch_fro2_b(dm, cnt, nmax, BF(R), 1, s))) return e;
+    if ((e = launch_dgemm_b(dm, cnt, nmax, 0, 0.5, offX, BF(R), 1.0, offX, offXb, s))) return e;
+    if ((e = launch_ns_flag_b(dm, cnt, s))) return e;
+    return launch_collect_b(dm, cnt, d_info, s);
+  }
   int ns_step(bool* converged) {
     if (ns_iter == 0) HIPCHK(launch_ns_reset_b(dm, cnt, s));
-    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s, 1));
-    HIPCHK(launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s, 1));
-    HIPCHK(launch_fro2_b(dm, cnt, nmax, BF(R), 1, s));
-    HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 0.5, offX, BF(R), 1.0, offX, offXb, s));
+    if (o.graph) {
+      graphs_current();
+      hipGraphExec_t& g = g_ns[offX == BF(X) ? 0 : 1];
+      if (!g)
+        if (int r = capture(&g, [&] { return ns_launches(); })) return r;
+      HIPCHK(hipGraphLaunch(g, s));
+    } else {
+      HIPCHK(ns_launches());
+    }
     std::swap(offX, offXb);
-    HIPCHK(launch_ns_flag_b(dm, cnt, s));
-    if (int r = collect()) return r;
+    HIPCHK(hipMemcpyAsync(hi.data(), d_info, (size_t)cnt * sizeof(BInfo), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
     bool all = true;
     for (int i = 0; i < cnt; ++i) all = all && ns_converged(hi[i].rnorm, hm[i].n);
     ++ns_iter;
@@ -1036,7 +1115,7 @@ struct Cohort {
         HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
         HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
         HIPCHK(f32.begin(dm, nv.data(), cnt, nmax, d_work, BF(A), BF(T), o.fp32_max_sweeps,
-                         kF32Tol2, kF32Rho2, s));
+                         kF32Tol2, kF32Rho2, s, o.graph != 0, cap));
         phase = F32B;
         S.ms_precond += tp.stop();
         return JE_OK;
@@ -1062,36 +1141,73 @@ struct Cohort {
       }
       case JACOBI: {
         Timer tj(s);
-        std::vector<int> ord(cnt);
-        for (int i = 0; i < cnt; ++i) ord[i] = i;
-        // largest first: the order of the FP64 work queue
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hm[a].n > hm[b].n; });
-        std::vector<int> il, ih;
-        int nl = 0, nh = 0;
-        for (int i : ord) {
-          if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
-          else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
+        if (o.graph) graphs_current();
+        if (!o.graph || !g_jq) {
+          std::vector<int> ord(cnt);
+          for (int i = 0; i < cnt; ++i) ord[i] = i;
+          // largest first: the order of the FP64 work queue
+          std::stable_sort(ord.begin(), ord.end(),
+                           [&](int a, int b) { return hm[a].n > hm[b].n; });
+          std::vector<int> il, ih;
+          int nl = 0, nh = 0;
+          for (int i : ord) {
+            if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
+            else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
+          }
+          if (!il.empty())
+            HIPCHK(hipMemcpyAsync(d_idx_lds, il.data(), il.size() * 4, hipMemcpyHostToDevice, s));
+          if (!ih.empty())
+            HIPCHK(hipMemcpyAsync(d_idx_hbm, ih.data(), ih.size() * 4, hipMemcpyHostToDevice, s));
+          HIPCHK(hipStreamSynchronize(s));  // the index vectors are host memory
+          const int gl = (int)std::min<size_t>(il.size(), 2048);
+          const int gh = (int)std::min<size_t>(ih.size(), 1024);
+          auto queue = [&]() -> hipError_t {
+            hipError_t e = launch_zero_words(d_cnt, 2, s);
+            if (e == hipSuccess && !il.empty())
+              e = launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, mirror,
+                                      shape_lds, d_cnt, gl, s);
+            if (e == hipSuccess && !ih.empty())
+              e = launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, mirror,
+                                      shape_hbm, d_cnt + 1, gh, s);
+            return e;
+          };
+          if (!o.graph) {
+            Timer tk(s);
+            HIPCHK(queue());
+            ms_kernel += tk.stop();
+          } else {
+            // kernel attributes (the LDS size) are set outside the capture: grid 0 only
+            // prepares the launch
+            if (!il.empty())
+              HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, mirror,
+                                         shape_lds, d_cnt, 0, s));
+            if (!ih.empty())
+              HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false,
+                                         mirror, shape_hbm, d_cnt + 1, 0, s));
+            if (int r = capture(&g_jq, queue)) return r;
+            if (int r = capture(&g_ja, [&]() -> hipError_t {
+                  hipError_t e = launch_apply_log_b(dm, cnt, nmax, s);
+                  return e == hipSuccess ? launch_collect_b(dm, cnt, d_info, s) : e;
+                }))
+              return r;
+          }
         }
-        if (!il.empty())
-          HIPCHK(hipMemcpyAsync(d_idx_lds, il.data(), il.size() * 4, hipMemcpyHostToDevice, s));
-        if (!ih.empty())
-          HIPCHK(hipMemcpyAsync(d_idx_hbm, ih.data(), ih.size() * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_zero_words(d_cnt, 2, s));
-        HIPCHK(hipStreamSynchronize(s));  // the index vectors are host memory
-        Timer tk(s);
-        if (!il.empty())
-          HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)il.size(), nl, pivot, true, mirror,
-                                     shape_lds, d_cnt, (int)std::min<size_t>(il.size(), 2048),
-                                     s));
-        if (!ih.empty())
-          HIPCHK(launch_jacobi_queue(dm, d_idx_hbm, (int)ih.size(), nh, pivot, false, mirror,
-                                     shape_hbm, d_cnt + 1,
-                                     (int)std::min<size_t>(ih.size(), 1024), s));
-        ms_kernel += tk.stop();
-        Timer ta(s);
-        HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
-        ms_apply += ta.stop();
-        if (int r = collect()) return r;
+        if (o.graph) {
+          Timer tk(s);
+          HIPCHK(hipGraphLaunch(g_jq, s));
+          ms_kernel += tk.stop();
+          Timer ta(s);
+          HIPCHK(hipGraphLaunch(g_ja, s));
+          ms_apply += ta.stop();
+          HIPCHK(hipMemcpyAsync(hi.data(), d_info, (size_t)cnt * sizeof(BInfo),
+                                hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+        } else {
+          Timer ta(s);
+          HIPCHK(launch_apply_log_b(dm, cnt, nmax, s));
+          ms_apply += ta.stop();
+          if (int r = collect()) return r;
+        }
         S.ms_jacobi += tj.stop();
         std::vector<char> fin(cnt, 0);
         bool any = false;

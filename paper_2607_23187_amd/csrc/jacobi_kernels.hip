@@ -973,11 +973,15 @@ static hipError_t launch_queue_one(BMat* m, const int* idx, int count, int nmax,
   size_t sh = lds_bytes(nmax, LDSA);
   auto fn = (LDSA || mirror) ? k_jacobi_queue<NT, RM, GAP, LDSA, true>
                              : k_jacobi_queue<NT, RM, GAP, LDSA, false>;
-  if (sh > 65536) {
+  // under graph capture the attribute was set by a preparing call (grid 0) beforehand
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return hipGetLastError();
+  if (sh > 65536 && cs == hipStreamCaptureStatusNone) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
   }
+  if (grid <= 0) return hipSuccess;  // attributes only (before a graph capture)
   hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), sh, s, m, idx, count, counter);
   return hipGetLastError();
 }

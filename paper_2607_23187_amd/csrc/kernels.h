@@ -180,7 +180,8 @@ hipError_t launch_copy_mat_b(BMat* m, int count, int nmax, size_t dst, size_t sr
 hipError_t launch_init_rows_b(BMat* m, int count, int nmax, int pivot, int use_cert,
                               hipStream_t s);
 // Persistent Jacobi over the matrices idx[0..count) (one workgroup per matrix at a time,
-// taken from a device counter in the given order); lds_mode as for launch_jacobi.
+// taken from a device counter in the given order); lds_mode as for launch_jacobi.  With
+// grid <= 0 only the kernel's attributes are set (before a graph capture).
 hipError_t launch_jacobi_queue(BMat* m, const int* idx, int count, int nmax, int pivot,
                                bool lds_mode, bool mirror, int threads, int* counter, int grid,
                                hipStream_t s);
@@ -228,13 +229,29 @@ struct F32Batch {
   bool finished = false;
   std::vector<int> done, act, ps, pa, pv;
   int tps = 0, tpa = 0, tpv = 0, na = 0, max_rounds = 1;
+  // graph replay: the steps between two polls of the done flags are one graph, captured
+  // at the first advance and replayed; the launch lists are kept (matrices that are done
+  // leave every launch at once) until a quarter of the listed matrices are done, then
+  // rebuilt and the graph captured again
+  // (captured on stream cap, which the caller owns, and launched on s)
+  bool graph = false;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gx = nullptr;
+  int live = 0;  // matrices not yet done (graph replay)
   hipError_t begin(BMat* m, const int* nvec, int count, int nmax, int* dwork, size_t off,
-                   size_t qoff, int max_sweeps, double tol, double rho, hipStream_t s);
+                   size_t qoff, int max_sweeps, double tol, double rho, hipStream_t s,
+                   bool graph = false, hipStream_t cap = nullptr);
   hipError_t advance(int steps);
+  void release();
+  F32Batch() = default;
+  F32Batch(const F32Batch&) = delete;
+  F32Batch& operator=(const F32Batch&) = delete;
+  ~F32Batch() { release(); }
 
  private:
   hipError_t rebuild();
   hipError_t poll();
+  hipError_t launch_steps(int k);
 };
 
 // ------------------------------------------------------------------ one-sided SVD

@@ -1285,11 +1285,17 @@ hipError_t F32Batch::poll() {
   return r;
 }
 
+void F32Batch::release() {
+  if (gx) (void)hipGraphExecDestroy(gx);
+  gx = nullptr;
+}
+
 hipError_t F32Batch::begin(BMat* m_, const int* nvec_, int count_, int nmax_, int* dwork_,
                            size_t off, size_t qoff_, int max_sweeps_, double tol_, double rho_,
-                           hipStream_t s_) {
+                           hipStream_t s_, bool graph_, hipStream_t cap_) {
+  release();
   m = m_; nvec = nvec_; count = count_; nmax = nmax_; dwork = dwork_; qoff = qoff_;
-  max_sweeps = max_sweeps_; tol = tol_; rho = rho_; s = s_;
+  max_sweeps = max_sweeps_; tol = tol_; rho = rho_; s = s_; graph = graph_ && cap_; cap = cap_;
   step = 0;
   finished = false;
   done.assign(count, 0);
@@ -1298,16 +1304,16 @@ hipError_t F32Batch::begin(BMat* m_, const int* nvec_, int count_, int nmax_, in
   if (e != hipSuccess) return e;
   if ((e = poll()) != hipSuccess) return e;
   if ((e = rebuild()) != hipSuccess) return e;
+  live = na;
   // every matrix ends within max_sweeps sweeps of at most max_rounds rounds
   max_steps = (long long)max_sweeps * max_rounds;
   return hipSuccess;
 }
 
-hipError_t F32Batch::advance(int steps) {
+// k steps of every listed matrix: subproblem solves, A and V block updates, round control.
+hipError_t F32Batch::launch_steps(int k) {
   constexpr int NT = Blk<BPB>::NT;
-  const int poll_every = 8;
-  hipError_t e;
-  for (int k = 0; k < steps && step < max_steps && na > 0; ++k, ++step) {
+  for (int j = 0; j < k; ++j) {
     hipLaunchKernelGGL(k_round_solve_b, dim3(tps), dim3(NT), 0, s, m, dwork + count,
                        dwork + 2 * count, na, max_sweeps, (float)(tol * tol), (float)(rho * rho));
     if (tpa > 0)
@@ -1317,18 +1323,67 @@ hipError_t F32Batch::advance(int steps) {
                        dwork + 4 * count, na);
     hipLaunchKernelGGL(k_f32_control_b, dim3((na + 63) / 64), dim3(64), 0, s, m, dwork + count,
                        na, max_sweeps, tol, rho);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((step + 1) % poll_every == 0) {
-      if ((e = poll()) != hipSuccess) return e;
-      if ((e = rebuild()) != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t F32Batch::advance(int steps) {
+  const int poll_every = 8;
+  hipError_t e;
+  if (graph) {
+    // the same steps and polls as below; every matrix is done by max_steps (its sweep
+    // limit), so the steps a last replay runs past it change nothing
+    for (int k = 0; k < steps && step < max_steps && live > 0; k += poll_every) {
+      if (!gx) {
+        hipGraph_t g = nullptr;
+        if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+          return e;
+        hipStream_t run = s;
+        s = cap;
+        hipError_t ec = launch_steps(poll_every);
+        if (ec == hipSuccess) {
+          hipLaunchKernelGGL(k_f32_done_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count,
+                             dwork);
+          ec = hipGetLastError();
+        }
+        s = run;
+        const hipError_t ee = hipStreamEndCapture(cap, &g);
+        if (ec == hipSuccess) ec = ee;
+        if (ec == hipSuccess) ec = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (ec != hipSuccess) { gx = nullptr; return ec; }
+      }
+      if ((e = hipGraphLaunch(gx, s)) != hipSuccess) return e;
+      step += poll_every;
+      if ((e = hipMemcpyAsync(done.data(), dwork, count * 4, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess)
+        return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      live = 0;
+      for (int i = 0; i < count; ++i) live += done[i] ? 0 : 1;
+      // once a quarter of the listed matrices are done, the lists are rebuilt and the
+      // graph captured again: blocks of finished matrices would otherwise fill every launch
+      if (live > 0 && live * 4 <= na * 3) {
+        if ((e = rebuild()) != hipSuccess) return e;
+        release();
+      }
+    }
+  } else {
+    for (int k = 0; k < steps && step < max_steps && na > 0; ++k, ++step) {
+      if ((e = launch_steps(1)) != hipSuccess) return e;
+      if ((step + 1) % poll_every == 0) {
+        if ((e = poll()) != hipSuccess) return e;
+        if ((e = rebuild()) != hipSuccess) return e;
+      }
     }
   }
-  if (step >= max_steps || na == 0) {
+  if (step >= max_steps || (graph ? live : na) == 0) {
     size_t tot = (size_t)nmax * nmax;
     hipLaunchKernelGGL(k_f32_gather_b, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0,
                        s, m, qoff);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     finished = true;
+    release();
   }
   return hipSuccess;
 }

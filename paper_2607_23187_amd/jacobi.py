@@ -279,9 +279,10 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
                  stop="cert", want_v: bool = True, max_rotations: int = 0,
                  polish_v: bool = True, abs_thr: float = 0.0, sort: bool = True,
                  update_mode="auto", tune: bool = True, fp32_passes: int = 2,
-                 stream: torch.cuda.Stream | None = None):
+                 graph: bool = False, stream: torch.cuda.Stream | None = None):
     """Batch of independent problems of possibly different sizes (host-array form, with
-    per-problem statistics)."""
+    per-problem statistics).  ``graph`` replays the repeated step sequences from captured
+    HIP graphs (same results)."""
     L = load()
     b = len(mats)
     for m in mats:
@@ -298,7 +299,7 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
     info = IA()
     stats = (Stats * b)()
     o = _opts(stop, polish_v, 20, fp32_passes, False, max_rotations, abs_thr, sort,
-              update_mode, tune)
+              update_mode, tune, graph)
     s = stream if stream is not None else torch.cuda.current_stream()
     status = L.jacobi_eigh_batched_host(b, a_p, ns, ns, w_p, v_p, ns, float(tol),
                                         _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o),
@@ -351,9 +352,9 @@ class Server:
 
     def __init__(self, workers: int = 2, hbm_budget: int = 1 << 30, tol: float = 1e-14,
                  pivot="gap", precond="fp32", stop="cert", want_v: bool = True,
-                 polish_v: bool = True):
+                 polish_v: bool = True, graph: bool = False):
         L = load()
-        o = _opts(stop, polish_v)
+        o = _opts(stop, polish_v, graph=graph)
         self._want_v = want_v
         self._h = L.jacobi_server_create(int(workers), int(hbm_budget), float(tol),
                                          _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o))

@@ -149,3 +149,41 @@ def test_batched_timestamp_and_mirror_modes_agree(pivot):
         assert x.stats["rotations"] == y.stats["rotations"]
         assert torch.equal(x.w, y.w)
         assert torch.equal(x.v, y.v)
+
+
+@pytest.mark.parametrize("precond", ["none", "fp32"])
+def test_graph_replay_equals_direct_launches(precond):
+    """opts.graph: the FP32 rounds, the Newton-Schulz steps and the persistent FP64
+    launches replayed from captured graphs (many replays per solve, host synchronisations
+    between them, a re-capture whenever members leave) give the same bits as direct
+    launches; a second graph solve on a smaller batch starts from fresh graphs."""
+    probs = problems(SIZES, 7600)
+    tol = min(tol_for(a, lam) for a, lam in probs)
+    mats = [torch.from_numpy(a).cuda() for a, _ in probs]
+    say("graph replay", precond, SIZES)
+    st0, direct = J.eigh_batched(mats, tol=tol, pivot="gap", precond=precond)
+    for sub in (mats, mats[3:9]):
+        st1, graph = J.eigh_batched(sub, tol=tol, pivot="gap", precond=precond, graph=True)
+        assert st1 == st0 == J.OK
+        off = 0 if sub is mats else 3
+        for i, r in enumerate(graph):
+            d = direct[i + off]
+            assert r.status == J.OK
+            assert r.stats["rotations"] == d.stats["rotations"], i
+            assert torch.equal(r.w, d.w), i
+            assert torch.equal(r.v, d.v), i
+    # and through the server (cohorts admitted while others run)
+    srv = J.Server(workers=2, hbm_budget=64 << 20, tol=tol, pivot="gap", precond=precond,
+                   graph=True)
+    for t, m in enumerate(mats):
+        srv.submit(m, t)
+    got = 0
+    while got < len(mats):
+        for rec in srv.poll(wait=True):
+            got += 1
+            d = direct[rec["tag"]]
+            assert rec["status"] == J.OK
+            assert torch.equal(rec["w"], d.w), rec["n"]
+            if rec["n"] >= 2:
+                assert torch.equal(rec["v"], d.v), rec["n"]
+    srv.close()
