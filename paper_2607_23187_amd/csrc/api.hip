@@ -1063,7 +1063,7 @@ struct Cohort {
       x.final_off = c.final_off * unscale;
       x.normF = nrm[i] * unscale;
       x.thr = hm[i].jd.thr * unscale;
-      x.sweeps32 = hm[i].f_pass_sweeps;
+      x.sweeps32 = hi[i].sweeps32;
       x.scale_exp = hm[i].a_exp;
       x.jacobi_wgs = 1;
       x.status = st;

@@ -96,7 +96,7 @@ __global__ void k_collect_b(const BMat* __restrict__ mats, int count, BInfo* __r
   x.rnorm = b.scal[1];
   x.maxabs = b.scal[4];
   x.nonfinite = b.flag[0];
-  x.pad = 0;
+  x.sweeps32 = b.f_pass_sweeps;
   x.ctl = *b.jd.ctl;
   out[i] = x;
 }

@@ -161,7 +161,7 @@ struct BMat {
 // Per-matrix results gathered into one array, so the host reads a batch with one copy.
 struct BInfo {
   double normF, rnorm, maxabs;
-  int nonfinite, pad;
+  int nonfinite, sweeps32;  // sweeps32: FP32 sweeps of all passes so far
   JCtl ctl;
 };
 
