@@ -143,14 +143,19 @@ def roofline(stats, n):
     t = tk + ta
     achieved = per_rot * rot / (t * 1e-3) / 1e9 if t > 0 else 0.0
     half = 32.0 * n
+    wgs = int(stats.get("jacobi_wgs", 1))
+    # the pivoted Jacobi kernel that ran: several one-wave workgroups (k_jacobi_mw) or one
+    # workgroup (k_jacobi)
+    kj = "k_jacobi_mw" if wgs > 1 else "k_jacobi"
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": pmc_traffic(PMC_FILE, "n", n),
-            "kernel": "k_jacobi + k_apply_log (the FP64 Jacobi phase of one solve)",
+            "kernel": f"{kj} ({wgs} workgroup{'s' if wgs > 1 else ''}) + k_apply_log "
+                      "(the FP64 Jacobi phase of one solve)",
             "algorithmic_bytes_per_rotation": per_rot, "rotations_per_launch": rot,
             "kernel_ms": t, "us_per_rotation": t * 1e3 / max(1, rot),
             "kernels": {
-                "k_jacobi": {"ms": tk, "bytes_per_rotation": half,
+                kj: {"ms": tk, "bytes_per_rotation": half, "workgroups": wgs,
                              "achieved_GBs": half * rot / (tk * 1e-3) / 1e9 if tk > 0 else 0.0,
                              "us_per_rotation": tk * 1e3 / max(1, rot),
                              "what": "rows p, q of A read and written"},

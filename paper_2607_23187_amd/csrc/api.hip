@@ -216,7 +216,7 @@ struct Timer {
 // R = I - X^T X, X <- X + X R / 2.  Returns ||R||_F (before the step) through `rnorm`.
 int ns_step(double*& X, double*& Xalt, double* R, int n, int ld, double* part, double* scal,
             double* rnorm, hipStream_t s) {
-  HIPCHK(launch_dgemm(n, 1, -1.0, X, ld, X, ld, 0.0, nullptr, 0, R, ld, s));
+  HIPCHK(launch_dgemm_sym(n, -1.0, X, ld, X, ld, R, ld, s));
   HIPCHK(launch_add_identity(R, n, ld, 1.0, s));
   if (rnorm) {
     HIPCHK(launch_fro2(R, n, ld, part, scal, s));
@@ -264,8 +264,7 @@ int precond_q(const double* Asym, int n, int ld, double*& X, double*& Xo, double
   if (r) return r;
   for (int pass = 1; pass < o.fp32_passes; ++pass) {
     HIPCHK(launch_dgemm(n, 0, 1.0, Asym, ld, X, ld, 0.0, nullptr, 0, T, ld, s));
-    HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, T, ld, 0.0, nullptr, 0, A, ld, s));
-    HIPCHK(launch_symmetrize(A, n, ld, s));
+    HIPCHK(launch_dgemm_sym(n, 1.0, X, ld, T, ld, A, ld, s));
     HIPCHK(run_precond_f32(A, n, ld, T, ld, f32, o.fp32_max_sweeps,
                            refine_floor ? kF32Tol2 : 0.0, kF32Rho2, &sw, o.fp32_block,
                            o.graph != 0, s));
@@ -327,15 +326,16 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
     if (r) return r;
     S.ms_precond = tp.stop();
     Timer tg(s);
-    // A_hat = X^T (A X): T = A X, A_hat = X^T T, then exact symmetry
+    // A_hat = X^T (A X): T = A X, A_hat = X^T T, exactly symmetric (the FP64 product forms
+    // the upper half and mirrors it; the split product forms all of it, then symmetrised)
     if (o.split_gemm) {
       HIPCHK(launch_gemm_split(n, 0, w.Asym, ld, X, ld, w.T, ld, w.split, s));
       HIPCHK(launch_gemm_split(n, 1, X, ld, w.T, ld, w.A, ld, w.split, s));
+      HIPCHK(launch_symmetrize(w.A, n, ld, s));
     } else {
       HIPCHK(launch_dgemm(n, 0, 1.0, w.Asym, ld, X, ld, 0.0, nullptr, 0, w.T, ld, s));
-      HIPCHK(launch_dgemm(n, 1, 1.0, X, ld, w.T, ld, 0.0, nullptr, 0, w.A, ld, s));
+      HIPCHK(launch_dgemm_sym(n, 1.0, X, ld, w.T, ld, w.A, ld, s));
     }
-    HIPCHK(launch_symmetrize(w.A, n, ld, s));
     HIPCHK(hipMemcpyAsync(Vw, X, (size_t)n * ld * 8, hipMemcpyDeviceToDevice, s));
     Ajac = w.A;
     S.ms_gemm = tg.stop();
@@ -935,7 +935,7 @@ struct Cohort {
   // One Newton-Schulz step on every member not yet converged; *converged when all are.
   hipError_t ns_launches() {
     hipError_t e;
-    if ((e = launch_dgemm_b(dm, cnt, nmax, 1, -1.0, offX, offX, 0.0, 0, BF(R), s, 1))) return e;
+    if ((e = launch_dgemm_sym_b(dm, cnt, nmax, -1.0, offX, offX, BF(R), s, 1))) return e;
     if ((e = launch_add_identity_b(dm, cnt, nmax, BF(R), 1.0, s, 1))) return e;
     if ((e = launch_fro2_b(dm, cnt, nmax, BF(R), 1, s))) return e;
     if ((e = launch_dgemm_b(dm, cnt, nmax, 0, 0.5, offX, BF(R), 1.0, offX, offXb, s))) return e;
@@ -1037,7 +1037,7 @@ struct Cohort {
     bool anyv = false;
     for (const BMat& x : hf) anyv = anyv || x.Vout != nullptr;
     if (anyv && o.polish_v) {
-      HIPCHK(launch_dgemm_b(dfin, nf, nfmax, 1, -1.0, BF(Vw), BF(Vw), 0.0, 0, BF(R), s));
+      HIPCHK(launch_dgemm_sym_b(dfin, nf, nfmax, -1.0, BF(Vw), BF(Vw), BF(R), s));
       HIPCHK(launch_add_identity_b(dfin, nf, nfmax, BF(R), 1.0, s));
       HIPCHK(launch_dgemm_b(dfin, nf, nfmax, 0, 0.5, BF(Vw), BF(R), 1.0, BF(Vw), BF(X), s));
       HIPCHK(launch_copy_mat_b(dfin, nf, nfmax, BF(Vw), BF(X), s));
@@ -1112,8 +1112,7 @@ struct Cohort {
       case REFINE: {
         Timer tp(s);
         HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
-        HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
-        HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
+        HIPCHK(launch_dgemm_sym_b(dm, cnt, nmax, 1.0, offX, BF(T), BF(A), s));
         HIPCHK(f32.begin(dm, nv.data(), cnt, nmax, d_work, BF(A), BF(T), o.fp32_max_sweeps,
                          kF32Tol2, kF32Rho2, s, o.graph != 0, cap));
         phase = F32B;
@@ -1124,8 +1123,7 @@ struct Cohort {
         if (precond) {
           Timer tg(s);
           HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
-          HIPCHK(launch_dgemm_b(dm, cnt, nmax, 1, 1.0, offX, BF(T), 0.0, 0, BF(A), s));
-          HIPCHK(launch_symmetrize_b(dm, cnt, nmax, BF(A), s));
+          HIPCHK(launch_dgemm_sym_b(dm, cnt, nmax, 1.0, offX, BF(T), BF(A), s));
           HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(Vw), offX, s));
           HIPCHK(launch_get_diag_b(dm, cnt, nmax, BF(A), s));
           S.ms_gemm += tg.stop();

@@ -18,8 +18,11 @@ constexpr int GK = 32;   // K step
 
 // One 64 x 64 tile of C.  K advances in steps of GK; the operands of the next step are
 // loaded into registers while the matrix cores work on the current one (with a single
-// workgroup per CU at n = 1024 nothing else would hide the global-load latency).
-template <int TRANSA>
+// workgroup per CU at n = 1024 nothing else would hide the global-load latency).  SYM: the
+// product is symmetric (X^T X, or Q^T (A Q) for symmetric A); only tiles on or above the
+// diagonal are computed, and each entry C[i][j], i <= j, is also stored at C[j][i], so the
+// result is exactly symmetric (beta must be 0).
+template <int TRANSA, bool SYM = false>
 __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __restrict__ A,
                                            int lda, const double* __restrict__ B, int ldb,
                                            double beta, const double* Cin, int ldcin, double* C,
@@ -94,7 +97,13 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
       for (int r = 0; r < 4; ++r) {
         int i = i0 + wi + a * 16 + 4 * r + lk;
         int j = j0 + wj + b * 16 + lr;
-        if (i < n && j < n) {
+        if (SYM) {
+          if (i <= j && j < n) {
+            const double v = alpha * acc[a][b][r];
+            C[(size_t)i * ldc + j] = v;
+            if (i < j) C[(size_t)j * ldc + i] = v;
+          }
+        } else if (i < n && j < n) {
           double v = alpha * acc[a][b][r];
           if (beta != 0.0) v += beta * Cin[(size_t)i * ldcin + j];
           C[(size_t)i * ldc + j] = v;
@@ -110,6 +119,23 @@ __global__ __launch_bounds__(256) void k_dgemm(int n, double alpha, const double
   dgemm_tile<TRANSA>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc, blockIdx.y, blockIdx.x);
 }
 
+// Tile t of the upper triangle of an nb x nb tile grid, row by row: (by, bx), by <= bx.
+__device__ __forceinline__ void upper_tile(int t, int nb, int& by, int& bx) {
+  by = 0;
+  while (t >= nb - by) { t -= nb - by; ++by; }
+  bx = by + t;
+}
+
+// C = alpha A^T B, symmetric: one workgroup per tile on or above the diagonal.
+__global__ __launch_bounds__(256) void k_dgemm_sym(int n, int nb, double alpha,
+                                                   const double* __restrict__ A, int lda,
+                                                   const double* __restrict__ B, int ldb,
+                                                   double* C, int ldc) {
+  int by, bx;
+  upper_tile(blockIdx.x, nb, by, bx);
+  dgemm_tile<1, true>(n, alpha, A, lda, B, ldb, 0.0, nullptr, 0, C, ldc, by, bx);
+}
+
 __device__ __forceinline__ double* bm_ptr(BMat& b, size_t off) {
   return *reinterpret_cast<double**>(reinterpret_cast<char*>(&b) + off);
 }
@@ -121,29 +147,44 @@ __device__ __forceinline__ double* bm_ptr(BMat& b, size_t off) {
 // L2 instead of fetching them into several.
 constexpr int kXcds = 8;
 
-template <int TRANSA>
+template <int TRANSA, bool SYM = false>
 __global__ __launch_bounds__(256) void k_dgemm_b(BMat* __restrict__ mats, int count, int nb,
                                                  double alpha, size_t offA, size_t offB,
                                                  double beta, size_t offCin, size_t offC,
                                                  int ns_mask) {
-  const int L = blockIdx.x, xcd = L % kXcds, slot = L / kXcds, T = nb * nb;
+  const int T = SYM ? nb * (nb + 1) / 2 : nb * nb;
+  const int L = blockIdx.x, xcd = L % kXcds, slot = L / kXcds;
   const int z = xcd + kXcds * (slot / T), t = slot % T;
   if (z >= count) return;
   BMat& b = mats[z];
   const int n = b.n;
-  const int by = t / nb, bx = t % nb;
+  int by, bx;
+  if (SYM) upper_tile(t, nb, by, bx);
+  else { by = t / nb; bx = t % nb; }
   if (by * GB >= n || bx * GB >= n) return;
   if (ns_mask && b.ns_done) {  // converged member: C = 0 (its update then leaves X as is)
     double* C = bm_ptr(b, offC);
     for (int e = threadIdx.x; e < GB * GB; e += 256) {
       const int i = by * GB + e / GB, j = bx * GB + e % GB;
-      if (i < n && j < n) C[(size_t)i * b.ld + j] = 0.0;
+      if (i < n && j < n) {
+        C[(size_t)i * b.ld + j] = 0.0;
+        if (SYM) C[(size_t)j * b.ld + i] = 0.0;  // and the mirrored tile
+      }
     }
     return;
   }
-  dgemm_tile<TRANSA>(n, alpha, bm_ptr(b, offA), b.ld, bm_ptr(b, offB), b.ld, beta,
-                     beta != 0.0 ? bm_ptr(b, offCin) : nullptr, b.ld, bm_ptr(b, offC), b.ld,
-                     by, bx);
+  dgemm_tile<TRANSA, SYM>(n, alpha, bm_ptr(b, offA), b.ld, bm_ptr(b, offB), b.ld, beta,
+                          beta != 0.0 ? bm_ptr(b, offCin) : nullptr, b.ld, bm_ptr(b, offC),
+                          b.ld, by, bx);
+}
+
+hipError_t launch_dgemm_sym_b(BMat* m, int count, int nmax, double alpha, size_t offA,
+                              size_t offB, size_t offC, hipStream_t s, int ns_mask) {
+  const int nb = (nmax + GB - 1) / GB;
+  const long long blocks = (long long)kXcds * ((count + kXcds - 1) / kXcds) * (nb * (nb + 1) / 2);
+  hipLaunchKernelGGL((k_dgemm_b<1, true>), dim3((unsigned)blocks), dim3(256), 0, s, m, count, nb,
+                     alpha, offA, offB, 0.0, (size_t)0, offC, ns_mask);
+  return hipGetLastError();
 }
 
 hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
@@ -198,6 +239,14 @@ hipError_t launch_ns_reset_b(BMat* m, int count, hipStream_t s) {
 
 hipError_t launch_ns_flag_b(BMat* m, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_ns_flag_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgemm_sym(int n, double alpha, const double* A, int lda, const double* B,
+                            int ldb, double* C, int ldc, hipStream_t s) {
+  const int nb = (n + GB - 1) / GB;
+  hipLaunchKernelGGL(k_dgemm_sym, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, n, nb, alpha, A, lda,
+                     B, ldb, C, ldc);
   return hipGetLastError();
 }
 

@@ -103,6 +103,10 @@ hipError_t launch_copy_pivots(const RotEntry* log, long long m, int* out, hipStr
 // FP64 GEMM on MFMA: C = alpha * op(A) * B + beta * Cin (all row-major, square n).
 // op(A) = A if transA == 0 else A^T.  Cin may equal C only if beta == 0 or the tiles
 // of C are only read by their own block (always true here).
+// C = alpha A^T B for a symmetric product (X^T X, Q^T (A Q)): the tiles on and above the
+// diagonal are computed and mirrored, so C is exactly symmetric.
+hipError_t launch_dgemm_sym(int n, double alpha, const double* A, int lda, const double* B,
+                            int ldb, double* C, int ldc, hipStream_t s);
 hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int lda,
                         const double* B, int ldb, double beta, const double* Cin, int ldcin,
                         double* C, int ldc, hipStream_t s);
@@ -193,6 +197,8 @@ hipError_t launch_maxabs_b(BMat* m, int count, int nmax, size_t off, int out_slo
 // members with a_exp != 0: matrix at `off` and diag scaled by 2^a_exp
 hipError_t launch_scale_b(BMat* m, int count, int nmax, size_t off, hipStream_t s);
 // ns_mask: members with ns_done get C = 0 (no product), resp. no identity added
+hipError_t launch_dgemm_sym_b(BMat* m, int count, int nmax, double alpha, size_t offA,
+                              size_t offB, size_t offC, hipStream_t s, int ns_mask = 0);
 hipError_t launch_dgemm_b(BMat* m, int count, int nmax, int transA, double alpha, size_t offA,
                           size_t offB, double beta, size_t offCin, size_t offC, hipStream_t s,
                           int ns_mask = 0);
