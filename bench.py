@@ -348,18 +348,20 @@ def run_batch(args):
                                           if ta > 0 else 0.0}}}
     # the same solve with the repeated step sequences replayed from captured graphs
     glat = []
-    for i in range(max(1, args.batch_warmup) + args.batch_steps):
+    for i in range(0 if args.no_graph else max(1, args.batch_warmup) + args.batch_steps):
         gst, gres, dt = run_batched(graph=True)
         if i >= max(1, args.batch_warmup):
             glat.append(dt)
         log(f"batched graph replay {i}: {dt * 1e3:.1f} ms, status {gst}")
-    same = all(torch.equal(a.w, b.w) and torch.equal(a.v, b.v) and
-               a.stats["rotations"] == b.stats["rotations"] for a, b in zip(res, gres))
-    gmed = float(np.median(glat))
-    out["graph_replay"] = {"seconds": gmed, "solves_per_s": len(probs) / gmed,
-                           "p50_ms": pct([x * 1e3 for x in glat], 50),
-                           "direct_over_graph": med / gmed, "same_bits_as_direct": bool(same)}
-    del gres
+    if glat:
+        same = all(torch.equal(a.w, b.w) and torch.equal(a.v, b.v) and
+                   a.stats["rotations"] == b.stats["rotations"] for a, b in zip(res, gres))
+        gmed = float(np.median(glat))
+        out["graph_replay"] = {"seconds": gmed, "solves_per_s": len(probs) / gmed,
+                               "p50_ms": pct([x * 1e3 for x in glat], 50),
+                               "direct_over_graph": med / gmed,
+                               "same_bits_as_direct": bool(same)}
+        del gres
     if not args.no_compare:
         singles = 0
         torch.cuda.synchronize()
@@ -758,6 +760,8 @@ def main():
                     help="default line without the batched workload")
     ap.add_argument("--no-precision", action="store_true",
                     help="default line without the n=4096 precision workload")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the batched solve replayed from captured graphs")
     ap.add_argument("--no-crossing", action="store_true",
                     help="skip the orthogonality-before-polish solve and the bisection for "
                          "the true-error crossing (every solve of the run is then a full one)")
