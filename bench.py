@@ -414,6 +414,9 @@ def bench_serve(args):
     import math
 
     import numpy as np
+    # one hardware queue per lane (set before the runtime starts): with HIP's default of 4,
+    # lanes share queues and a long step of one lane holds back the steps queued behind it
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(max(8, args.workers)))
     import torch
 
     from paper_2607_23187_amd import inputs as I
@@ -751,7 +754,7 @@ def main():
     ap.add_argument("--requests", type=int, default=20000)
     ap.add_argument("--pool", type=int, default=512)
     ap.add_argument("--workers", type=int, default=8, help="server lanes")
-    ap.add_argument("--budget", type=int, default=8192, help="server HBM budget, MiB")
+    ap.add_argument("--budget", type=int, default=65536, help="server HBM budget, MiB")
     ap.add_argument("--rho-list", default="0.5,0.8,0.95")
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--batch-steps", type=int, default=3)

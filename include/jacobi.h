@@ -279,7 +279,9 @@ void jacobi_release(void);
  * running; a request that does not fit, or whose lane runs two cohorts, waits and joins the
  * lane's next cohort.  A problem whose solve has ended
  * leaves its cohort at once: its completion record is posted and its memory returned.
- * Cohorts of different lanes run concurrently on the device.
+ * Cohorts of different lanes run concurrently on the device (when the process has at least
+ * as many hardware queues as lanes: HIP's GPU_MAX_HW_QUEUES, 4 by default, is read when the
+ * runtime starts; with fewer, lanes share queues and their launches serialize).
  *
  * Ownership: A, W and V of a request are the caller's device memory and must stay valid
  * (A unmodified) until the request's completion record has been polled.  The server owns
