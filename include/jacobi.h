@@ -128,7 +128,8 @@ typedef struct je_opts {
                              /* results as direct launches)                          */
   int profile;               /* 1: phase timers of the FP64 Jacobi kernel into        */
                              /* je_stats.prof_ns (slows the kernel slightly)     (0)  */
-  int fp32_block;            /* rows per block of the FP32 stage: 0 by n, 16 or 32 (0) */
+  int fp32_block;            /* rows per block of the FP32 stage: 0 by n (batches:  (0) */
+                             /* 32), 16 or 32                                         */
   int jacobi_wgs;            /* FP64 phase of one problem: 0 automatic (several       */
                              /* workgroups from n = 768), 1 one workgroup, 2 several */
                              /* workgroups when the matrix lives in HBM; same results */

@@ -604,11 +604,12 @@ size_t bws_bytes(int n, int precond, long long cap) {
   size_t mat = al((size_t)n * ld * 8);
   size_t b = 7 * mat + 8 * al((size_t)n * 8) + al(64) + 7 * al((size_t)n * 4) +
              al(sizeof(JCtl)) + al((size_t)cap * sizeof(RotEntry));
-  if (precond) b += al(precond_f32_bytes_b(n));
+  // the FP32 stage's state for either block size (a cohort picks one for all members)
+  if (precond) b += al(std::max(precond_f32_bytes_b(n, 16), precond_f32_bytes_b(n, 32)));
   return b;
 }
 
-void bws_carve(char* p, BMat& b, int n, int precond, long long cap) {
+void bws_carve(char* p, BMat& b, int n, int precond, long long cap, int pb) {
   const size_t ld = ld_of(n);
   const size_t mat = al((size_t)n * ld * 8);
   auto take = [&](size_t bytes) { char* r = p; p += al(bytes); return (void*)r; };
@@ -630,18 +631,15 @@ void bws_carve(char* p, BMat& b, int n, int precond, long long cap) {
   d.log = (RotEntry*)take((size_t)cap * sizeof(RotEntry));
   d.log_cap = cap;
   if (precond) {
-    const int PB = precond_f32_block_b(), PM = 2 * PB;
+    const int PM = 2 * pb;
     const int np = (n + PM - 1) / PM * PM;
-    char* f = (char*)take(precond_f32_bytes_b(n));
+    char* f = (char*)take(std::max(precond_f32_bytes_b(n, 16), precond_f32_bytes_b(n, 32)));
     b.np = np;
-    b.nb = np / PB;
+    b.nb = np / pb;
     b.A32 = (float*)f;
     b.V32 = b.A32 + (size_t)np * np;
     b.U = b.V32 + (size_t)n * np;
-    const size_t nb2 = (size_t)b.nb / 2;
-    const size_t fb = ((size_t)np * np * 4 + (size_t)n * np * 4 + 2 * nb2 * PM * PM * 4 + 255) &
-                      ~(size_t)255;
-    b.part = (double*)(f + fb);
+    b.part = (double*)(f + precond_f32_part_b(n, pb));
   }
 }
 
@@ -732,6 +730,7 @@ struct Cohort {
   int ns_iter = 0, pass = 0;
   size_t offX = BF(X), offXb = BF(Xb);
   F32Batch f32;
+  int f32_pb = 32;  // block rows of the FP32 stage (one size for the cohort)
   bool mirror = false;
   int shape_lds = 64, shape_hbm = 512;
   je_stats S{};
@@ -848,12 +847,15 @@ struct Cohort {
     d_info = (BInfo*)mp;
     hi.assign(cnt, BInfo{});
     hm.assign(cnt, BMat{});
+    int nbig = 0;
+    for (const Member& m : mem) nbig = std::max(nbig, m.n);
+    f32_pb = precond_f32_block_b(nbig, o.fp32_block);
     for (int i = 0; i < cnt; ++i) {
       BMat& x = hm[i];
       std::memset(&x, 0, sizeof(x));
       x.Au = mem[i].A; x.n = mem[i].n; x.lda = mem[i].lda;
       x.Wout = mem[i].W; x.Vout = mem[i].V; x.ldv = mem[i].ldv;
-      bws_carve(mem[i].ws, x, mem[i].n, precond, kBatchLogCap);
+      bws_carve(mem[i].ws, x, mem[i].n, precond, kBatchLogCap, f32_pb);
     }
     refresh_sizes();
     if (int r = upload()) return r;
@@ -922,7 +924,7 @@ struct Cohort {
       if (o.graph)
         if (int r = capture_stream()) return r;
       HIPCHK(f32.begin(dm, nv.data(), cnt, nmax, d_work, BF(Asym), offX, o.fp32_max_sweeps,
-                       f32_tol1(o.fp32_passes), kF32Rho1, s, o.graph != 0, cap));
+                       f32_tol1(o.fp32_passes), kF32Rho1, s, o.graph != 0, cap, f32_pb));
       phase = F32A;
     } else {
       HIPCHK(launch_set_identity_b(dm, cnt, nmax, BF(Vw), s));
@@ -1114,7 +1116,7 @@ struct Cohort {
         HIPCHK(launch_dgemm_b(dm, cnt, nmax, 0, 1.0, BF(Asym), offX, 0.0, 0, BF(T), s));
         HIPCHK(launch_dgemm_sym_b(dm, cnt, nmax, 1.0, offX, BF(T), BF(A), s));
         HIPCHK(f32.begin(dm, nv.data(), cnt, nmax, d_work, BF(A), BF(T), o.fp32_max_sweeps,
-                         kF32Tol2, kF32Rho2, s, o.graph != 0, cap));
+                         kF32Tol2, kF32Rho2, s, o.graph != 0, cap, f32_pb));
         phase = F32B;
         S.ms_precond += tp.stop();
         return JE_OK;

@@ -213,8 +213,12 @@ hipError_t launch_symmetrize_b(BMat* m, int count, int nmax, size_t off, hipStre
 // given stop rule until every matrix is done (each at its own pace, at most max_sweeps);
 // then the first n columns of V32 (FP64) into the matrix at `qoff`.  nvec: host array of
 // the sizes; dwork: device ints, 5 per matrix.
-size_t precond_f32_bytes_b(int n);
-int precond_f32_block_b();  // block rows PB of the batched FP32 stage
+// Batched FP32 stage: bytes of one matrix's state with blocks of pb rows (and the part
+// before its per-block sums), and the block rows of a batch whose largest n is nmax
+// (request 16 or 32 overrides the choice).
+size_t precond_f32_bytes_b(int n, int pb);
+size_t precond_f32_part_b(int n, int pb);
+int precond_f32_block_b(int nmax, int request);
 hipError_t run_precond_f32_b(BMat* m, const int* nvec, int count, int nmax, int* dwork,
                              size_t off, size_t qoff, int max_sweeps, double tol, double rho,
                              hipStream_t s);
@@ -244,9 +248,10 @@ struct F32Batch {
   hipStream_t cap = nullptr;
   hipGraphExec_t gx = nullptr;
   int live = 0;  // matrices not yet done (graph replay)
+  int pb = 32;  // block rows
   hipError_t begin(BMat* m, const int* nvec, int count, int nmax, int* dwork, size_t off,
                    size_t qoff, int max_sweeps, double tol, double rho, hipStream_t s,
-                   bool graph = false, hipStream_t cap = nullptr);
+                   bool graph = false, hipStream_t cap = nullptr, int pb = 32);
   hipError_t advance(int steps);
   void release();
   F32Batch() = default;

@@ -989,14 +989,19 @@ static hipError_t run_blocked(const double* Asym, int n, int ld, double* Q, int 
 }
 
 // ------------------------------------------------------------------ batches
-// Every matrix of a batch runs the same blocked FP32 Jacobi (blocks of 16 rows) at its own
-// pace: a step performs the next round of every matrix not yet done (subproblem solves,
-// then the A and V block updates), and a control kernel closes a sweep when a matrix's
-// round counter wraps (off-norm, stop rule).  Blocks of a launch are spread over the
-// matrices by prefix sums of their per-matrix block counts.
-constexpr int BPB = 32;
-
-int precond_f32_block_b() { return BPB; }
+// Every matrix of a batch runs the same blocked FP32 Jacobi (blocks of PB = 16 or 32 rows,
+// one size per batch) at its own pace: a step performs the next round of every matrix not
+// yet done (subproblem solves, then the A and V block updates), and a control kernel
+// closes a sweep when a matrix's round counter wraps (off-norm, stop rule).  Blocks of a
+// launch are spread over the matrices by prefix sums of their per-matrix block counts.
+// 32 by default: a batch is throughput-bound, and 16-row blocks need more sweeps (2048
+// matrices, n in [32, 512]: 9.6 against 8.1 sweeps on average, 280-285 against 256-265 ms
+// per batch on MI355X).
+int precond_f32_block_b(int nmax, int request) {
+  if (request == 16 || request == 32) return request;
+  (void)nmax;
+  return 32;
+}
 
 __device__ __forceinline__ int find_mat(const int* __restrict__ prefix, int count, int blk) {
   int lo = 0, hi = count - 1;  // largest m with prefix[m] <= blk
@@ -1014,8 +1019,9 @@ __device__ __forceinline__ int2 block_pair(int nb, int r, int k) {
   return int2{min(x, y), max(x, y)};
 }
 
+template <int PB>
 __device__ __forceinline__ float* ubuf_b(const BMat& b, int par) {
-  constexpr int PM = Blk<BPB>::PM;
+  constexpr int PM = Blk<PB>::PM;
   return b.U + (size_t)par * (b.nb / 2) * PM * PM;
 }
 
@@ -1044,10 +1050,11 @@ __device__ __forceinline__ void tile_sq(float (*T)[Blk<PB>::PL], bool diag, doub
   }
 }
 
-__global__ __launch_bounds__(Blk<BPB>::NT) void k_round_solve_b(
+template <int PB>
+__global__ __launch_bounds__(Blk<PB>::NT) void k_round_solve_b(
     BMat* __restrict__ mats, const int* __restrict__ act, const int* __restrict__ prefix,
     int count, int max_inner, float tol2, float rho2) {
-  constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL;
+  constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL;
   __shared__ __align__(16) float lds[3][PM][PL];
   const int j = find_mat(prefix, count, blockIdx.x);
   BMat& b = mats[act[j]];
@@ -1056,22 +1063,23 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_solve_b(
   const int r = b.f_round;
   const int2 pr = block_pair(b.nb, r, k);
   const int par = (b.f_sweeps * (b.nb - 1) + r) & 1;
-  solve_body<BPB>(lds[0], lds[1], lds[2], b.A32, b.A32, b.np, pr, ubuf_b(b, par) + (size_t)k * PM * PM,
+  solve_body<PB>(lds[0], lds[1], lds[2], b.A32, b.A32, b.np, pr, ubuf_b<PB>(b, par) + (size_t)k * PM * PM,
                   b.nb == 2 ? max_inner : 1, r == 0 ? 1 : 0, tol2, rho2);
   // the solved block as written back: its upper triangle, mirrored
-  for (int e = threadIdx.x; e < PM * PM; e += Blk<BPB>::NT) {
+  for (int e = threadIdx.x; e < PM * PM; e += Blk<PB>::NT) {
     const int i = e / PM, j = e % PM;
     if (i > j) lds[1][i][j] = lds[0][j][i];
     else lds[1][i][j] = lds[0][i][j];
   }
   __syncthreads();
-  tile_sq<BPB>(lds[1], true, 1.0, b.part + 2 * k);
+  tile_sq<PB>(lds[1], true, 1.0, b.part + 2 * k);
 }
 
-__global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
+template <int PB>
+__global__ __launch_bounds__(Blk<PB>::NT) void k_round_apply_a_b(
     BMat* __restrict__ mats, const int* __restrict__ act, const int* __restrict__ prefix,
     int count) {
-  constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL, NT = Blk<BPB>::NT;
+  constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL, NT = Blk<PB>::NT;
   static_assert(2 * NT * 4 == PM * PM, "two four-float groups of a tile per thread");
   // two LDS tiles (four workgroups per CU): U_R waits in registers until U_P is consumed
   __shared__ __align__(16) float X[PM][PL], Y[PM][PL];
@@ -1086,11 +1094,11 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
   const int r = bm.f_round;
   const int2 pp = block_pair(bm.nb, r, P), pr = block_pair(bm.nb, r, R);
   const int par = (bm.f_sweeps * (bm.nb - 1) + r) & 1;
-  const float* Ug = ubuf_b(bm, par) + (size_t)P * PM * PM;
-  const float* Uh = ubuf_b(bm, par) + (size_t)R * PM * PM;
+  const float* Ug = ubuf_b<PB>(bm, par) + (size_t)P * PM * PM;
+  const float* Uh = ubuf_b<PB>(bm, par) + (size_t)R * PM * PM;
   float* A = bm.A32;
   const int np = bm.np, tid = threadIdx.x;
-  // four consecutive columns per lane (they lie in one block: BPB is a multiple of 4):
+  // four consecutive columns per lane (they lie in one block: PB is a multiple of 4):
   // X = U_P, Y = A_PR, registers = U_R
   const int i0 = tid / (PM / 4), j0 = (tid % (PM / 4)) * 4, i1 = i0 + NT / (PM / 4);
   const float4 ur0 = *reinterpret_cast<const float4*>(Uh + i0 * PM + j0);
@@ -1098,47 +1106,48 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_a_b(
   *reinterpret_cast<float4*>(&X[i0][j0]) = *reinterpret_cast<const float4*>(Ug + i0 * PM + j0);
   *reinterpret_cast<float4*>(&X[i1][j0]) = *reinterpret_cast<const float4*>(Ug + i1 * PM + j0);
   *reinterpret_cast<float4*>(&Y[i0][j0]) = *reinterpret_cast<const float4*>(
-      A + (size_t)blk_row<BPB>(pp.x, pp.y, i0) * np + blk_row<BPB>(pr.x, pr.y, j0));
+      A + (size_t)blk_row<PB>(pp.x, pp.y, i0) * np + blk_row<PB>(pr.x, pr.y, j0));
   *reinterpret_cast<float4*>(&Y[i1][j0]) = *reinterpret_cast<const float4*>(
-      A + (size_t)blk_row<BPB>(pp.x, pp.y, i1) * np + blk_row<BPB>(pr.x, pr.y, j0));
+      A + (size_t)blk_row<PB>(pp.x, pp.y, i1) * np + blk_row<PB>(pr.x, pr.y, j0));
   __syncthreads();
   f4 acc[2];
-  tile_mfma<BPB, true>(X, Y, acc);  // T = U_P^T A_PR
+  tile_mfma<PB, true>(X, Y, acc);  // T = U_P^T A_PR
   __syncthreads();
-  tile_store_lds<BPB>(Y, acc);
+  tile_store_lds<PB>(Y, acc);
   *reinterpret_cast<float4*>(&X[i0][j0]) = ur0;
   *reinterpret_cast<float4*>(&X[i1][j0]) = ur1;
   __syncthreads();
-  tile_mfma<BPB, false>(Y, X, acc);  // T U_R
+  tile_mfma<PB, false>(Y, X, acc);  // T U_R
   __syncthreads();
   // the new block A_PR by rows in X and transposed (A_RP by rows) in Y, so that both are
   // stored four consecutive columns per lane
-  tile_store_lds<BPB>(X, acc);
+  tile_store_lds<PB>(X, acc);
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int i, j;
-      tile_rc<BPB>(u, v, i, j);
+      tile_rc<PB>(u, v, i, j);
       Y[j][i] = acc[u][v];
     }
   __syncthreads();
   for (int e = tid; e < PM * PM / 4; e += NT) {
     const int i = e / (PM / 4), j = (e % (PM / 4)) * 4;
-    *reinterpret_cast<float4*>(A + (size_t)blk_row<BPB>(pp.x, pp.y, i) * np +
-                               blk_row<BPB>(pr.x, pr.y, j)) =
+    *reinterpret_cast<float4*>(A + (size_t)blk_row<PB>(pp.x, pp.y, i) * np +
+                               blk_row<PB>(pr.x, pr.y, j)) =
         *reinterpret_cast<const float4*>(&X[i][j]);
-    *reinterpret_cast<float4*>(A + (size_t)blk_row<BPB>(pr.x, pr.y, i) * np +
-                               blk_row<BPB>(pp.x, pp.y, j)) =
+    *reinterpret_cast<float4*>(A + (size_t)blk_row<PB>(pr.x, pr.y, i) * np +
+                               blk_row<PB>(pp.x, pp.y, j)) =
         *reinterpret_cast<const float4*>(&Y[i][j]);
   }
-  tile_sq<BPB>(X, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
+  tile_sq<PB>(X, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
 }
 
-__global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_v_b(
+template <int PB>
+__global__ __launch_bounds__(Blk<PB>::NT) void k_round_apply_v_b(
     BMat* __restrict__ mats, const int* __restrict__ act, const int* __restrict__ prefix,
     int count) {
-  constexpr int PM = Blk<BPB>::PM, PL = Blk<BPB>::PL;
+  constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL;
   __shared__ __align__(16) float lds[2][PM][PL];
   const int j = find_mat(prefix, count, blockIdx.x);
   BMat& b = mats[act[j]];
@@ -1148,8 +1157,8 @@ __global__ __launch_bounds__(Blk<BPB>::NT) void k_round_apply_v_b(
   const int R = bl / nvt, rt = bl - R * nvt;
   const int r = b.f_round;
   const int par = (b.f_sweeps * (b.nb - 1) + r) & 1;
-  vtile_body<BPB, true>(lds[0], lds[1], b.V32, b.n, b.np, rt * PM, block_pair(b.nb, r, R),
-                  ubuf_b(b, par) + (size_t)R * PM * PM);
+  vtile_body<PB, true>(lds[0], lds[1], b.V32, b.n, b.np, rt * PM, block_pair(b.nb, r, R),
+                  ubuf_b<PB>(b, par) + (size_t)R * PM * PM);
 }
 
 // off(A32) and ||A32||_F of one matrix by one workgroup (FP64 sums, fixed order).
@@ -1242,17 +1251,25 @@ __global__ void k_f32_gather_b(BMat* __restrict__ mats, size_t qoff) {
   Q[(size_t)i * b.ld + j] = (double)b.V32[(size_t)i * b.np + j];
 }
 
-size_t precond_f32_bytes_b(int n) {
-  constexpr int PM = Blk<BPB>::PM;
-  size_t np = (size_t)((n + PM - 1) / PM * PM), nb = np / BPB, nb2 = nb / 2;
+// Bytes of the FP32 stage of one matrix of a batch with blocks of pb rows; its layout:
+// A32 (np x np), V32 (n x np), two rounds of subproblem factors, per-block sums.
+size_t precond_f32_part_b(int n, int pb) {
+  const size_t PM = 2 * (size_t)pb;
+  size_t np = ((size_t)n + PM - 1) / PM * PM, nb = np / pb, nb2 = nb / 2;
   size_t b = np * np * 4 + (size_t)n * np * 4 + 2 * nb2 * PM * PM * 4;
-  b = (b + 255) & ~(size_t)255;
+  return (b + 255) & ~(size_t)255;
+}
+
+size_t precond_f32_bytes_b(int n, int pb) {
+  const size_t PM = 2 * (size_t)pb;
+  size_t np = ((size_t)n + PM - 1) / PM * PM, nb = np / pb, nb2 = nb / 2;
+  size_t b = precond_f32_part_b(n, pb);
   b += (nb2 + nb2 * (nb2 - 1) / 2) * 16;  // per-block sums of squares of a round
   return (b + 255) & ~(size_t)255;
 }
 
 hipError_t F32Batch::rebuild() {
-  constexpr int PM = Blk<BPB>::PM;
+  const int PM = 2 * pb;
   int* d_act = dwork + count;
   int* d_ps = dwork + 2 * count;
   int* d_pa = dwork + 3 * count;
@@ -1262,7 +1279,7 @@ hipError_t F32Batch::rebuild() {
   max_rounds = 1;
   for (int i = 0; i < count; ++i) {
     if (done[i]) continue;
-    const int np = (nvec[i] + PM - 1) / PM * PM, nb = np / BPB, nb2 = nb / 2;
+    const int np = (nvec[i] + PM - 1) / PM * PM, nb = np / pb, nb2 = nb / 2;
     const int nvt = (nvec[i] + PM - 1) / PM;
     act.push_back(i); ps.push_back(tps); pa.push_back(tpa); pv.push_back(tpv);
     tps += nb2; tpa += nb2 * (nb2 - 1) / 2; tpv += nvt * nb2;
@@ -1292,8 +1309,9 @@ void F32Batch::release() {
 
 hipError_t F32Batch::begin(BMat* m_, const int* nvec_, int count_, int nmax_, int* dwork_,
                            size_t off, size_t qoff_, int max_sweeps_, double tol_, double rho_,
-                           hipStream_t s_, bool graph_, hipStream_t cap_) {
+                           hipStream_t s_, bool graph_, hipStream_t cap_, int pb_) {
   release();
+  pb = pb_ == 16 ? 16 : 32;
   m = m_; nvec = nvec_; count = count_; nmax = nmax_; dwork = dwork_; qoff = qoff_;
   max_sweeps = max_sweeps_; tol = tol_; rho = rho_; s = s_; graph = graph_ && cap_; cap = cap_;
   step = 0;
@@ -1311,16 +1329,24 @@ hipError_t F32Batch::begin(BMat* m_, const int* nvec_, int count_, int nmax_, in
 }
 
 // k steps of every listed matrix: subproblem solves, A and V block updates, round control.
+template <int PB>
+static void round_launches(const F32Batch& f) {
+  constexpr int NT = Blk<PB>::NT;
+  const int c = f.count;
+  hipLaunchKernelGGL(k_round_solve_b<PB>, dim3(f.tps), dim3(NT), 0, f.s, f.m, f.dwork + c,
+                     f.dwork + 2 * c, f.na, f.max_sweeps, (float)(f.tol * f.tol),
+                     (float)(f.rho * f.rho));
+  if (f.tpa > 0)
+    hipLaunchKernelGGL(k_round_apply_a_b<PB>, dim3(f.tpa), dim3(NT), 0, f.s, f.m, f.dwork + c,
+                       f.dwork + 3 * c, f.na);
+  hipLaunchKernelGGL(k_round_apply_v_b<PB>, dim3(f.tpv), dim3(NT), 0, f.s, f.m, f.dwork + c,
+                     f.dwork + 4 * c, f.na);
+}
+
 hipError_t F32Batch::launch_steps(int k) {
-  constexpr int NT = Blk<BPB>::NT;
   for (int j = 0; j < k; ++j) {
-    hipLaunchKernelGGL(k_round_solve_b, dim3(tps), dim3(NT), 0, s, m, dwork + count,
-                       dwork + 2 * count, na, max_sweeps, (float)(tol * tol), (float)(rho * rho));
-    if (tpa > 0)
-      hipLaunchKernelGGL(k_round_apply_a_b, dim3(tpa), dim3(NT), 0, s, m, dwork + count,
-                         dwork + 3 * count, na);
-    hipLaunchKernelGGL(k_round_apply_v_b, dim3(tpv), dim3(NT), 0, s, m, dwork + count,
-                       dwork + 4 * count, na);
+    if (pb == 16) round_launches<16>(*this);
+    else round_launches<32>(*this);
     hipLaunchKernelGGL(k_f32_control_b, dim3((na + 63) / 64), dim3(64), 0, s, m, dwork + count,
                        na, max_sweeps, tol, rho);
   }

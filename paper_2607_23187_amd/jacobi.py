@@ -279,7 +279,8 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
                  stop="cert", want_v: bool = True, max_rotations: int = 0,
                  polish_v: bool = True, abs_thr: float = 0.0, sort: bool = True,
                  update_mode="auto", tune: bool = True, fp32_passes: int = 2,
-                 graph: bool = False, stream: torch.cuda.Stream | None = None):
+                 graph: bool = False, fp32_block: int = 0,
+                 stream: torch.cuda.Stream | None = None):
     """Batch of independent problems of possibly different sizes (host-array form, with
     per-problem statistics).  ``graph`` replays the repeated step sequences from captured
     HIP graphs (same results)."""
@@ -299,7 +300,7 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
     info = IA()
     stats = (Stats * b)()
     o = _opts(stop, polish_v, 20, fp32_passes, False, max_rotations, abs_thr, sort,
-              update_mode, tune, graph)
+              update_mode, tune, graph, fp32_block=fp32_block)
     s = stream if stream is not None else torch.cuda.current_stream()
     status = L.jacobi_eigh_batched_host(b, a_p, ns, ns, w_p, v_p, ns, float(tol),
                                         _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o),
