@@ -69,13 +69,14 @@ def test_batched_plain_equals_single_and_oracle(pivot):
 
 
 @pytest.mark.parametrize("pivot", ["greedy", "gap"])
-def test_batched_preconditioned_accuracy(pivot):
+def test_batched_preconditioned_accuracy(pivot, fp32_block=0):
     sizes = [2, 5, 31, 32, 33, 64, 97, 128, 160, 256, 333, 512]
     probs = problems(sizes, 7300)
     tol = min(tol_for(a, lam) for a, lam in probs)
     mats = [torch.from_numpy(a).cuda() for a, _ in probs]
-    say("batched fp32", pivot, sizes)
-    status, res = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="fp32")
+    say("batched fp32", pivot, sizes, "block rows", fp32_block)
+    status, res = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="fp32",
+                                 fp32_block=fp32_block)
     assert status == J.OK
     for (a, lam), r in zip(probs, res):
         n = a.shape[0]
@@ -92,6 +93,11 @@ def test_batched_preconditioned_accuracy(pivot):
         thr = tol * normF / (2.0 * n * (n - 1))
         resid = np.linalg.norm(a @ v - v * w[None, :])
         assert resid <= n * np.sqrt(4 * thr * lam2) + 100 * n * U * normF, n
+
+
+def test_batched_sixteen_row_blocks():
+    """The batched FP32 stage with 16-row blocks (opts.fp32_block = 16) meets the same bar."""
+    test_batched_preconditioned_accuracy("gap", fp32_block=16)
 
 
 def test_batched_repeatable_and_order_independent():
