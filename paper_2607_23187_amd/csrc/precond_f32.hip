@@ -22,6 +22,12 @@
 
 namespace je {
 
+// The FP32 stage's rotations may fuse multiply-adds (the library is built without
+// contraction so that the FP64 pivot sequence is a function of the input bits alone; the
+// FP32 stage only has to reach FP32 working accuracy, and its result is re-orthogonalised
+// in FP64): one fused operation instead of a product and a sum in every rotated entry.
+#define FP32_CONTRACT _Pragma("clang fp contract(fast)")
+
 // Block geometry: PB rows per block, PM = 2 PB per subproblem, LDS rows padded by 4 floats
 // (16-byte aligned), NT threads per workgroup so that both phases of an inner round give
 // every thread four entries of S.
@@ -139,6 +145,7 @@ __device__ __forceinline__ bool f32_noise_pair(float app, float aqq, float apq) 
 // round issue-bound.
 __device__ __forceinline__ void rot_fast(float app, float aqq, float apq, float& t, float& c,
                                          float& s) {
+  FP32_CONTRACT
   float d = app - aqq, a = apq;
   const float m = fmaxf(fabsf(d), fabsf(a));
   if (m < 0x1p-50f || m > 0x1p50f) {
@@ -176,6 +183,7 @@ __device__ __forceinline__ void solve_body_rows(float (*S)[Blk<PB>::PL], float (
                                            float* Aout, int np, int2 pr, float* __restrict__ Uo,
                                            int inner_max, int full, float tol2, float rho2,
                                            bool preloaded) {
+  FP32_CONTRACT
   constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, LB = PM / 4;
   __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
@@ -271,6 +279,7 @@ struct RotF {
 
 template <int PL>
 __device__ __forceinline__ RotF pair_rot(const float (*S)[PL], int p, int q) {
+  FP32_CONTRACT
   const float app = S[p][p], aqq = S[q][q], apq = S[p][q];
   RotF r{1.0f, 0.0f, app, aqq, apq};
   if (!(apq == 0.0f || f32_noise_pair(app, aqq, apq))) {
@@ -288,6 +297,7 @@ __device__ __forceinline__ RotF pair_rot(const float (*S)[PL], int p, int q) {
 // pivot entries exactly.
 __device__ __forceinline__ void rot_block(const RotF& rb, const RotF& rc, bool diag, float& x,
                                           float& y, float& z, float& w) {
+  FP32_CONTRACT
   const float x1 = rb.c * x + rb.s * z, y1 = rb.c * y + rb.s * w;
   const float z1 = rb.c * z - rb.s * x, w1 = rb.c * w - rb.s * y;
   x = diag ? rb.napp : rc.c * x1 + rc.s * y1;
@@ -323,6 +333,7 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
                                            float* Aout, int np, int2 pr, float* __restrict__ Uo,
                                            int inner_max, int full, float tol2, float rho2,
                                            bool preloaded) {
+  FP32_CONTRACT
   constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, LB = PM / 4, PL = Blk<PB>::PL;
   __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
