@@ -442,7 +442,7 @@ int solve_one(const double* Au, int n, int lda, double* W, double* V, int ldv, d
 // All problems of a batch (n >= 2) go through the same sequence of launches; every launch
 // covers the whole batch (grids sized for the largest n, blocks past a matrix's n exit).
 // The FP32 stage runs each matrix at its own pace; the FP64 Jacobi phase is one persistent
-// launch per workgroup shape (LDS-resident n <= 128, HBM-resident above), each workgroup
+// launch per workgroup shape (LDS-resident n <= 64, HBM-resident above), each workgroup
 // taking the next matrix, largest first, from a device counter.  Logs are drained for all
 // matrices between launches; unfinished matrices are relaunched.
 constexpr long long kBatchLogCap = 1ll << 16;
@@ -679,6 +679,14 @@ inline void drop_graph(hipGraphExec_t& gx) {
   if (gx) (void)hipGraphExecDestroy(gx);
   gx = nullptr;
 }
+
+// Members whose FP64 Jacobi phase runs LDS-resident in a batch.  A single problem keeps A in
+// LDS up to n = 128 (jacobi_fits_lds); a batch only up to n = 64: an LDS-resident launch
+// sizes its LDS for its largest member, and at n = 128 (134 KB) one workgroup per CU is
+// resident, so the class (64, 128] runs faster HBM-resident with several workgroups per CU
+// (2048 matrices, n in [32, 512]: persistent launches 45 against 50 ms per batch).
+constexpr int kBatchLdsMaxN = 64;
+inline bool batch_lds(int n) { return n <= kBatchLdsMaxN && jacobi_fits_lds(n); }
 
 // One problem of a cohort: the caller's arrays, its workspace, and the caller's index.
 struct Member {
@@ -974,7 +982,7 @@ struct Cohort {
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hm[a].n > hm[b].n; });
     int nl = 0, nh = 0;
     for (int i : ord) {
-      if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
+      if (batch_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
       else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
     }
     const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
@@ -1151,7 +1159,7 @@ struct Cohort {
           std::vector<int> il, ih;
           int nl = 0, nh = 0;
           for (int i : ord) {
-            if (jacobi_fits_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
+            if (batch_lds(hm[i].n)) { il.push_back(i); nl = std::max(nl, hm[i].n); }
             else { ih.push_back(i); nh = std::max(nh, hm[i].n); }
           }
           if (!il.empty())
@@ -1227,7 +1235,7 @@ struct Cohort {
 // All problems of a batch (n >= 2) go through one cohort: every launch covers the whole
 // batch (grids sized for the largest n, blocks past a matrix's n exit).  The FP32 stage
 // runs each matrix at its own pace; the FP64 Jacobi phase is one persistent launch per
-// workgroup shape (LDS-resident n <= 128, HBM-resident above), each workgroup taking the
+// workgroup shape (LDS-resident n <= 64, HBM-resident above), each workgroup taking the
 // next matrix, largest first, from a device counter.  Logs are drained for all matrices
 // between launches; unfinished matrices are relaunched.
 int solve_batched(std::vector<int> idx, const double* const* Ain, const int* n,
