@@ -15,31 +15,38 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int GB = 64;   // tile of C
 constexpr int GK = 32;   // K step
+// Products up to n = kNarrowMaxN use 64 x 32 tiles: twice the workgroups of the 64 x 64
+// tiling (at n = 1024, 512 instead of 256: two per CU), so that the K-loop latency of one
+// workgroup is hidden by the other's matrix-core work.
+constexpr int kNarrowMaxN = 1024;
 
-// One 64 x 64 tile of C.  K advances in steps of GK; the operands of the next step are
-// loaded into registers while the matrix cores work on the current one (with a single
-// workgroup per CU at n = 1024 nothing else would hide the global-load latency).  SYM: the
-// product is symmetric (X^T X, or Q^T (A Q) for symmetric A); only tiles on or above the
-// diagonal are computed, and each entry C[i][j], i <= j, is also stored at C[j][i], so the
-// result is exactly symmetric (beta must be 0).
-template <int TRANSA, bool SYM = false>
+// One 64 x BN tile of C (BN = 64, or 32 for the narrow tiles of small products).  K
+// advances in steps of GK; the operands of the next step are loaded into registers while
+// the matrix cores work on the current one (with few workgroups per CU nothing else would
+// hide the global-load latency).  The four waves split the tile 2 x 2 (32 x BN/2 each).
+// SYM: the product is symmetric (X^T X, or Q^T (A Q) for symmetric A); only tiles on or
+// above the diagonal are computed, and each entry C[i][j], i <= j, is also stored at
+// C[j][i], so the result is exactly symmetric (beta must be 0).
+template <int TRANSA, bool SYM = false, int BN = GB>
 __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __restrict__ A,
                                            int lda, const double* __restrict__ B, int ldb,
                                            double beta, const double* Cin, int ldcin, double* C,
                                            int ldc, int tile_i, int tile_j) {
+  static_assert(BN == 64 || BN == 32, "64 x 64 or 64 x 32 tiles");
+  constexpr int NB = BN / 32;             // 16-column MFMA tiles per wave
   __shared__ double sA[GK][GB + 2];  // sA[k][i] = op(A)[i0 + i][k0 + k]
-  __shared__ double sB[GK][GB + 2];  // sB[k][j] = B[k0 + k][j0 + j]
-  constexpr int PER = GB * GK / 256;
+  __shared__ double sB[GK][BN + 2];  // sB[k][j] = B[k0 + k][j0 + j]
+  constexpr int PER = GB * GK / 256, PERB = BN * GK / 256;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int i0 = tile_i * GB, j0 = tile_j * GB;
-  const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
+  const int i0 = tile_i * GB, j0 = tile_j * BN;
+  const int wi = (w >> 1) * 32, wj = (w & 1) * (BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
-  d4 acc[2][2];
+  d4 acc[2][NB];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  double ra[PER], rb[PER];
+    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  double ra[PER], rb[PERB];
   // element e of a K step: A part (i, k) with the contiguous index fastest, B part (k, j)
   auto a_idx = [&](int e, int& i, int& k) {
     if (TRANSA) { i = e % GB; k = e / GB; }   // A[k][i]: contiguous in i
@@ -54,7 +61,11 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
       const int gi = i0 + i, gk = k0 + k;
       ra[t] = (gi < n && gk < n) ? (TRANSA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk])
                                  : 0.0;
-      const int j = e % GB, kb = e / GB;
+    }
+#pragma unroll
+    for (int t = 0; t < PERB; ++t) {
+      const int e = tid + t * 256;
+      const int j = e % BN, kb = e / BN;
       const int gkb = k0 + kb, gj = j0 + j;
       rb[t] = (gkb < n && gj < n) ? B[(size_t)gkb * ldb + gj] : 0.0;
     }
@@ -67,22 +78,25 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
       int i, k;
       a_idx(e, i, k);
       sA[k][i] = ra[t];
-      sB[e / GB][e % GB] = rb[t];
+    }
+#pragma unroll
+    for (int t = 0; t < PERB; ++t) {
+      const int e = tid + t * 256;
+      sB[e / BN][e % BN] = rb[t];
     }
     __syncthreads();
     if (k0 + GK < n) fetch(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
-      double av[2], bv[2];
+      double av[2], bv[NB];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = sA[kk + lk][wi + t * 16 + lr];
-        bv[t] = sB[kk + lk][wj + t * 16 + lr];
-      }
+      for (int t = 0; t < 2; ++t) av[t] = sA[kk + lk][wi + t * 16 + lr];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) bv[t] = sB[kk + lk][wj + t * 16 + lr];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < NB; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
@@ -92,7 +106,7 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int i = i0 + wi + a * 16 + 4 * r + lk;
@@ -111,29 +125,41 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
       }
 }
 
-template <int TRANSA>
+template <int TRANSA, int BN = GB>
 __global__ __launch_bounds__(256) void k_dgemm(int n, double alpha, const double* __restrict__ A,
                                                int lda, const double* __restrict__ B, int ldb,
                                                double beta, const double* Cin, int ldcin,
                                                double* C, int ldc) {
-  dgemm_tile<TRANSA>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc, blockIdx.y, blockIdx.x);
+  dgemm_tile<TRANSA, false, BN>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc,
+                                blockIdx.y, blockIdx.x);
 }
 
-// Tile t of the upper triangle of an nb x nb tile grid, row by row: (by, bx), by <= bx.
-__device__ __forceinline__ void upper_tile(int t, int nb, int& by, int& bx) {
+// Tile t of the tiles holding entries on or above the diagonal, row by row, for row tiles
+// of 64 and column tiles of 64 / r (r = 1 or 2): (by, bx) with bx >= r by, bx < nbc.
+__device__ __forceinline__ void upper_tile(int t, int nbc, int r, int& by, int& bx) {
   by = 0;
-  while (t >= nb - by) { t -= nb - by; ++by; }
-  bx = by + t;
+  while (t >= nbc - r * by) { t -= nbc - r * by; ++by; }
+  bx = r * by + t;
 }
 
-// C = alpha A^T B, symmetric: one workgroup per tile on or above the diagonal.
-__global__ __launch_bounds__(256) void k_dgemm_sym(int n, int nb, double alpha,
+// Tiles of upper_tile for n: row tiles of 64, column tiles of BN.
+static int upper_tiles(int n, int BN) {
+  const int nbr = (n + GB - 1) / GB, nbc = (n + BN - 1) / BN, r = GB / BN;
+  int t = 0;
+  for (int by = 0; by < nbr; ++by) t += nbc - r * by;
+  return t;
+}
+
+// C = alpha A^T B, symmetric: one workgroup per tile holding entries on or above the
+// diagonal.
+template <int BN>
+__global__ __launch_bounds__(256) void k_dgemm_sym(int n, int nbc, double alpha,
                                                    const double* __restrict__ A, int lda,
                                                    const double* __restrict__ B, int ldb,
                                                    double* C, int ldc) {
   int by, bx;
-  upper_tile(blockIdx.x, nb, by, bx);
-  dgemm_tile<1, true>(n, alpha, A, lda, B, ldb, 0.0, nullptr, 0, C, ldc, by, bx);
+  upper_tile(blockIdx.x, nbc, GB / BN, by, bx);
+  dgemm_tile<1, true, BN>(n, alpha, A, lda, B, ldb, 0.0, nullptr, 0, C, ldc, by, bx);
 }
 
 __device__ __forceinline__ double* bm_ptr(BMat& b, size_t off) {
@@ -159,7 +185,7 @@ __global__ __launch_bounds__(256) void k_dgemm_b(BMat* __restrict__ mats, int co
   BMat& b = mats[z];
   const int n = b.n;
   int by, bx;
-  if (SYM) upper_tile(t, nb, by, bx);
+  if (SYM) upper_tile(t, nb, 1, by, bx);
   else { by = t / nb; bx = t % nb; }
   if (by * GB >= n || bx * GB >= n) return;
   if (ns_mask && b.ns_done) {  // converged member: C = 0 (its update then leaves X as is)
@@ -244,16 +270,31 @@ hipError_t launch_ns_flag_b(BMat* m, int count, hipStream_t s) {
 
 hipError_t launch_dgemm_sym(int n, double alpha, const double* A, int lda, const double* B,
                             int ldb, double* C, int ldc, hipStream_t s) {
-  const int nb = (n + GB - 1) / GB;
-  hipLaunchKernelGGL(k_dgemm_sym, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, n, nb, alpha, A, lda,
-                     B, ldb, C, ldc);
+  if (n <= kNarrowMaxN) {
+    hipLaunchKernelGGL(k_dgemm_sym<32>, dim3(upper_tiles(n, 32)), dim3(256), 0, s, n,
+                       (n + 31) / 32, alpha, A, lda, B, ldb, C, ldc);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_dgemm_sym<GB>, dim3(upper_tiles(n, GB)), dim3(256), 0, s, n,
+                     (n + GB - 1) / GB, alpha, A, lda, B, ldb, C, ldc);
   return hipGetLastError();
 }
+
 
 hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int lda, const double* B,
                         int ldb, double beta, const double* Cin, int ldcin, double* C, int ldc,
                         hipStream_t s) {
-  int nb = (n + GB - 1) / GB;
+  const int nb = (n + GB - 1) / GB;
+  if (n <= kNarrowMaxN) {
+    const dim3 g((n + 31) / 32, nb), b(256);
+    if (transA)
+      hipLaunchKernelGGL((k_dgemm<1, 32>), g, b, 0, s, n, alpha, A, lda, B, ldb, beta, Cin, ldcin,
+                         C, ldc);
+    else
+      hipLaunchKernelGGL((k_dgemm<0, 32>), g, b, 0, s, n, alpha, A, lda, B, ldb, beta, Cin, ldcin,
+                         C, ldc);
+    return hipGetLastError();
+  }
   dim3 g(nb, nb), b(256);
   if (transA)
     hipLaunchKernelGGL(k_dgemm<1>, g, b, 0, s, n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc);
