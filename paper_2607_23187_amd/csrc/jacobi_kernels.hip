@@ -1035,31 +1035,163 @@ hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, bool
 // ------------------------------------------------------------------ J5: apply the log to V
 // Each block holds `R` rows of V in LDS, transposed (column index major) so that lane r
 // touches row r's entries p and q in consecutive banks.  The log is staged 64 entries at a
-// time, one per lane (a coalesced load), and each entry is broadcast to the wave with
-// readlane, so the rotations' LDS chain never waits on a memory load.
-__device__ __forceinline__ void apply_log_rows(double* __restrict__ tile, int R, int rows,
-                                               const RotEntry* __restrict__ log, long long m) {
+// time, one per lane (a coalesced load, the next 64 in flight while these are applied), and
+// each entry is broadcast to the wave with readlane, so the rotations' LDS chain never waits
+// on a memory load.  Rotations on pairwise disjoint column pairs commute, so up to four
+// consecutive ones issue their LDS loads together (consecutive pivots are disjoint in about
+// four groups of four out of five); a group with a shared column runs in log order.  Either
+// way every entry of V sees the same rotations in the same order with the same arithmetic.
+
+// Global-memory views: accesses through them are global instructions, which count on the
+// vector-memory counter only, so they never hold up a wait for LDS results.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+
+__device__ __forceinline__ void rot_col(double* __restrict__ t, int p, int q, int R, int off,
+                                        double c, double s) {
+  double* xp = t + p * R + off;
+  double* xq = t + q * R + off;
+  const double x = *xp, y = *xq;
+  *xp = c * x + s * y;
+  *xq = c * y - s * x;
+}
+
+template <int K>
+__device__ __forceinline__ void rot_cols_disjoint(double* __restrict__ t, const int* p,
+                                                  const int* q, int R, int off,
+                                                  const double* c, const double* s) {
+  double x[K], y[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    x[u] = t[p[u] * R + off];
+    y[u] = t[q[u] * R + off];
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    t[p[u] * R + off] = c[u] * x[u] + s[u] * y[u];
+    t[q[u] * R + off] = c[u] * y[u] - s[u] * x[u];
+  }
+}
+
+__device__ __forceinline__ bool pairs_disjoint(int p0, int q0, int p1, int q1) {
+  return p0 != p1 && p0 != q1 && q0 != p1 && q0 != q1;
+}
+
+// Log entries k .. k + 3 of the staged chunk (lane j holds entry j: columns p | q << 16,
+// cosine, sine) applied to the tile.
+__device__ __forceinline__ void rot_group4(double* __restrict__ tile, int R, int off, int cpq,
+                                           double cc, double cs, int k) {
+  int p[4], q[4];
+  double c[4], s[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int pq = __builtin_amdgcn_readlane(cpq, k + u);
+    p[u] = pq & 0xffff; q[u] = pq >> 16;
+    c[u] = readlane_d(cc, k + u); s[u] = readlane_d(cs, k + u);
+  }
+  const bool d01 = pairs_disjoint(p[0], q[0], p[1], q[1]);
+  const bool d23 = pairs_disjoint(p[2], q[2], p[3], q[3]);
+  const bool dx = pairs_disjoint(p[0], q[0], p[2], q[2]) &&
+                  pairs_disjoint(p[0], q[0], p[3], q[3]) &&
+                  pairs_disjoint(p[1], q[1], p[2], q[2]) &&
+                  pairs_disjoint(p[1], q[1], p[3], q[3]);
+  if (d01 && d23 && dx) {
+    rot_cols_disjoint<4>(tile, p, q, R, off, c, s);
+    return;
+  }
+  if (d01) {
+    rot_cols_disjoint<2>(tile, p, q, R, off, c, s);
+  } else {
+    rot_col(tile, p[0], q[0], R, off, c[0], s[0]);
+    rot_col(tile, p[1], q[1], R, off, c[1], s[1]);
+  }
+  if (d23) {
+    rot_cols_disjoint<2>(tile, p + 2, q + 2, R, off, c + 2, s + 2);
+  } else {
+    rot_col(tile, p[2], q[2], R, off, c[2], s[2]);
+    rot_col(tile, p[3], q[3], R, off, c[3], s[3]);
+  }
+}
+
+// Applies log entries [0, m) to the tile.  Lanes past the block's rows repeat the work of
+// lane (lane mod R): same addresses, same inputs, same results, so no lane diverges.  A full
+// chunk of 64 entries is unrolled, so the loads of the next chunk stay in flight until it
+// is done.
+__device__ __forceinline__ void apply_log_rows(double* __restrict__ tile, int R,
+                                               const RotEntry* log_, long long m) {
+  const gmem<RotEntry>* log = (const gmem<RotEntry>*)log_;
   const int lane = threadIdx.x;
+  const int off = lane % R;
+  // the chunk being loaded: entry e0 + lane (identity rotations past the end)
+  int np = 0, nq = 0;
+  double nc = 1.0, ns = 0.0;
+  if (lane < m) {
+    np = log[lane].p; nq = log[lane].q; nc = log[lane].c; ns = log[lane].s;
+  }
+  // the first chunk is complete before the loop, as every later one is at its top, so no
+  // wait inside the loop has to cover loads from before it
+  __builtin_amdgcn_s_waitcnt(0);
   for (long long e0 = 0; e0 < m; e0 += 64) {
-    const int cnt = (int)(m - e0 < 64 ? m - e0 : 64);
-    int lp = 0, lq = 0;
-    double lc = 1.0, ls = 0.0;
-    if (lane < cnt) {
-      const RotEntry g = log[e0 + lane];
-      lp = g.p; lq = g.q; lc = g.c; ls = g.s;
+    const int cnt = __builtin_amdgcn_readfirstlane((int)(m - e0 < 64 ? m - e0 : 64));
+    const int cpq = np | (nq << 16);  // n <= 8192
+    const double cc = nc, cs = ns;
+    np = 0; nq = 0; nc = 1.0; ns = 0.0;
+    if (e0 + 64 + lane < m) {
+      const gmem<RotEntry>* g = log + e0 + 64 + lane;
+      np = g->p; nq = g->q; nc = g->c; ns = g->s;
     }
-#pragma unroll 4
-    for (int k = 0; k < cnt; ++k) {
-      const int p = __builtin_amdgcn_readlane(lp, k), q = __builtin_amdgcn_readlane(lq, k);
-      const double c = readlane_d(lc, k), s = readlane_d(ls, k);
-      if (lane < rows) {
-        double* xp = tile + p * R + lane;
-        double* xq = tile + q * R + lane;
-        const double x = *xp, y = *xq;
-        *xp = c * x + s * y;
-        *xq = c * y - s * x;
+    if (cnt == 64) {
+#pragma unroll
+      for (int k = 0; k < 64; k += 4) rot_group4(tile, R, off, cpq, cc, cs, k);
+    } else {
+      int k = 0;
+      for (; k + 4 <= cnt; k += 4) rot_group4(tile, R, off, cpq, cc, cs, k);
+      for (; k < cnt; ++k) {
+        const int pq = __builtin_amdgcn_readlane(cpq, k);
+        rot_col(tile, pq & 0xffff, pq >> 16, R, off, readlane_d(cc, k), readlane_d(cs, k));
       }
     }
+  }
+}
+
+// Rows [r0, r0 + rows) of V (row stride ldv) into the transposed tile and back, eight
+// loads per lane in flight.  Indices past the end are clamped to the last element, whose
+// lane then repeats the same load or store.
+__device__ __forceinline__ void tile_in(double* __restrict__ tile, int R, int rows, int n,
+                                        const double* V_, int ldv, int r0) {
+  const gmem<double>* V = (const gmem<double>*)V_;
+  const int total = rows * n;
+  for (int base = threadIdx.x; base < total + 63; base += 512) {
+    double v[8];
+    int at[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = min(base + 64 * u, total - 1);
+      const int r = idx / n, j = idx - r * n;
+      v[u] = V[(size_t)(r0 + r) * ldv + j];
+      at[u] = j * R + r;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tile[at[u]] = v[u];
+  }
+}
+
+__device__ __forceinline__ void tile_out(const double* __restrict__ tile, int R, int rows, int n,
+                                         double* V_, int ldv, int r0) {
+  gmem<double>* V = (gmem<double>*)V_;
+  const int total = rows * n;
+  for (int base = threadIdx.x; base < total + 63; base += 512) {
+    double v[8];
+    size_t at[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = min(base + 64 * u, total - 1);
+      const int r = idx / n, j = idx - r * n;
+      v[u] = tile[j * R + r];
+      at[u] = (size_t)(r0 + r) * ldv + j;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) V[at[u]] = v[u];
   }
 }
 
@@ -1068,19 +1200,12 @@ __global__ __launch_bounds__(64) void k_apply_log(double* __restrict__ V, int n,
                                                   long long m, int R) {
   extern __shared__ double tile[];  // tile[j * R + r]
   const int r0 = blockIdx.x * R;
-  const int lane = threadIdx.x;
   const int rows = min(R, n - r0);
-  for (int idx = lane; idx < rows * n; idx += 64) {
-    int r = idx / n, j = idx - r * n;
-    tile[j * R + r] = V[(size_t)(r0 + r) * ldv + j];
-  }
+  tile_in(tile, R, rows, n, V, ldv, r0);
   __syncthreads();
-  apply_log_rows(tile, R, rows, log, m);
+  apply_log_rows(tile, R, log, m);
   __syncthreads();
-  for (int idx = lane; idx < rows * n; idx += 64) {
-    int r = idx / n, j = idx - r * n;
-    V[(size_t)(r0 + r) * ldv + j] = tile[j * R + r];
-  }
+  tile_out(tile, R, rows, n, V, ldv, r0);
 }
 
 // Rows of V per workgroup of the log drain: as many as fit 64 KB of LDS, at most 64.
@@ -1091,27 +1216,18 @@ __host__ __device__ __forceinline__ int apply_rows(int n) {
 
 __global__ __launch_bounds__(64) void k_apply_log_b(BMat* __restrict__ mats) {
   extern __shared__ double tile[];
-  BMat& b = mats[blockIdx.y];
+  const BMat& b = mats[blockIdx.y];
   const int n = b.n, R = apply_rows(n);
   const int r0 = blockIdx.x * R;
   if (r0 >= n) return;
   const long long m = b.jd.ctl->rotations - b.log_base;
   if (m <= 0) return;
-  double* V = b.Vw;
-  const int ldv = b.ld;
-  const int lane = threadIdx.x;
   const int rows = min(R, n - r0);
-  for (int idx = lane; idx < rows * n; idx += 64) {
-    int r = idx / n, j = idx - r * n;
-    tile[j * R + r] = V[(size_t)(r0 + r) * ldv + j];
-  }
+  tile_in(tile, R, rows, n, b.Vw, b.ld, r0);
   __syncthreads();
-  apply_log_rows(tile, R, rows, b.jd.log, m);
+  apply_log_rows(tile, R, b.jd.log, m);
   __syncthreads();
-  for (int idx = lane; idx < rows * n; idx += 64) {
-    int r = idx / n, j = idx - r * n;
-    V[(size_t)(r0 + r) * ldv + j] = tile[j * R + r];
-  }
+  tile_out(tile, R, rows, n, b.Vw, b.ld, r0);
 }
 
 // After the drain: the log of every matrix is empty again.
@@ -1131,10 +1247,8 @@ hipError_t launch_apply_log_b(BMat* m, int count, int nmax, hipStream_t s) {
 hipError_t launch_apply_log(double* V, int n, int ldv, const RotEntry* log, long long m,
                             hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  int R = (int)(65536 / ((size_t)n * 8));
-  if (R > 64) R = 64;
-  if (R < 1) R = 1;
-  size_t sh = (size_t)R * n * 8;
+  const int R = apply_rows(n);
+  const size_t sh = (size_t)R * n * 8;
   if (sh > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_apply_log,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
