@@ -1195,39 +1195,135 @@ __device__ __forceinline__ void tile_out(const double* __restrict__ tile, int R,
   }
 }
 
-__global__ __launch_bounds__(64) void k_apply_log(double* __restrict__ V, int n, int ldv,
-                                                  const RotEntry* __restrict__ log,
-                                                  long long m, int R) {
-  extern __shared__ double tile[];  // tile[j * R + r]
-  const int r0 = blockIdx.x * R;
-  const int rows = min(R, n - r0);
-  tile_in(tile, R, rows, n, V, ldv, r0);
-  __syncthreads();
-  apply_log_rows(tile, R, log, m);
-  __syncthreads();
-  tile_out(tile, R, rows, n, V, ldv, r0);
+// Geometry of a log-drain workgroup (one wave, 64 KB of LDS) for V with n columns: rows
+// R of V per workgroup, and lane groups G.  With R <= 32 the wave applies up to G = 64 / R
+// (at most 32) rotations at once (lane group u, lanes u R .. u R + R - 1, rotation k + u of the log on
+// the R rows) for the longest run of consecutive rotations on pairwise disjoint columns
+// (they commute); the log chunk and a small column-mark table then share the LDS with the
+// tile.  Larger R (small n) keeps one rotation per step over R lanes, and so does R = 1
+// (n > 7776), where the tile alone fills the LDS.
+constexpr int kApplyLds = 65536;
+constexpr int kMarkSlots = 512;  // column marks, indexed by column mod 512
+constexpr int kStageBytes = 64 * 16 + 64 * 4 + kMarkSlots * 4;
+
+struct ApplyGeom {
+  int R, G;
+};
+
+__host__ __device__ __forceinline__ ApplyGeom apply_geom(int n) {
+  const int r1 = (kApplyLds - kStageBytes) / (n * 8);
+  if (r1 >= 1 && r1 <= 32) return {r1, r1 == 1 ? 32 : 64 / r1};  // 2 G marking lanes <= 64
+  int r0 = kApplyLds / (n * 8);
+  r0 = r0 > 64 ? 64 : (r0 < 1 ? 1 : r0);
+  return {r0, 1};
 }
 
-// Rows of V per workgroup of the log drain: as many as fit 64 KB of LDS, at most 64.
-__host__ __device__ __forceinline__ int apply_rows(int n) {
-  int R = (int)(65536 / ((size_t)n * 8));
-  return R > 64 ? 64 : (R < 1 ? 1 : R);
+// Lane-group form of the drain (G >= 2; `stage` is the LDS after the tile, 16-byte
+// aligned).  Each step: (1) lane i < 2 Ge reads column i mod 2 of rotation k + i / 2 and
+// the lanes mark their columns with an LDS minimum of their lane index; a lane that finds
+// a smaller index on its column shares it with an earlier rotation of the window, so the
+// run of pairwise disjoint rotations ends before the rotation of the lowest such lane
+// (columns are marked modulo kMarkSlots: a false clash only shortens the run, which always
+// holds the first rotation); (2) lane group u < L applies rotation k + u.  Every entry of
+// V sees the rotations touching it in log order, with the same arithmetic as one at a time.
+__device__ __forceinline__ void apply_log_groups(double* __restrict__ tile, char* stage, int R,
+                                                 int G, const RotEntry* log_, long long m) {
+  const gmem<RotEntry>* log = (const gmem<RotEntry>*)log_;
+  double2* ecs = reinterpret_cast<double2*>(stage);             // 64 (c, s)
+  int* epq = reinterpret_cast<int*>(stage + 64 * 16);           // 64 (p | q << 16)
+  int* mark = reinterpret_cast<int*>(stage + 64 * 16 + 64 * 4);  // kMarkSlots
+  const int lane = threadIdx.x;
+  const int u = lane / R, rr = lane - u * R;
+  for (long long e0 = 0; e0 < m; e0 += 64) {
+    const int cnt = __builtin_amdgcn_readfirstlane((int)(m - e0 < 64 ? m - e0 : 64));
+    if (lane < cnt) {
+      const gmem<RotEntry>* g = log + e0 + lane;
+      epq[lane] = g->p | (g->q << 16);  // n <= 8192
+      ecs[lane] = make_double2(g->c, g->s);
+    }
+    __syncthreads();  // one wave: orders the staging before the reads below
+    int k = 0;
+    while (k < cnt) {
+      const int ge = min(G, cnt - k);
+      const bool marker = lane < 2 * ge;
+      int slot = 0;
+      if (marker) {
+        const int pq = epq[k + (lane >> 1)];
+        slot = ((lane & 1) ? (pq >> 16) : (pq & 0xffff)) & (kMarkSlots - 1);
+        mark[slot] = 0x7fffffff;
+      }
+      // the applying lanes read their rotation meanwhile (it does not depend on the run)
+      const bool applier = u < ge;
+      int apq = 0;
+      double2 acs = make_double2(1.0, 0.0);
+      if (applier) {
+        apq = epq[k + u];
+        acs = ecs[k + u];
+      }
+      if (marker) atomicMin(&mark[slot], lane);
+      const bool clash = marker && mark[slot] != lane;
+      const unsigned long long lost = __ballot(clash);
+      int L = lost ? (__ffsll((long long)lost) - 1) >> 1 : ge;
+      L = __builtin_amdgcn_readfirstlane(L < 1 ? 1 : L);
+      if (u < L) {
+        double* xp = tile + (apq & 0xffff) * R + rr;
+        double* xq = tile + (apq >> 16) * R + rr;
+        const double x = *xp, y = *xq;
+        *xp = acs.x * x + acs.y * y;
+        *xq = acs.x * y - acs.y * x;
+      }
+      k += L;
+    }
+    __syncthreads();  // the next chunk's staging overwrites this one
+  }
+}
+
+__device__ __forceinline__ void apply_log_block(double* __restrict__ tile, ApplyGeom g, int n,
+                                                const RotEntry* log, long long m) {
+  if (g.G >= 2) {
+    char* stage = reinterpret_cast<char*>(tile) + (((size_t)g.R * n * 8 + 15) & ~(size_t)15);
+    apply_log_groups(tile, stage, g.R, g.G, log, m);
+  } else {
+    apply_log_rows(tile, g.R, log, m);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_apply_log(double* __restrict__ V, int n, int ldv,
+                                                  const RotEntry* __restrict__ log,
+                                                  long long m) {
+  extern __shared__ double tile[];  // tile[j * R + r]
+  const ApplyGeom g = apply_geom(n);
+  const int r0 = blockIdx.x * g.R;
+  const int rows = min(g.R, n - r0);
+  tile_in(tile, g.R, rows, n, V, ldv, r0);
+  __syncthreads();
+  apply_log_block(tile, g, n, log, m);
+  __syncthreads();
+  tile_out(tile, g.R, rows, n, V, ldv, r0);
 }
 
 __global__ __launch_bounds__(64) void k_apply_log_b(BMat* __restrict__ mats) {
   extern __shared__ double tile[];
   const BMat& b = mats[blockIdx.y];
-  const int n = b.n, R = apply_rows(n);
-  const int r0 = blockIdx.x * R;
+  const int n = b.n;
+  const ApplyGeom g = apply_geom(n);
+  const int r0 = blockIdx.x * g.R;
   if (r0 >= n) return;
   const long long m = b.jd.ctl->rotations - b.log_base;
   if (m <= 0) return;
-  const int rows = min(R, n - r0);
-  tile_in(tile, R, rows, n, b.Vw, b.ld, r0);
+  const int rows = min(g.R, n - r0);
+  tile_in(tile, g.R, rows, n, b.Vw, b.ld, r0);
   __syncthreads();
-  apply_log_rows(tile, R, b.jd.log, m);
+  apply_log_block(tile, g, n, b.jd.log, m);
   __syncthreads();
-  tile_out(tile, R, rows, n, b.Vw, b.ld, r0);
+  tile_out(tile, g.R, rows, n, b.Vw, b.ld, r0);
+}
+
+// LDS bytes of a drain workgroup (at most kApplyLds for every n <= 8192).
+static size_t apply_lds_bytes(int n) {
+  const ApplyGeom g = apply_geom(n);
+  const size_t t = (size_t)g.R * n * 8;
+  return g.G >= 2 ? ((t + 15) & ~(size_t)15) + kStageBytes : t;
 }
 
 // After the drain: the log of every matrix is empty again.
@@ -1237,9 +1333,11 @@ __global__ void k_log_drained_b(BMat* __restrict__ mats, int count) {
 }
 
 hipError_t launch_apply_log_b(BMat* m, int count, int nmax, hipStream_t s) {
-  // blocks per matrix: ceil(n / R(n)) grows with n, so the largest matrix sets the grid
-  const int gx = (nmax + apply_rows(nmax) - 1) / apply_rows(nmax);
-  hipLaunchKernelGGL(k_apply_log_b, dim3(gx, count), dim3(64), 65536, s, m);
+  // blocks per matrix: ceil(n / R(n)) does not decrease with n (R(n) does not increase), so
+  // the largest matrix sets the grid
+  const int R = apply_geom(nmax).R;
+  const int gx = (nmax + R - 1) / R;
+  hipLaunchKernelGGL(k_apply_log_b, dim3(gx, count), dim3(64), kApplyLds, s, m);
   hipLaunchKernelGGL(k_log_drained_b, dim3((count + 255) / 256), dim3(256), 0, s, m, count);
   return hipGetLastError();
 }
@@ -1247,14 +1345,9 @@ hipError_t launch_apply_log_b(BMat* m, int count, int nmax, hipStream_t s) {
 hipError_t launch_apply_log(double* V, int n, int ldv, const RotEntry* log, long long m,
                             hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const int R = apply_rows(n);
-  const size_t sh = (size_t)R * n * 8;
-  if (sh > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_apply_log,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_apply_log, dim3((n + R - 1) / R), dim3(64), sh, s, V, n, ldv, log, m, R);
+  const int R = apply_geom(n).R;
+  hipLaunchKernelGGL(k_apply_log, dim3((n + R - 1) / R), dim3(64), apply_lds_bytes(n), s, V, n,
+                     ldv, log, m);
   return hipGetLastError();
 }
 
