@@ -321,34 +321,17 @@ def run_batch(args):
         worst = max(worst, err)
         worst_orth = max(worst_orth, orth)
         ok += int(r.status == J.OK and err <= 10 and orth <= 10)
+    s0 = res[0].stats
     rot = np.array([r.stats["rotations"] for r in res], dtype=np.float64)
-    # the library solves a batch as one cohort, or as two concurrent ones (the members above
-    # half the largest size, and the rest); the phase times are per cohort, shared by its
-    # members
-    keys = ("ms_precond", "ms_gemm", "ms_jacobi", "ms_finalize", "ms_jacobi_kernel",
-            "ms_apply_log")
-    groups = {}
-    for i, r in enumerate(res):
-        groups.setdefault(tuple(r.stats[k] for k in keys), []).append(i)
-    cohorts = []
-    for kt, members in sorted(groups.items(), key=lambda g: -max(sizes[g[1]])):
-        cohorts.append({"members": len(members), "n_min": int(min(sizes[members])),
-                        "n_max": int(max(sizes[members])),
-                        "rotations": int(rot[members].sum()),
-                        "algorithmic_bytes": float(np.sum(rot[members] * 64.0 * sizes[members])),
-                        "phase_ms": dict(zip(keys, kt))})
-    # the FP64 phase's kernels over all cohorts (their launch times added: a lower bound
-    # on the rate when the cohorts run concurrently)
-    tk = sum(c["phase_ms"]["ms_jacobi_kernel"] for c in cohorts)
-    ta = sum(c["phase_ms"]["ms_apply_log"] for c in cohorts)
+    tk, ta = s0["ms_jacobi_kernel"], s0["ms_apply_log"]
     algo = float(np.sum(rot * 64.0 * sizes))   # rows p, q of A and columns p, q of V
     med = float(np.median(lat))
     out = {"batch": len(probs), "seconds": med, "solves_per_s": len(probs) / med,
            "fp64_accurate_solves_per_s": len(probs) / med if ok == len(probs) else 0.0,
            "p50_ms": pct([x * 1e3 for x in lat], 50), "p99_ms": pct([x * 1e3 for x in lat], 99),
            "steps": args.batch_steps,
-           "phase_ms": cohorts[0]["phase_ms"],
-           "cohorts": cohorts,
+           "phase_ms": {k: s0[k] for k in ("ms_precond", "ms_gemm", "ms_jacobi", "ms_finalize",
+                                            "ms_jacobi_kernel", "ms_apply_log")},
            "rotations_total": int(rot.sum()), "fp64_accurate": f"{ok}/{len(probs)}",
            "worst_err_over_n_u_norm2": worst, "worst_orth_over_n_u": worst_orth,
            "roofline": {"bound": "hbm",
@@ -357,8 +340,7 @@ def run_batch(args):
                         "frac": (algo / ((tk + ta) * 1e-3) / 1e9) / HBM_PEAK_GBS
                         if tk + ta > 0 else 0.0,
                         "traffic": queue_traffic(len(probs)),
-                        "kernel": "k_jacobi_queue + k_apply_log_b (FP64 Jacobi phase of the "
-                                  "batch, launch times of all cohorts added)",
+                        "kernel": "k_jacobi_queue + k_apply_log_b (FP64 Jacobi phase of the batch)",
                         "algorithmic_bytes": algo, "kernel_ms": tk + ta,
                         "k_jacobi_queue": {"ms": tk, "achieved_GBs": algo / 2 / (tk * 1e-3) / 1e9
                                            if tk > 0 else 0.0},

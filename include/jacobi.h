@@ -202,10 +202,7 @@ int jacobi_eigh_noalloc(const double* A, int n, int lda, double* W, double* V, i
  * device int array receiving each problem's status; V[b] has leading dimension n[b].  The
  * whole batch shares tol, pivot, precond and opts (opts->pivot_log is ignored).  Returns
  * the worst status (errors before warnings) or a negative argument index
- * (A = 2 ... stream = 12).  Stream-ordered like the other calls, and blocking.  When at
- * least four problems are at most half the largest size, those run as a second group,
- * concurrently, on a stream and host thread of the library's own (forked from `stream`
- * and joined back into it before the call returns). */
+ * (A = 2 ... stream = 12).  Stream-ordered like the other calls, and blocking. */
 int jacobi_eigh_batched(int batch, const double* const* A, const int* n, const int* lda,
                         double* const* W, double* const* V, double tol, int pivot,
                         int precond, const je_opts* opts, int* info, je_stream stream);

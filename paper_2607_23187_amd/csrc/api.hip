@@ -1238,113 +1238,37 @@ struct Cohort {
 // workgroup shape (LDS-resident n <= 64, HBM-resident above), each workgroup taking the
 // next matrix, largest first, from a device counter.  Logs are drained for all matrices
 // between launches; unfinished matrices are relaunched.
-// Second stream of a device for the batched call's second cohort (created once, default
-// priority, kept until the process ends).
-std::mutex g_side_mu;
-std::map<int, hipStream_t> g_side;
-
-hipStream_t side_stream(int dev) {
-  std::lock_guard<std::mutex> lk(g_side_mu);
-  auto it = g_side.find(dev);
-  if (it != g_side.end()) return it->second;
-  hipStream_t st = nullptr;
-  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  g_side[dev] = st;
-  return st;
-}
-
-int run_cohort(Cohort& c, std::vector<Member> mem, char* meta, double tol, int pivot,
-               int precond, const je_opts& o, hipStream_t s) {
-  int r = c.begin(std::move(mem), meta, tol, pivot, precond, o, s, kBatchLogCap);
-  while (r == JE_OK && c.phase != Cohort::DONE) r = c.step();
-  return r;
-}
-
-// Members above half the largest size form a cohort of their own when the rest number at
-// least kSplitMin: the two cohorts run concurrently (the second on its own host thread and
-// stream, forked from and joined back into the caller's stream), so that the smaller
-// members' whole solve overlaps the larger members' longer FP32 stage and FP64 tail
-// instead of waiting for them at every phase boundary.  A member's result does not depend
-// on the cohort it is solved in.
-constexpr int kSplitMin = 4;
-
 int solve_batched(std::vector<int> idx, const double* const* Ain, const int* n,
                   const int* lda, double* const* W, double* const* V, const int* ldv, double tol,
                   int pivot, int precond, const je_opts& o, int* info, je_stats* stats,
                   hipStream_t s) {
   const int cnt = (int)idx.size();
   if (cnt == 0) return JE_OK;
-  int nmax = 0;
-  for (int b : idx) nmax = std::max(nmax, n[b]);
-  std::vector<int> part(cnt, 0);  // 1: the cohort of the larger members
-  int n_big = 0;
-  for (int i = 0; i < cnt; ++i)
-    if (2 * n[idx[i]] > nmax) { part[i] = 1; ++n_big; }
-  const bool split = cnt - n_big >= kSplitMin;
-  std::vector<Member> mem[2];
+  std::vector<Member> mem(cnt);
   size_t tot = 0;
   std::vector<size_t> woff(cnt);
   for (int i = 0; i < cnt; ++i) {
     woff[i] = tot;
     tot += bws_bytes(n[idx[i]], precond, kBatchLogCap);
   }
-  const size_t meta0 = tot;
-  size_t meta1 = tot;
-  if (split) meta1 += cohort_meta_bytes(n_big);
-  const size_t bytes = split ? meta1 + cohort_meta_bytes(cnt - n_big) : tot + cohort_meta_bytes(cnt);
   int err = JE_OK;
-  char* base = (char*)pool_get(bytes, &err);
+  char* base = (char*)pool_get(tot + cohort_meta_bytes(cnt), &err);
   if (!base) return err;
   for (int i = 0; i < cnt; ++i) {
     const int b = idx[i];
-    mem[split ? 1 - part[i] : 0].push_back(
-        Member{Ain[b], n[b], lda[b], W[b], V ? V[b] : nullptr, ldv ? ldv[b] : n[b],
-               base + woff[i], b});
+    mem[i] = Member{Ain[b], n[b], lda[b], W[b], V ? V[b] : nullptr, ldv ? ldv[b] : n[b],
+                    base + woff[i], b};
   }
-  Cohort c[2];
-  int r0 = JE_OK, r1 = JE_OK;
-  if (!split) {
-    r0 = run_cohort(c[0], std::move(mem[0]), base + meta0, tol, pivot, precond, o, s);
-  } else {
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    hipStream_t s2 = side_stream(dev);
-    if (!s2) return JE_ERR_DEVICE;
-    hipEvent_t fork = nullptr, join = nullptr;
-    HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipEventDestroy(fork);
-      return JE_ERR_DEVICE;
-    }
-    bool ok = hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(s2, fork, 0) == hipSuccess;
-    if (ok) {
-      // cohort 1 (the smaller members) on the second stream, cohort 0 here
-      std::thread t([&] {
-        if (hipSetDevice(dev) != hipSuccess) { r1 = JE_ERR_DEVICE; return; }
-        r1 = run_cohort(c[1], std::move(mem[1]), base + meta1, tol, pivot, precond, o, s2);
-      });
-      r0 = run_cohort(c[0], std::move(mem[0]), base + meta0, tol, pivot, precond, o, s);
-      t.join();
-      ok = hipEventRecord(join, s2) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
-    }
-    if (!ok) (void)hipGetLastError();
-    (void)hipEventDestroy(fork);
-    (void)hipEventDestroy(join);
-    if (!ok) return JE_ERR_DEVICE;
-  }
-  if (r0 != JE_OK) return r0;
-  if (r1 != JE_OK) return r1;
+  Cohort c;
+  int r = c.begin(mem, base + tot, tol, pivot, precond, o, s, kBatchLogCap);
+  while (r == JE_OK && c.phase != Cohort::DONE) r = c.step();
+  if (r != JE_OK) return r;
   int worst = JE_OK;
-  for (int k = 0; k < 2; ++k)
-    for (const Cohort::Left& l : c[k].left) {
-      info[l.idx] = l.status;
-      worst = std::max(worst, l.status);
-      if (stats) stats[l.idx] = l.st;
-    }
+  for (const Cohort::Left& l : c.left) {
+    info[l.idx] = l.status;
+    worst = std::max(worst, l.status);
+    if (stats) stats[l.idx] = l.st;
+  }
   return worst;
 }
 
