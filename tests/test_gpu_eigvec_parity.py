@@ -9,7 +9,8 @@ polish, both sides therefore perform the same IEEE operations in the same order:
   for every kernel variant (LDS-resident, HBM-resident with 1, 2, 4 and 8 rows per
   thread, 512 and 1024 threads), single and batched, across rotation-log drains;
 * at n = 1500 (512 threads x 4 rows), 4096 (512 x 8) and 6000 (1024 x 8) the pivot
-  sequence and the diagonal bytes after a common rotation cap equal the oracle's.
+  sequence and the diagonal bytes after a common rotation cap equal the oracle's, and at
+  n = 2048 to 7800 (every layout of the log drain) so does V.
 
 Large cases stop both sides at the same rotation cap (status MAXROT), which keeps the
 oracle's cost to seconds while every rotation is still compared.
@@ -152,6 +153,32 @@ def test_batched_large_members_match_oracle(sizes):
         assert r.status == J.WARN_MAXROT
         assert r.stats["rotations"] == ref.rotations == cap
         assert np.array_equal(r.w.cpu().numpy(), np.sort(np.diag(ref.a))), a.shape[0]
+
+
+@pytest.mark.parametrize("n,batched", [(2048, False), (4100, False), (7800, False),
+                                       (2100, True)])
+def test_large_n_eigenvectors_bitwise(n, batched):
+    """The log drain's layouts beyond n = 1024: 3 rows of V per wave in 21 lane groups
+    (n = 2048, 2100), one row in 32 lane groups (n = 4100), one row and one rotation per
+    step (n = 7800, where the row alone fills the LDS).  The first 5000 rotations of a
+    dense random symmetric matrix, single and batched: V equals the oracle's V_J bit for
+    bit (columns in the sorted order of the diagonal)."""
+    cap = 5000
+    a = I.random_symmetric(n, seed=6700 + n)
+    say("large-n V parity", n, "batched" if batched else "single")
+    if batched:
+        small = I.random_symmetric(300, seed=6701)
+        st, res = J.eigh_batched([gpu(a), gpu(small)], tol=1.0, pivot="gap", precond="none",
+                                 polish_v=False, abs_thr=1e-300, max_rotations=cap)
+        r = res[0]
+    else:
+        r = J.eigh(gpu(a), precond="none", pivot=J.GAP, stop="cert", abs_thr=1e-300,
+                   polish_v=False, max_rotations=cap)
+    ref, w, v = oracle_sorted(a, J.GAP, 1e-300, maxrot=cap)
+    assert r.status == J.WARN_MAXROT and ref.status == O.MAXROT
+    assert r.stats["rotations"] == ref.rotations == cap
+    assert np.array_equal(r.w.cpu().numpy(), w)
+    assert np.array_equal(r.v.cpu().numpy(), v)
 
 
 def test_device_array_batched_form_equals_host_form():
