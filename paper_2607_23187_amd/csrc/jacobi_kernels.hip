@@ -1033,14 +1033,17 @@ hipError_t launch_jacobi(const JDesc& d, long long log_base, bool lds_mode, bool
 }
 
 // ------------------------------------------------------------------ J5: apply the log to V
-// Each block holds `R` rows of V in LDS, transposed (column index major) so that lane r
-// touches row r's entries p and q in consecutive banks.  The log is staged 64 entries at a
-// time, one per lane (a coalesced load, the next 64 in flight while these are applied), and
-// each entry is broadcast to the wave with readlane, so the rotations' LDS chain never waits
-// on a memory load.  Rotations on pairwise disjoint column pairs commute, so up to four
-// consecutive ones issue their LDS loads together (consecutive pivots are disjoint in about
-// four groups of four out of five); a group with a shared column runs in log order.  Either
-// way every entry of V sees the same rotations in the same order with the same arithmetic.
+// Each block (one wave) holds `R` rows of V in LDS, transposed (column index major) so that
+// lane r touches row r's entries p and q in consecutive banks.  Rotations on pairwise
+// disjoint column pairs commute, which both forms below use; either way every entry of V
+// sees the rotations that touch it in log order, with the same arithmetic.
+//   R > 32 (n up to about 200; apply_log_rows): all lanes work on the same rotation.  The
+//     log is staged 64 entries at a time, one per lane (a coalesced load, the next 64 in
+//     flight while these are applied), each entry broadcast with readlane; up to four
+//     consecutive rotations issue their LDS loads together when their columns are
+//     disjoint (consecutive pivots are, in about four groups of four out of five).
+//   R <= 32 (apply_log_groups, further below): the lanes split into 64 / R groups, each
+//     applying one rotation of a run of consecutive disjoint ones.
 
 // Global-memory views: accesses through them are global instructions, which count on the
 // vector-memory counter only, so they never hold up a wait for LDS results.
