@@ -23,21 +23,26 @@ constexpr int kNarrowMaxN = 1024;
 // One 64 x BN tile of C (BN = 64, or 32 for the narrow tiles of small products).  K
 // advances in steps of GK; the operands of the next step are loaded into registers while
 // the matrix cores work on the current one (with few workgroups per CU nothing else would
-// hide the global-load latency).  The four waves split the tile 2 x 2 (32 x BN/2 each).
+// hide the global-load latency).  Four waves split the tile 2 x 2 (32 x BN/2 each).
+// KS = 2 (narrow tiles): eight waves, the second four taking the second half of every K
+// step into accumulators of their own, added to the first four's at the end (first half +
+// second half, a fixed order): twice the waves per CU to hide the matrix-core latency.
 // SYM: the product is symmetric (X^T X, or Q^T (A Q) for symmetric A); only tiles on or
 // above the diagonal are computed, and each entry C[i][j], i <= j, is also stored at
 // C[j][i], so the result is exactly symmetric (beta must be 0).
-template <int TRANSA, bool SYM = false, int BN = GB>
+template <int TRANSA, bool SYM = false, int BN = GB, int KS = 1>
 __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __restrict__ A,
                                            int lda, const double* __restrict__ B, int ldb,
                                            double beta, const double* Cin, int ldcin, double* C,
                                            int ldc, int tile_i, int tile_j) {
   static_assert(BN == 64 || BN == 32, "64 x 64 or 64 x 32 tiles");
+  static_assert(KS == 1 || (KS == 2 && BN == 32), "K split only for the narrow tiles");
   constexpr int NB = BN / 32;             // 16-column MFMA tiles per wave
+  constexpr int NT = 256 * KS;
   __shared__ double sA[GK][GB + 2];  // sA[k][i] = op(A)[i0 + i][k0 + k]
   __shared__ double sB[GK][BN + 2];  // sB[k][j] = B[k0 + k][j0 + j]
-  constexpr int PER = GB * GK / 256, PERB = BN * GK / 256;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int PER = GB * GK / NT, PERB = BN * GK / NT;
+  const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) & 3, kh = tid >> 8;
   const int i0 = tile_i * GB, j0 = tile_j * BN;
   const int wi = (w >> 1) * 32, wj = (w & 1) * (BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
@@ -55,7 +60,7 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const int e = tid + t * 256;
+      const int e = tid + t * NT;
       int i, k;
       a_idx(e, i, k);
       const int gi = i0 + i, gk = k0 + k;
@@ -64,7 +69,7 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
     }
 #pragma unroll
     for (int t = 0; t < PERB; ++t) {
-      const int e = tid + t * 256;
+      const int e = tid + t * NT;
       const int j = e % BN, kb = e / BN;
       const int gkb = k0 + kb, gj = j0 + j;
       rb[t] = (gkb < n && gj < n) ? B[(size_t)gkb * ldb + gj] : 0.0;
@@ -74,20 +79,20 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
   for (int k0 = 0; k0 < n; k0 += GK) {
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const int e = tid + t * 256;
+      const int e = tid + t * NT;
       int i, k;
       a_idx(e, i, k);
       sA[k][i] = ra[t];
     }
 #pragma unroll
     for (int t = 0; t < PERB; ++t) {
-      const int e = tid + t * 256;
+      const int e = tid + t * NT;
       sB[e / BN][e % BN] = rb[t];
     }
     __syncthreads();
     if (k0 + GK < n) fetch(k0 + GK);
 #pragma unroll
-    for (int kk = 0; kk < GK; kk += 4) {
+    for (int kk = kh * (GK / KS); kk < (kh + 1) * (GK / KS); kk += 4) {
       double av[2], bv[NB];
 #pragma unroll
       for (int t = 0; t < 2; ++t) av[t] = sA[kk + lk][wi + t * 16 + lr];
@@ -100,6 +105,22 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
+  }
+  if constexpr (KS == 2) {
+    // the second half's accumulators through LDS (sA is free after the last step)
+    double* part = &sA[0][0];
+    if (kh == 1) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[((w * 2 + a) * 4 + r) * 64 + lane] = acc[a][0][r];
+    }
+    __syncthreads();
+    if (kh == 1) return;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][0][r] += part[((w * 2 + a) * 4 + r) * 64 + lane];
   }
   // D[i][j] of a 16 x 16 tile sits in lane j + 16 * (i % 4), register i / 4
   // (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k).
@@ -125,13 +146,16 @@ __device__ __forceinline__ void dgemm_tile(int n, double alpha, const double* __
       }
 }
 
+// K split (eight waves) for the narrow tiles
+template <int BN>
+constexpr int ks_of() { return BN == 32 ? 2 : 1; }
+
 template <int TRANSA, int BN = GB>
-__global__ __launch_bounds__(256) void k_dgemm(int n, double alpha, const double* __restrict__ A,
-                                               int lda, const double* __restrict__ B, int ldb,
-                                               double beta, const double* Cin, int ldcin,
-                                               double* C, int ldc) {
-  dgemm_tile<TRANSA, false, BN>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc,
-                                blockIdx.y, blockIdx.x);
+__global__ __launch_bounds__(256 * ks_of<BN>()) void k_dgemm(
+    int n, double alpha, const double* __restrict__ A, int lda, const double* __restrict__ B,
+    int ldb, double beta, const double* Cin, int ldcin, double* C, int ldc) {
+  dgemm_tile<TRANSA, false, BN, ks_of<BN>()>(n, alpha, A, lda, B, ldb, beta, Cin, ldcin, C,
+                                             ldc, blockIdx.y, blockIdx.x);
 }
 
 // Tile t of the tiles holding entries on or above the diagonal, row by row, for row tiles
@@ -153,13 +177,13 @@ static int upper_tiles(int n, int BN) {
 // C = alpha A^T B, symmetric: one workgroup per tile holding entries on or above the
 // diagonal.
 template <int BN>
-__global__ __launch_bounds__(256) void k_dgemm_sym(int n, int nbc, double alpha,
-                                                   const double* __restrict__ A, int lda,
-                                                   const double* __restrict__ B, int ldb,
-                                                   double* C, int ldc) {
+__global__ __launch_bounds__(256 * ks_of<BN>()) void k_dgemm_sym(
+    int n, int nbc, double alpha, const double* __restrict__ A, int lda,
+    const double* __restrict__ B, int ldb, double* C, int ldc) {
   int by, bx;
   upper_tile(blockIdx.x, nbc, GB / BN, by, bx);
-  dgemm_tile<1, true, BN>(n, alpha, A, lda, B, ldb, 0.0, nullptr, 0, C, ldc, by, bx);
+  dgemm_tile<1, true, BN, ks_of<BN>()>(n, alpha, A, lda, B, ldb, 0.0, nullptr, 0, C, ldc, by,
+                                       bx);
 }
 
 __device__ __forceinline__ double* bm_ptr(BMat& b, size_t off) {
@@ -271,7 +295,7 @@ hipError_t launch_ns_flag_b(BMat* m, int count, hipStream_t s) {
 hipError_t launch_dgemm_sym(int n, double alpha, const double* A, int lda, const double* B,
                             int ldb, double* C, int ldc, hipStream_t s) {
   if (n <= kNarrowMaxN) {
-    hipLaunchKernelGGL(k_dgemm_sym<32>, dim3(upper_tiles(n, 32)), dim3(256), 0, s, n,
+    hipLaunchKernelGGL(k_dgemm_sym<32>, dim3(upper_tiles(n, 32)), dim3(256 * ks_of<32>()), 0, s, n,
                        (n + 31) / 32, alpha, A, lda, B, ldb, C, ldc);
     return hipGetLastError();
   }
@@ -286,7 +310,7 @@ hipError_t launch_dgemm(int n, int transA, double alpha, const double* A, int ld
                         hipStream_t s) {
   const int nb = (n + GB - 1) / GB;
   if (n <= kNarrowMaxN) {
-    const dim3 g((n + 31) / 32, nb), b(256);
+    const dim3 g((n + 31) / 32, nb), b(256 * ks_of<32>());
     if (transA)
       hipLaunchKernelGGL((k_dgemm<1, 32>), g, b, 0, s, n, alpha, A, lda, B, ldb, beta, Cin, ldcin,
                          C, ldc);
