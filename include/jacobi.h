@@ -134,6 +134,10 @@ typedef struct je_opts {
                              /* workgroups from n = 768), 1 one workgroup, 2 several */
                              /* workgroups when the matrix lives in HBM; same results */
                              /* (0); batches always use one workgroup per matrix      */
+  int batch_threads;         /* batches: threads per workgroup of the persistent FP64  */
+                             /* launch for the HBM-resident members: 0 tuned (tune=1) */
+                             /* or 512; 128 or 256 (members up to n = 512), or 512;   */
+                             /* same results                                     (0)  */
 } je_opts;
 
 /* Statistics of one solve (host struct, filled before return). */

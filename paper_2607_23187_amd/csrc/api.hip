@@ -688,6 +688,12 @@ inline void drop_graph(hipGraphExec_t& gx) {
 constexpr int kBatchLdsMaxN = 64;
 inline bool batch_lds(int n) { return n <= kBatchLdsMaxN && jacobi_fits_lds(n); }
 
+// Workgroups of a persistent batched launch: one per member up to 2048 one-wave (LDS) or
+// 128-thread workgroups, up to 1024 larger ones (four per CU).
+inline int queue_grid(bool lds, int threads, size_t members) {
+  return (int)std::min<size_t>(members, (lds || threads <= 128) ? 2048 : 1024);
+}
+
 // One problem of a cohort: the caller's arrays, its workspace, and the caller's index.
 struct Member {
   const double* A;
@@ -988,8 +994,11 @@ struct Cohort {
     const int use_cert = (pivot == 0 && o.stop == JE_STOP_CERT) ? 1 : 0;
     auto tuned = [&](bool lds, const std::vector<int>& lst, int nmx, int* shape) -> int {
       if (lst.empty()) return JE_OK;
-      // the default shape first; the other replaces it only if it is 5% faster
-      const int a = lds ? 64 : 512, b = lds ? 128 : 256;
+      // the default shape first; another replaces it only if it is 5% faster (the fastest
+      // such)
+      const int a = lds ? 64 : 512;
+      const std::vector<int> shapes = lds ? std::vector<int>{64, 128}
+                                          : std::vector<int>{512, 256, 128};
       if ((lds && nmx > 128) || (!lds && nmx > 512)) return JE_OK;  // one shape only
       const int key = (lds ? 1 : 2) * 1000 + pivot * 100 + (int)std::ceil(std::log2((double)nmx));
       {
@@ -1007,16 +1016,15 @@ struct Cohort {
       const size_t offJ = precond ? BF(A) : BF(Asym);
       // the FP64 matrices of the whole batch are saved in T and restored after each trial
       HIPCHK(launch_copy_mat_b(dm, cnt, nmax, BF(T), offJ, s));
-      float t_default = 0.f;
-      for (int shp : {a, b}) {
+      float t_default = 0.f, t_best = 0.f;
+      for (int shp : shapes) {
         HIPCHK(launch_zero_words(d_cnt, 2, s));
         Timer tt(s);
         HIPCHK(launch_jacobi_queue(dm, d_idx_lds, (int)smp.size(), nmx, pivot, lds, mirror,
-                                   shp, d_cnt,
-                                   (int)std::min<size_t>(smp.size(), lds ? 2048 : 1024), s));
+                                   shp, d_cnt, queue_grid(lds, shp, smp.size()), s));
         const float ms = tt.stop();
-        if (shp == a) { t_default = ms; *shape = a; }
-        else if (ms < 0.95f * t_default) { *shape = shp; }
+        if (shp == a) { t_default = ms; t_best = ms; *shape = a; }
+        else if (ms < 0.95f * t_default && ms < t_best) { t_best = ms; *shape = shp; }
         HIPCHK(launch_copy_mat_b(dm, cnt, nmax, offJ, BF(T), s));
         HIPCHK(launch_get_diag_b(dm, cnt, nmax, offJ, s));
         HIPCHK(launch_reset_b(dm, cnt, s));
@@ -1028,6 +1036,11 @@ struct Cohort {
       return JE_OK;
     };
     if (int r = tuned(true, il, nl, &shape_lds)) return r;
+    // a requested shape of the HBM-resident class (128 and 256 threads cover n <= 512)
+    if (o.batch_threads == 512 || (o.batch_threads > 0 && nh <= 512)) {
+      shape_hbm = o.batch_threads;
+      return JE_OK;
+    }
     if (int r = tuned(false, ih, nh, &shape_hbm)) return r;
     return JE_OK;
   }
@@ -1167,8 +1180,8 @@ struct Cohort {
           if (!ih.empty())
             HIPCHK(hipMemcpyAsync(d_idx_hbm, ih.data(), ih.size() * 4, hipMemcpyHostToDevice, s));
           HIPCHK(hipStreamSynchronize(s));  // the index vectors are host memory
-          const int gl = (int)std::min<size_t>(il.size(), 2048);
-          const int gh = (int)std::min<size_t>(ih.size(), 1024);
+          const int gl = queue_grid(true, shape_lds, il.size());
+          const int gh = queue_grid(false, shape_hbm, ih.size());
           auto queue = [&]() -> hipError_t {
             hipError_t e = launch_zero_words(d_cnt, 2, s);
             if (e == hipSuccess && !il.empty())
@@ -1554,6 +1567,9 @@ int check_args(const double* A, int n, int lda, const double* W, const double* V
   if (o.profile != 0 && o.profile != 1) return -10;
   if (o.fp32_block != 0 && o.fp32_block != 16 && o.fp32_block != 32) return -10;
   if (o.jacobi_wgs < 0 || o.jacobi_wgs > 2) return -10;
+  if (o.batch_threads != 0 && o.batch_threads != 128 && o.batch_threads != 256 &&
+      o.batch_threads != 512)
+    return -10;
   return 0;
 }
 
@@ -1609,6 +1625,7 @@ void je_opts_default(je_opts* o) {
   o->profile = 0;
   o->fp32_block = 0;
   o->jacobi_wgs = 0;
+  o->batch_threads = 0;
 }
 
 int jacobi_eigh_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,

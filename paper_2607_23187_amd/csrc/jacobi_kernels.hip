@@ -987,8 +987,8 @@ static hipError_t launch_queue_one(BMat* m, const int* idx, int count, int nmax,
 }
 
 // Workgroup shapes of the batched Jacobi: LDS-resident matrices (n <= 128) with one or two
-// waves, HBM-resident ones with 256 or 512 threads (1024 above n = 4096); rows per thread
-// = ceil(nmax / threads).
+// waves, HBM-resident ones with 128, 256 or 512 threads (128 and 256 up to n = 512; 1024
+// threads above n = 4096); rows per thread = ceil(nmax / threads).
 template <bool GAP>
 static hipError_t launch_queue_t(BMat* m, const int* idx, int count, int nmax, bool lds,
                                  bool mirror, int threads, int* counter, int grid,
@@ -1005,6 +1005,14 @@ static hipError_t launch_queue_t(BMat* m, const int* idx, int count, int nmax, b
       return launch_queue_one<256, 1, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
     if (nmax <= 512)
       return launch_queue_one<256, 2, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+  }
+  if (threads == 128) {
+    if (nmax <= 128)
+      return launch_queue_one<128, 1, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+    if (nmax <= 256)
+      return launch_queue_one<128, 2, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
+    if (nmax <= 512)
+      return launch_queue_one<128, 4, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);
   }
   if (nmax <= 512)
     return launch_queue_one<512, 1, GAP, false>(m, idx, count, nmax, mirror, counter, grid, s);

@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
                 ("pivot_log_cap", ctypes.c_longlong), ("split_gemm", ctypes.c_int),
                 ("sort", ctypes.c_int), ("update_mode", ctypes.c_int), ("tune", ctypes.c_int),
                 ("graph", ctypes.c_int), ("profile", ctypes.c_int),
-                ("fp32_block", ctypes.c_int), ("jacobi_wgs", ctypes.c_int)]
+                ("fp32_block", ctypes.c_int), ("jacobi_wgs", ctypes.c_int),
+                ("batch_threads", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -163,7 +164,7 @@ _WGS = {"auto": 0, "one": 1, "many": 2, 0: 0, 1: 1, 2: 2}
 
 def _opts(stop="cert", polish_v=True, fp32_max_sweeps=20, fp32_passes=2, split_gemm=False,
           max_rotations=0, abs_thr=0.0, sort=True, update_mode="auto", tune=True, graph=False,
-          profile=False, fp32_block=0, jacobi_wgs="auto") -> Opts:
+          profile=False, fp32_block=0, jacobi_wgs="auto", batch_threads=0) -> Opts:
     o = default_opts()
     o.stop = _STOPS[stop]
     o.polish_v = 1 if polish_v else 0
@@ -179,6 +180,7 @@ def _opts(stop="cert", polish_v=True, fp32_max_sweeps=20, fp32_passes=2, split_g
     o.profile = 1 if profile else 0
     o.fp32_block = int(fp32_block)
     o.jacobi_wgs = _WGS[jacobi_wgs]
+    o.batch_threads = int(batch_threads)
     return o
 
 
@@ -279,7 +281,7 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
                  stop="cert", want_v: bool = True, max_rotations: int = 0,
                  polish_v: bool = True, abs_thr: float = 0.0, sort: bool = True,
                  update_mode="auto", tune: bool = True, fp32_passes: int = 2,
-                 graph: bool = False, fp32_block: int = 0,
+                 graph: bool = False, fp32_block: int = 0, batch_threads: int = 0,
                  stream: torch.cuda.Stream | None = None):
     """Batch of independent problems of possibly different sizes (host-array form, with
     per-problem statistics).  ``graph`` replays the repeated step sequences from captured
@@ -300,7 +302,7 @@ def eigh_batched(mats: list[torch.Tensor], tol: float = 1e-14, pivot="gap", prec
     info = IA()
     stats = (Stats * b)()
     o = _opts(stop, polish_v, 20, fp32_passes, False, max_rotations, abs_thr, sort,
-              update_mode, tune, graph, fp32_block=fp32_block)
+              update_mode, tune, graph, fp32_block=fp32_block, batch_threads=batch_threads)
     s = stream if stream is not None else torch.cuda.current_stream()
     status = L.jacobi_eigh_batched_host(b, a_p, ns, ns, w_p, v_p, ns, float(tol),
                                         _PIVOTS[pivot], _PRECONDS[precond], ctypes.byref(o),

@@ -35,7 +35,7 @@ def test_defaults_and_strings():
     assert (o.stop, o.polish_v, o.fp32_max_sweeps, o.fp32_passes, o.max_rotations, o.abs_thr,
             o.split_gemm) == (0, 1, 20, 2, 0, 0.0, 0)
     assert (o.sort, o.update_mode, o.tune, o.graph, o.profile, o.fp32_block,
-            o.jacobi_wgs) == (1, 0, 1, 0, 0, 0, 0)
+            o.jacobi_wgs, o.batch_threads) == (1, 0, 1, 0, 0, 0, 0, 0)
     assert J.strerror(0) == "ok"
     assert "NaN" in J.strerror(J.ERR_NONFINITE)
     assert J.strerror(-3) == "invalid argument"
@@ -62,7 +62,7 @@ def test_argument_errors_follow_lapack_info_convention():
     assert _ex(fake, 4, 4, fake, None, 4, 1e-12, precond=5) == -9
     for field, bad in (("stop", 9), ("sort", 2), ("update_mode", 3), ("tune", -1),
                        ("graph", 2), ("profile", 5), ("fp32_block", 24), ("fp32_passes", 3),
-                       ("jacobi_wgs", 3)):
+                       ("jacobi_wgs", 3), ("batch_threads", 64)):
         o = J.default_opts()
         setattr(o, field, bad)
         assert _ex(fake, 4, 4, fake, None, 4, 1e-12, opts=o) == -10, field

@@ -138,6 +138,26 @@ def test_tuned_shapes_do_not_change_results():
         assert torch.equal(x.v, y.v)
 
 
+@pytest.mark.parametrize("threads", [128, 256])
+@pytest.mark.parametrize("pivot", ["greedy", "gap"])
+def test_forced_shapes_give_the_same_bits(pivot, threads):
+    """The other workgroup shapes the tuner may pick for the HBM-resident members
+    (opts.batch_threads: 128 threads x up to 4 rows, 256 x up to 2) give the bits of the
+    default 512 x 1."""
+    probs = problems([70, 100, 129, 200, 300, 500], 8300)
+    tol = min(tol_for(a, lam) for a, lam in probs)
+    mats = [torch.from_numpy(a).cuda() for a, _ in probs]
+    say("forced shape", pivot, threads)
+    s0, r0 = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="fp32", tune=False)
+    s1, r1 = J.eigh_batched(mats, tol=tol, pivot=pivot, precond="fp32", tune=False,
+                            batch_threads=threads)
+    assert s0 == s1 == J.OK
+    for x, y in zip(r0, r1):
+        assert x.stats["rotations"] == y.stats["rotations"]
+        assert torch.equal(x.w, y.w)
+        assert torch.equal(x.v, y.v)
+
+
 @pytest.mark.parametrize("pivot", ["greedy", "gap"])
 def test_batched_timestamp_and_mirror_modes_agree(pivot):
     """The persistent batched launch keeps A current either by mirrored column stores
