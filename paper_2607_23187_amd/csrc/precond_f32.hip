@@ -319,14 +319,18 @@ __device__ __forceinline__ RotF fetch_rot(const RotF& x, int src) {
 
 // An inner round is one phase: the pairs of the round are disjoint, so J^T S J is, block by
 // block, X_bc -> J_b^T X_bc J_c over the 2 x 2 blocks of pair b's rows and pair c's columns.
-// Lane (kb, i) owns the blocks (kb, 2i) and (kb, 2i + 1) and columns 4i .. 4i + 3 of rows
-// p, q of U^T; it evaluates the three rotations it needs itself (the same instructions on
-// the same values in every lane, so all lanes agree).  S is double-buffered: a round reads
-// one buffer and writes the other, and a single barrier separates rounds.  S stays
-// symmetric up to rounding; its upper triangle is the one used.  (Used for 32-row blocks:
-// measured against the two-phase form, n = 4096 FP32 stage 243 -> 236 ms, batches
-// 272 -> 261 ms; for 16-row blocks, two waves per subproblem, the two-phase form is faster,
-// n = 1024 27.8 vs 34.7 ms.)
+// Lane l of wave w owns column pair c = l mod 32 and row pairs kb = 2 w + l / 32 and
+// kb + PM / 4: the blocks (kb, c), (kb + PM / 4, c), and columns 4 (c mod 16) .. + 3 of rows
+// p, q of U^T for one of the two row pairs.  The 32 lanes of a half wave share a row pair,
+// so their reads and writes of S fall on 32 consecutive columns (32 banks) in the rounds
+// that pair the two blocks (with the former layout, two column pairs per lane, they met
+// two-way bank conflicts: batched solve 66 -> 62 ms).  A lane evaluates its column pair's rotation itself and reads the row pairs'
+// from the lanes that evaluated them (the same instructions on the same values in every
+// lane, so all lanes agree).  S is double-buffered: a round reads one buffer and writes the
+// other, and a single barrier separates rounds.  S stays symmetric up to rounding; its upper
+// triangle is the one used.  (Used for 32-row blocks: measured against the two-phase form,
+// n = 4096 FP32 stage 243 -> 236 ms, batches 272 -> 261 ms; for 16-row blocks, two waves per
+// subproblem, the two-phase form is faster, n = 1024 27.8 vs 34.7 ms.)
 template <int PB>
 __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float (*W)[Blk<PB>::PL],
                                            float (*Ut)[Blk<PB>::PL], const float* Ain,
@@ -334,7 +338,8 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
                                            int inner_max, int full, float tol2, float rho2,
                                            bool preloaded) {
   FP32_CONTRACT
-  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, LB = PM / 4, PL = Blk<PB>::PL;
+  constexpr int PM = Blk<PB>::PM, NT = Blk<PB>::NT, PL = Blk<PB>::PL;
+  static_assert(PM == 64 && NT == 512, "32-row blocks: 8 waves, 32 column pairs");
   __shared__ float red[2][NT / 64];
   const int tid = threadIdx.x;
   if (!preloaded) {
@@ -342,39 +347,44 @@ __device__ __forceinline__ void solve_body_blocks(float (*S)[Blk<PB>::PL], float
     set_identity<PB>(Ut);
     __syncthreads();
   }
-  const int lane = tid & 63;
-  const int kb = tid / LB, li = tid % LB, jb = li * 4, kc = 2 * li;
+  const int lane = tid & 63, c = lane & 31;
+  const int kb0 = 2 * (tid >> 6) + (lane >> 5);
   const int nr = full ? PM - 1 : PB;
   float(*Sc)[PL] = S;
   float(*Sn)[PL] = W;
   float prev_off = 3.4e38f;
   for (int sw = 0; sw < inner_max; ++sw) {
     for (int r = 0; r < nr; ++r) {
-      int pb, qb, p0, q0, p1, q1;
-      inner_pair<PB>(full, r, kb, pb, qb);
-      inner_pair<PB>(full, r, kc, p0, q0);
-      inner_pair<PB>(full, r, kc + 1, p1, q1);
-      float x0 = Sc[pb][p0], y0 = Sc[pb][q0], z0 = Sc[qb][p0], w0 = Sc[qb][q0];
-      float x1 = Sc[pb][p1], y1 = Sc[pb][q1], z1 = Sc[qb][p1], w1 = Sc[qb][q1];
-      const float4 up = *reinterpret_cast<const float4*>(&Ut[pb][jb]);
-      const float4 uq = *reinterpret_cast<const float4*>(&Ut[qb][jb]);
-      // lane l evaluates the rotation of pair l mod (PM/2) (each pair twice per wave) and
-      // every lane fetches the three it needs from those lanes (no barrier: same wave)
-      int pm, qm;
-      inner_pair<PB>(full, r, lane % (PM / 2), pm, qm);
-      const RotF mine = pair_rot<PL>(Sc, pm, qm);
-      const RotF rb = fetch_rot(mine, kb), r0 = fetch_rot(mine, kc), r1 = fetch_rot(mine, kc + 1);
-      rot_block(rb, r0, kb == kc, x0, y0, z0, w0);
-      rot_block(rb, r1, kb == kc + 1, x1, y1, z1, w1);
-      Sn[pb][p0] = x0; Sn[pb][q0] = y0; Sn[qb][p0] = z0; Sn[qb][q0] = w0;
-      Sn[pb][p1] = x1; Sn[pb][q1] = y1; Sn[qb][p1] = z1; Sn[qb][q1] = w1;
-      float4 po, qo;
-      po.x = rb.c * up.x + rb.s * uq.x; qo.x = rb.c * uq.x - rb.s * up.x;
-      po.y = rb.c * up.y + rb.s * uq.y; qo.y = rb.c * uq.y - rb.s * up.y;
-      po.z = rb.c * up.z + rb.s * uq.z; qo.z = rb.c * uq.z - rb.s * up.z;
-      po.w = rb.c * up.w + rb.s * uq.w; qo.w = rb.c * uq.w - rb.s * up.w;
-      *reinterpret_cast<float4*>(&Ut[pb][jb]) = po;
-      *reinterpret_cast<float4*>(&Ut[qb][jb]) = qo;
+      int pc, qc;
+      inner_pair<PB>(full, r, c, pc, qc);
+      const RotF rc = pair_rot<PL>(Sc, pc, qc);
+      int pb[2], qb[2];
+      RotF rb[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int kb = kb0 + h * (PM / 4);
+        inner_pair<PB>(full, r, kb, pb[h], qb[h]);
+        float x = Sc[pb[h]][pc], y = Sc[pb[h]][qc], z = Sc[qb[h]][pc], w = Sc[qb[h]][qc];
+        rb[h] = fetch_rot(rc, kb);
+        rot_block(rb[h], rc, kb == c, x, y, z, w);
+        Sn[pb[h]][pc] = x; Sn[pb[h]][qc] = y; Sn[qb[h]][pc] = z; Sn[qb[h]][qc] = w;
+      }
+      {
+        // rows p, q of U^T: lane c < 16 takes columns 4c .. 4c + 3 of the first row pair,
+        // lane c >= 16 those of the second
+        const int h = c >> 4, jb = 4 * (c & 15);
+        const RotF& ru = h ? rb[1] : rb[0];
+        const int pu = h ? pb[1] : pb[0], qu = h ? qb[1] : qb[0];
+        const float4 up = *reinterpret_cast<const float4*>(&Ut[pu][jb]);
+        const float4 uq = *reinterpret_cast<const float4*>(&Ut[qu][jb]);
+        float4 po, qo;
+        po.x = ru.c * up.x + ru.s * uq.x; qo.x = ru.c * uq.x - ru.s * up.x;
+        po.y = ru.c * up.y + ru.s * uq.y; qo.y = ru.c * uq.y - ru.s * up.y;
+        po.z = ru.c * up.z + ru.s * uq.z; qo.z = ru.c * uq.z - ru.s * up.z;
+        po.w = ru.c * up.w + ru.s * uq.w; qo.w = ru.c * uq.w - ru.s * up.w;
+        *reinterpret_cast<float4*>(&Ut[pu][jb]) = po;
+        *reinterpret_cast<float4*>(&Ut[qu][jb]) = qo;
+      }
       __syncthreads();
       float(*t)[PL] = Sc;
       Sc = Sn;
