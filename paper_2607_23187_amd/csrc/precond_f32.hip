@@ -1024,6 +1024,18 @@ int precond_f32_block_b(int nmax, int request) {
   return 32;
 }
 
+// Workgroup index in the order that keeps consecutive indices on one XCD: the hardware
+// hands workgroups to the 8 XCDs round-robin (id mod 8), so XCD x gets the contiguous range
+// of indices [x q + min(x, r), + q + (x < r)) of the G = 8 q + r workgroups.  The block
+// updates of a step read each subproblem factor from several consecutive workgroups; on one
+// XCD they share its L2 instead of fetching the factor once per XCD.
+constexpr int kF32Xcds = 8;
+
+__device__ __forceinline__ int xcd_order(int bid, int G) {
+  const int x = bid % kF32Xcds, i = bid / kF32Xcds, q = G / kF32Xcds, r = G % kF32Xcds;
+  return x * q + min(x, r) + i;
+}
+
 __device__ __forceinline__ int find_mat(const int* __restrict__ prefix, int count, int blk) {
   int lo = 0, hi = count - 1;  // largest m with prefix[m] <= blk
   while (lo < hi) {
@@ -1104,10 +1116,11 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_round_apply_a_b(
   static_assert(2 * NT * 4 == PM * PM, "two four-float groups of a tile per thread");
   // two LDS tiles (four workgroups per CU): U_R waits in registers until U_P is consumed
   __shared__ __align__(16) float X[PM][PL], Y[PM][PL];
-  const int j = find_mat(prefix, count, blockIdx.x);
+  const int L = xcd_order(blockIdx.x, gridDim.x);
+  const int j = find_mat(prefix, count, L);
   BMat& bm = mats[act[j]];
   const int nb2 = bm.nb / 2;
-  int bl = blockIdx.x - prefix[j];
+  int bl = L - prefix[j];
   if (bm.f_done || bl >= nb2 * (nb2 - 1) / 2) return;
   int P = 0;
   while (bl >= nb2 - 1 - P) { bl -= nb2 - 1 - P; ++P; }
@@ -1161,7 +1174,7 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_round_apply_a_b(
                                blk_row<PB>(pp.x, pp.y, j)) =
         *reinterpret_cast<const float4*>(&Y[i][j]);
   }
-  tile_sq<PB>(X, false, 2.0, bm.part + 2 * (nb2 + blockIdx.x - prefix[j]));
+  tile_sq<PB>(X, false, 2.0, bm.part + 2 * (nb2 + L - prefix[j]));
 }
 
 template <int PB>
@@ -1170,10 +1183,11 @@ __global__ __launch_bounds__(Blk<PB>::NT) void k_round_apply_v_b(
     int count) {
   constexpr int PM = Blk<PB>::PM, PL = Blk<PB>::PL;
   __shared__ __align__(16) float lds[2][PM][PL];
-  const int j = find_mat(prefix, count, blockIdx.x);
+  const int L = xcd_order(blockIdx.x, gridDim.x);
+  const int j = find_mat(prefix, count, L);
   BMat& b = mats[act[j]];
   const int nvt = (b.n + PM - 1) / PM, nb2 = b.nb / 2;
-  const int bl = blockIdx.x - prefix[j];
+  const int bl = L - prefix[j];
   if (b.f_done || bl >= nvt * nb2) return;
   const int R = bl / nvt, rt = bl - R * nvt;
   const int r = b.f_round;
